@@ -1,0 +1,182 @@
+"""ctypes front end of the FP64 CPU oracle (oracle/tc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
+CPU-baseline leg import this module.  The product library never does, and
+this module imports nothing from the product package.
+
+Arrays are numpy float64, C-contiguous, in the layouts of tc_oracle.h:
+U [R_f][n], p [R_N][2n-1], W [R_N][R_f][n], G [R_N][R_f][R_f], J [R_f][R_f].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# IEEE semantics are required by the error-free transformations in the
+# compensated sums: no contraction into FMAs, no fast-math.  x86-64-v3 gives a
+# hardware FMA for the TwoProduct step on any AVX2 host.
+CFLAGS = ["-O2", "-std=c11", "-march=x86-64-v3", "-ffp-contract=off",
+          "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (every call recompiles when force)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        d = ctypes.c_double
+        pd = ctypes.POINTER(ctypes.c_double)
+        ppd = ctypes.POINTER(pd)
+        pi = ctypes.POINTER(ctypes.c_int)
+        L.oracle_sinc_rule.argtypes = [ctypes.c_int, d, d, pd, pd]
+        L.oracle_cell_integral.argtypes = [d, d, ctypes.c_long]
+        L.oracle_cell_integral.restype = d
+        L.oracle_newton_kernel.argtypes = [ctypes.c_int, d, ctypes.c_int, d, d, pd, pd, pd, pd]
+        L.oracle_convolve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, pd, pd, pd,
+                                      ctypes.c_int]
+        L.oracle_gram.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, pd, pd, pd,
+                                  ctypes.c_int]
+        L.oracle_tei_gram.argtypes = [pi, ctypes.c_int, ctypes.c_int, pd, ppd, ppd, pd, pd,
+                                      ctypes.c_int]
+        L.oracle_tei_gram_columns.argtypes = [pi, ctypes.c_int, ctypes.c_int, pd, ppd, ppd,
+                                              ctypes.c_int, pi, pd, ctypes.c_int]
+        L.oracle_tei_gram_backward.argtypes = [pi, ctypes.c_int, ctypes.c_int, pd, ppd, ppd,
+                                               pd, ppd]
+        L.oracle_bruteforce_J.argtypes = [ctypes.c_int, d, ctypes.c_int, ctypes.c_int, pd, pd,
+                                          ppd, pd]
+        L.oracle_gauss_legendre.argtypes = [ctypes.c_int, pd, pd]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pp(arrs):
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(arrs))(*[_p(a) for a in arrs])
+    return ptrs
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sinc_rule(R_N: int, u0: float, hu: float):
+    t = np.empty(R_N)
+    a = np.empty(R_N)
+    lib().oracle_sinc_rule(R_N, u0, hu, _p(t), _p(a))
+    return t, a
+
+
+def cell_integral(t: float, h: float, m: int) -> float:
+    return lib().oracle_cell_integral(t, h, m)
+
+
+def newton_kernel(n: int, h: float, R_N: int, u0: float, hu: float):
+    """Returns (t, a, c, p) with c_k = a_k h^3 and p [R_N][2n-1]."""
+    t, a, c = np.empty(R_N), np.empty(R_N), np.empty(R_N)
+    p = np.empty((R_N, 2 * n - 1))
+    lib().oracle_newton_kernel(n, h, R_N, u0, hu, _p(t), _p(a), _p(c), _p(p))
+    return t, a, c, p
+
+
+def convolve(p: np.ndarray, U: np.ndarray, compensated: bool = True) -> np.ndarray:
+    p, U = _f64(p), _f64(U)
+    R_N, L = p.shape
+    R_f, n = U.shape
+    assert L == 2 * n - 1
+    W = np.empty((R_N, R_f, n))
+    lib().oracle_convolve(n, R_f, R_N, _p(p), _p(U), _p(W), int(compensated))
+    return W
+
+
+def gram(U: np.ndarray, W: np.ndarray, compensated: bool = True) -> np.ndarray:
+    U, W = _f64(U), _f64(W)
+    R_f, n = U.shape
+    R_N = W.shape[0]
+    G = np.empty((R_N, R_f, R_f))
+    lib().oracle_gram(n, R_f, R_N, _p(U), _p(W), _p(G), int(compensated))
+    return G
+
+
+def tei_gram(c, p3, U3, return_G: bool = False, compensated: bool = True):
+    """J = sum_k c_k G1_k o G2_k o G3_k.  p3, U3: sequences of 3 arrays."""
+    c = _f64(c)
+    p3 = [_f64(x) for x in p3]
+    U3 = [_f64(x) for x in U3]
+    R_f = U3[0].shape[0]
+    R_N = c.shape[0]
+    n = (ctypes.c_int * 3)(*[u.shape[1] for u in U3])
+    J = np.empty((R_f, R_f))
+    G = np.empty((3, R_N, R_f, R_f)) if return_G else None
+    lib().oracle_tei_gram(n, R_f, R_N, _p(c), _pp(p3), _pp(U3), _p(J),
+                          _p(G) if G is not None else None, int(compensated))
+    return (J, G) if return_G else J
+
+
+def tei_gram_columns(c, p3, U3, cols, compensated: bool = True) -> np.ndarray:
+    """Returns J[:, cols] as an array of shape [len(cols)][R_f] (row q = column cols[q])."""
+    c = _f64(c)
+    p3 = [_f64(x) for x in p3]
+    U3 = [_f64(x) for x in U3]
+    R_f = U3[0].shape[0]
+    R_N = c.shape[0]
+    n = (ctypes.c_int * 3)(*[u.shape[1] for u in U3])
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    out = np.empty((len(cols), R_f))
+    lib().oracle_tei_gram_columns(n, R_f, R_N, _p(c), _pp(p3), _pp(U3), len(cols),
+                                  cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  _p(out), int(compensated))
+    return out
+
+
+def tei_gram_backward(c, p3, U3, Jbar):
+    c = _f64(c)
+    p3 = [_f64(x) for x in p3]
+    U3 = [_f64(x) for x in U3]
+    Jbar = _f64(Jbar)
+    R_f = U3[0].shape[0]
+    R_N = c.shape[0]
+    n = (ctypes.c_int * 3)(*[u.shape[1] for u in U3])
+    dU = [np.empty_like(u) for u in U3]
+    lib().oracle_tei_gram_backward(n, R_f, R_N, _p(c), _pp(p3), _pp(U3), _p(Jbar), _pp(dU))
+    return dU
+
+
+def bruteforce_J(h: float, a, p, U3) -> np.ndarray:
+    a, p = _f64(a), _f64(p)
+    U3 = [_f64(x) for x in U3]
+    R_f, n = U3[0].shape
+    R_N = a.shape[0]
+    J = np.empty((R_f, R_f))
+    lib().oracle_bruteforce_J(n, h, R_f, R_N, _p(a), _p(p), _pp(U3), _p(J))
+    return J
+
+
+def gauss_legendre(npts: int):
+    x, w = np.empty(npts), np.empty(npts)
+    lib().oracle_gauss_legendre(npts, _p(x), _p(w))
+    return x, w

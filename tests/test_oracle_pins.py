@@ -1,0 +1,370 @@
+"""Pins of the FP64 oracle against mathematics and the paper (CPU only).
+
+Each test ties one oracle function to something other than itself: a
+library routine for a special case, a closed form, an identity, an
+invariant, or brute force on a small grid.  Together they are chosen so that
+a plausible mistake anywhere in the oracle (a dropped term, a wrong sign or
+index, a transposed operand, a missing h^3) fails at least one of them.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_1504_06289_amd import workloads as wl
+from tests.metrics import e_J
+
+SQRTPI = math.sqrt(math.pi)
+
+
+def accurate_rule(h, t_lo=1e-9, hu=0.25):
+    """A fine sinc rule: nodes from t_lo (lower truncation error about
+    1.13 t_lo r) to 2e4/h (the origin-cell error falls like (t_hi h)^-2) with
+    step hu (discretisation error ~exp(-pi^2/hu))."""
+    lo, hi = math.log(t_lo), math.log(2e4 / h)
+    R_N = int(math.ceil((hi - lo) / hu)) + 1
+    return R_N, lo, hu
+
+
+# --------------------------------------------------------------------------
+# Quadrature building blocks
+# --------------------------------------------------------------------------
+def test_gauss_legendre_matches_library(orc):
+    x, w = orc.gauss_legendre(20)
+    xr, wr = np.polynomial.legendre.leggauss(20)
+    order = np.argsort(x)
+    np.testing.assert_allclose(x[order], xr, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w[order], wr, rtol=1e-13)
+    # exact for polynomials of degree <= 39
+    for k in range(20):
+        assert abs(np.sum(w * x ** (2 * k)) - 2.0 / (2 * k + 1)) < 1e-14
+
+
+def _cell_integral_mp(t, h, m):
+    """(sqrt(pi)/2t)(erfc(alpha) - erfc(beta)) in 60-digit arithmetic (the
+    complementary form keeps full relative precision in the far tail)."""
+    m = abs(m)
+    with mp.workdps(60):
+        t, h = mp.mpf(t), mp.mpf(h)
+        alpha = t * (m - mp.mpf(1) / 2) * h
+        beta = t * (m + mp.mpf(1) / 2) * h
+        return mp.sqrt(mp.pi) / (2 * t) * (mp.erfc(alpha) - mp.erfc(beta))
+
+
+@pytest.mark.parametrize("t", [6.5e-6, 1e-3, 0.37, 2.0, 17.0, 183.0, 533.0])
+@pytest.mark.parametrize("h", [0.15625, 0.0195, 0.005859375])
+def test_cell_integral_vs_mpmath(orc, t, h):
+    """Appendix 3, vector b(t_k): every evaluation branch (erf at the
+    origin, erf / erfc differences, the flat-cell Gauss-Legendre form) against
+    high-precision arithmetic."""
+    for m in [0, 1, -1, 2, 3, 7, 31, 100, 1023, 4095]:
+        ref = _cell_integral_mp(t, h, m)
+        got = orc.cell_integral(t, h, m)
+        if abs(ref) < 1e-300:      # below the smallest normal double
+            assert abs(got) < 1e-300
+            continue
+        rel = abs((got - ref) / ref)
+        # the value at the given doubles is conditioned like exp(-x^2) at
+        # x = t(|m|+1/2)h: rounding the argument alone moves it by ~2x^2 ulp
+        x = t * (abs(m) + 0.5) * h
+        assert rel < 3e-15 + 4.5e-16 * 2 * x * x, (t, h, m, got, float(ref), float(rel))
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_kernel_telescoping_and_symmetry(orc, name):
+    """The cells tile [-(n-1/2)h, (n-1/2)h]: the sum over all lags is a single
+    erf (an identity independent of the per-cell evaluation)."""
+    w = wl.config(name) if name == "c1" else None
+    if w is None:
+        n, b, R_N = 4096, 12.0, 32
+        u0, hu = wl.sinc_params(R_N, n, b)
+    else:
+        n, b, R_N, u0, hu = w.n[0], w.b, w.R_N, w.u0, w.hu
+    h = 2 * b / n
+    t, a, c, p = orc.newton_kernel(n, h, R_N, u0, hu)
+    assert p.shape == (R_N, 2 * n - 1)
+    np.testing.assert_array_equal(p, p[:, ::-1])            # p[-m] = p[m]
+    np.testing.assert_allclose(c, a * h ** 3, rtol=1e-15)
+    for k in range(R_N):
+        tot = math.fsum(p[k])
+        ref = SQRTPI / t[k] * math.erf(t[k] * (n - 0.5) * h)
+        assert abs(tot - ref) / ref < 2e-14, (k, tot, ref)
+        # bell shape: maximal at lag 0, non-increasing in |m|
+        assert np.all(np.diff(p[k, n - 1:]) <= 0)
+
+
+def test_sinc_rule_reproduces_inverse_distance(orc):
+    """r * sum_k a_k exp(-t_k^2 r^2) -> 1 (eq. sinc_Newt) with the fitted
+    parameters, and the error falls fast when the node density is raised
+    over the same node range (the exponential sinc convergence)."""
+    h, b = 20.0 / 128, 10.0
+    r = np.logspace(np.log10(h / 2), np.log10(2 * np.sqrt(3) * b), 3000)
+
+    def err(R_N, u0, hu):
+        t, a = orc.sinc_rule(R_N, u0, hu)
+        s = (a[None, :] * np.exp(-np.outer(r * r, t * t))).sum(1)
+        return np.max(np.abs(r * s - 1))
+
+    u0, hu = wl.sinc_params(20, 128, 10.0)
+    assert err(20, u0, hu) < 1e-2
+    # refine: same node range [lo, hi], more nodes, wider coverage
+    lo, hi = math.log(1e-10), math.log(1e3)
+    errs = []
+    for R_N in (30, 45, 60, 90, 120):
+        errs.append(err(R_N, lo, (hi - lo) / (R_N - 1)))
+    assert errs[-1] < 3e-8, errs
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+    # the weights are the rule's: a_k = (2/sqrt(pi)) hu t_k
+    t, a = orc.sinc_rule(5, -1.0, 0.25)
+    np.testing.assert_allclose(t, np.exp(-1.0 + 0.25 * np.arange(5)), rtol=1e-15)
+    np.testing.assert_allclose(a, 2 / SQRTPI * 0.25 * t, rtol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# The 3D kernel against exact cell integrals of 1/|y|
+# --------------------------------------------------------------------------
+def _prism(x1, x2, y1, y2, z1, z2):
+    """Exact integral of 1/|y| over a box (potential of a uniform prism)."""
+    def F(x, y, z):
+        r = mp.sqrt(x * x + y * y + z * z)
+        s = mp.mpf(0)
+        for c, v in ((y * z, x + r), (x * z, y + r), (x * y, z + r)):
+            if c != 0:
+                s += c * mp.log(v)
+        for q, num, den in ((x, y * z, x * r), (y, x * z, y * r), (z, x * y, z * r)):
+            if q != 0:
+                s -= q * q / 2 * mp.atan(num / den)
+        return s
+
+    tot = mp.mpf(0)
+    for x, sx in ((x2, 1), (x1, -1)):
+        for y, sy in ((y2, 1), (y1, -1)):
+            for z, sz in ((z2, 1), (z1, -1)):
+                tot += sx * sy * sz * F(mp.mpf(x), mp.mpf(y), mp.mpf(z))
+    return tot
+
+
+def test_prism_formula_against_cubature():
+    from scipy.integrate import tplquad
+    with mp.workdps(30):
+        got = float(_prism(0.5, 1.5, -0.5, 0.5, -0.5, 1.5))
+    ref, err = tplquad(lambda z, y, x: 1 / math.sqrt(x * x + y * y + z * z),
+                       0.5, 1.5, -0.5, 0.5, -0.5, 1.5, epsabs=1e-14, epsrel=1e-13)
+    assert abs(got - ref) / ref < 1e-12
+    with mp.workdps(30):
+        assert abs(_prism(-.5, .5, -.5, .5, -.5, .5)
+                   - (3 * mp.log(2 + mp.sqrt(3)) - mp.pi / 2)) < 1e-25
+
+
+def test_origin_cell_identity(orc):
+    """sum_k a_k p_k[0]^3 -> h^2 (3 ln(2+sqrt3) - pi/2) = integral of 1/|y|
+    over the cell at the origin."""
+    const = 3 * math.log(2 + math.sqrt(3)) - math.pi / 2
+    assert abs(const - 2.3800773639795535) < 1e-15
+    for h in (0.15625, 0.0195, 0.004):
+        R_N, lo, hu = accurate_rule(h)
+        t, a, c, p = orc.newton_kernel(8, h, R_N, lo, hu)
+        val = math.fsum(a * p[:, 7] ** 3)
+        assert abs(val / (h * h) - const) / const < 2e-7, (h, val / h / h)
+
+
+def test_lag_kernel_vs_exact_prism(orc):
+    """sum_k a_k prod_l p_k[m_l] against the exact cell integral of 1/|y| at
+    a spread of lag vectors: pins the Galerkin kernel (with h^3 scaling)
+    up to the sinc-quadrature error."""
+    n, h = 64, 0.1
+    R_N, lo, hu = accurate_rule(h)
+    t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+    for m in [(0, 0, 0), (1, 0, 0), (1, 1, 1), (3, 2, 0), (10, 5, 7), (40, 0, 3), (-7, 2, -1),
+              (63, 63, 63)]:
+        val = math.fsum(a * p[:, m[0] + n - 1] * p[:, m[1] + n - 1] * p[:, m[2] + n - 1])
+        with mp.workdps(40):
+            ref = _prism(*[x for mm in m for x in ((mm - 0.5) * h, (mm + 0.5) * h)])
+        assert abs(val - ref) / ref < 2e-7, (m, val, float(ref))
+    # the fitted 20-term rule of the 128-cell workload: within its fit error
+    w = wl.config("c1")
+    h = 2 * w.b / 128
+    t, a, c, p = orc.newton_kernel(128, h, w.R_N, w.u0, w.hu)
+    for m in [(0, 0, 0), (2, 1, 0), (30, 20, 10), (100, 0, 0)]:
+        val = math.fsum(a * p[:, m[0] + 127] * p[:, m[1] + 127] * p[:, m[2] + 127])
+        with mp.workdps(40):
+            ref = _prism(*[x for mm in m for x in ((mm - 0.5) * h, (mm + 0.5) * h)])
+        assert abs(val - ref) / ref < 5e-3
+
+
+# --------------------------------------------------------------------------
+# Separable algebra: Toeplitz products, Grams, Hadamard sum
+# --------------------------------------------------------------------------
+def test_convolve_and_gram_against_dense_algebra(orc):
+    """W_k = T_k U with T_k[a, b] = p_k[a-b], G_k = U^T W_k: an explicit dense
+    Toeplitz matrix built with scipy and a matmul (library special case)."""
+    from scipy.linalg import toeplitz
+    rng = np.random.default_rng(3)
+    n, R_f, R_N = 37, 5, 3
+    p = rng.standard_normal((R_N, 2 * n - 1))
+    p = 0.5 * (p + p[:, ::-1])
+    U = rng.standard_normal((R_f, n))
+    W = orc.convolve(p, U)
+    G = orc.gram(U, W)
+    for k in range(R_N):
+        col = p[k, n - 1:]           # T[a, 0] = p[a]
+        row = p[k, n - 1::-1]        # T[0, b] = p[-b]
+        T = toeplitz(col, row)
+        np.testing.assert_allclose(W[k], (T @ U.T).T, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(G[k], U @ T @ U.T, rtol=1e-12, atol=1e-12)
+    # asymmetric p pins the lag direction: W[a] = sum_b p[a-b] u[b]
+    q = rng.standard_normal((1, 2 * n - 1))
+    Wq = orc.convolve(q, U)
+    Tq = toeplitz(q[0, n - 1:], q[0, n - 1::-1])
+    np.testing.assert_allclose(Wq[0], (Tq @ U.T).T, rtol=1e-13, atol=1e-13)
+    # plain (uncompensated) loops agree to rounding
+    np.testing.assert_allclose(orc.convolve(p, U, compensated=False), W, rtol=1e-12, atol=1e-12)
+
+
+def test_tei_gram_matches_bruteforce_3d(orc):
+    """The factorised J against direct summation over the full 3D grid with
+    the assembled 3D kernel: pins lag direction, mode pairing and h^3."""
+    n, b, R_N = 14, 6.0, 10
+    h = 2 * b / n
+    u0, hu = wl.sinc_params(R_N, n, b)
+    U, meta = wl.gaussian_products(n, b, 3, seed=11, alpha=(0.1, 3.0))
+    t, a, c, p = orc.newton_kernel(n, h, R_N, u0, hu)
+    J = orc.tei_gram(c, [p, p, p], U)
+    Jb = orc.bruteforce_J(h, a, p, U)
+    assert e_J(J, Jb) < 1e-13
+    # symmetric up to rounding
+    assert np.max(np.abs(J - J.T)) <= 1e-14 * np.max(np.abs(J))
+
+
+def _boys_ssss(a1, A1, a2, A2):
+    """(ss|ss) for unnormalised s Gaussians: 2 pi^{5/2}/(pq sqrt(p+q)) F0(T)."""
+    with mp.workdps(40):
+        p, q = mp.mpf(a1), mp.mpf(a2)
+        R2 = sum((mp.mpf(x) - mp.mpf(y)) ** 2 for x, y in zip(A1, A2))
+        T = p * q / (p + q) * R2
+        F0 = mp.mpf(1) if T == 0 else mp.sqrt(mp.pi / T) * mp.erf(mp.sqrt(T)) / 2
+        return 2 * mp.pi ** mp.mpf(2.5) / (p * q * mp.sqrt(p + q)) * F0
+
+
+@pytest.mark.slow
+def test_tei_gram_boys_closed_form_h2(orc):
+    """J -> the Gaussian-Gaussian Coulomb integral (Boys function) with an
+    O(h^2) discretisation error (the accuracy of the collocated grid
+    representation), once the quadrature error is negligible."""
+    b = 10.0
+    alphas = np.array([0.6, 1.3, 0.8, 2.0])
+    centres = np.array([[0.3, -0.4, 0.1], [-1.1, 0.7, 0.5], [1.4, 1.0, -0.8], [0.0, 0.2, 0.0]])
+    ref = np.array([[float(_boys_ssss(alphas[i], centres[i], alphas[j], centres[j]))
+                     for j in range(4)] for i in range(4)])
+    errs = []
+    Js = {}
+    for n in (64, 128, 256, 512):
+        h = 2 * b / n
+        R_N, lo, hu = accurate_rule(h)
+        t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+        U, _ = wl.s_gaussians(n, b, 4, alphas=alphas, centres=centres)
+        J = orc.tei_gram(c, [p, p, p], U)
+        Js[n] = J
+        errs.append(np.max(np.abs(J - ref) / np.abs(ref)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert errs[-1] < 2e-4
+    for r in ratios[1:]:
+        assert 3.5 < r < 4.6, (errs, ratios)
+    rich = (4 * Js[512] - Js[256]) / 3
+    assert np.max(np.abs(rich - ref) / np.abs(ref)) < 2e-6, errs
+
+
+def test_J_symmetric_psd_products(orc):
+    """J = J^T, J_ii > 0 and J is positive semi-definite up to rounding (each
+    T_k is positive definite, Schur products of PSD matrices are PSD and
+    c_k > 0)."""
+    w = wl.small_products(96, 24, R_N=12, b=8.0, seed=5)
+    h = w.h[0]
+    t, a, c, p = orc.newton_kernel(w.n[0], h, w.R_N, w.u0, w.hu)
+    assert np.all(c > 0)
+    J = orc.tei_gram(c, [p, p, p], w.U)
+    assert np.max(np.abs(J - J.T)) <= 1e-15 * np.max(np.abs(J))
+    assert np.all(np.diag(J) > 0)
+    lam = np.linalg.eigvalsh(0.5 * (J + J.T))
+    assert lam[0] >= -1e-13 * lam[-1]
+    # Cauchy-Schwarz bound that the normalised metric relies on
+    d = np.sqrt(np.diag(J))
+    assert np.all(np.abs(J) <= np.outer(d, d) * (1 + 1e-12))
+
+
+def test_tei_gram_columns_match_full(orc):
+    w = wl.small_products((40, 33, 47), 9, R_N=7, b=7.0, seed=2)
+    ps, c = [], None
+    for l in range(3):
+        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
+        ps.append(p)
+    c = a * w.h[0] * w.h[1] * w.h[2]
+    J, G = orc.tei_gram(c, ps, w.U, return_G=True)
+    cols = [0, 4, 8]
+    Jc = orc.tei_gram_columns(c, ps, w.U, cols)
+    np.testing.assert_allclose(Jc, J[:, cols].T, rtol=1e-14, atol=0)
+    # G symmetric per mode and term
+    np.testing.assert_allclose(G, np.swapaxes(G, 2, 3), rtol=1e-13, atol=1e-300)
+
+
+# --------------------------------------------------------------------------
+# Potential factors (tc_convolve): the Hartree potential of one Gaussian
+# --------------------------------------------------------------------------
+def test_potential_factors_give_gaussian_potential(orc):
+    """V(x) = sum_k a_k prod_l W^l_k[x_l] (eq. conv with the canonical kernel)
+    approximates the potential of exp(-alpha|x-A|^2), which is
+    (pi/alpha)^{3/2} erf(sqrt(alpha)|x-A|)/|x-A|."""
+    n, b = 256, 10.0
+    h = 2 * b / n
+    R_N, lo, hu = accurate_rule(h)
+    t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+    alpha, A = np.array([0.9]), np.array([[0.2, -0.3, 0.45]])
+    U, _ = wl.s_gaussians(n, b, 1, alphas=alpha, centres=A)
+    Ws = [orc.convolve(p, U[l]) for l in range(3)]
+    x = wl.grid(n, b)
+    worst = 0.0
+    for idx in [(128, 128, 128), (100, 140, 129), (60, 200, 130), (10, 128, 240)]:
+        V = math.fsum(a[k] * Ws[0][k, 0, idx[0]] * Ws[1][k, 0, idx[1]] * Ws[2][k, 0, idx[2]]
+                      for k in range(R_N))
+        r = math.sqrt(sum((x[idx[l]] - A[0, l]) ** 2 for l in range(3)))
+        ref = (math.pi / alpha[0]) ** 1.5 * math.erf(math.sqrt(alpha[0]) * r) / r
+        worst = max(worst, abs(V - ref) / ref)
+    assert worst < 2e-3
+
+
+# --------------------------------------------------------------------------
+# Adjoint
+# --------------------------------------------------------------------------
+def test_backward_matches_central_differences(orc):
+    """f = w^T J w is quadratic in every single entry of U^l, so the central
+    difference is exact up to rounding of the compensated forward."""
+    w = wl.small_products((24, 19, 28), 6, R_N=6, b=6.0, seed=9)
+    ps = []
+    for l in range(3):
+        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
+        ps.append(p)
+    c = a * w.h[0] * w.h[1] * w.h[2]
+    rng = np.random.default_rng(4)
+    wv = rng.standard_normal(w.R_f)
+    dU = orc.tei_gram_backward(c, ps, w.U, np.outer(wv, wv))
+
+    def f(U3):
+        return float(wv @ orc.tei_gram(c, ps, U3) @ wv)
+
+    for l in range(3):
+        for (i, a_) in [(0, 3), (2, w.n[l] // 2), (5, w.n[l] - 1), (3, 7)]:
+            delta = 1e-3 * max(abs(w.U[l][i, a_]), 1e-3)
+            Up = [u.copy() for u in w.U]
+            Um = [u.copy() for u in w.U]
+            Up[l][i, a_] += delta
+            Um[l][i, a_] -= delta
+            fd = (f(Up) - f(Um)) / (2 * delta)
+            scale = np.max(np.abs(dU[l]))
+            assert abs(fd - dU[l][i, a_]) <= 1e-9 * scale, (l, i, a_, fd, dU[l][i, a_])
+    # a non-symmetric Jbar is symmetrised by the adjoint
+    Jb = rng.standard_normal((w.R_f, w.R_f))
+    d1 = orc.tei_gram_backward(c, ps, w.U, Jb)
+    d2 = orc.tei_gram_backward(c, ps, w.U, 0.5 * (Jb + Jb.T))
+    for l in range(3):
+        np.testing.assert_allclose(d1[l], d2[l], rtol=1e-13, atol=1e-13 * np.abs(d2[l]).max())
