@@ -1,0 +1,177 @@
+/*
+ * tc.h -- C ABI of the MI355X (gfx950) library for the grid-based
+ * Newton-kernel convolution and two-electron-integral (TEI) Gram assembly of
+ * Khoromskaia & Khoromskij, arXiv:1504.06289.
+ *
+ * What the library computes (notation of the paper, Sections 2.5, 3.1, 3.2
+ * and Appendix 3):
+ *
+ *   grid          n_l cells of width h_l per mode l = 1,2,3, cell-centred;
+ *   side matrix   U^l in R^{n_l x R_f}: column j is function j's mode-l
+ *                 vector (the product side matrices of Section 3.2);
+ *   kernel        rank-R_N canonical Newton kernel (eq. NewtCan and
+ *                 Appendix 3 eq. sinc_general), term k given by the weight
+ *                 c_k > 0 and the per-mode vectors p^l_k[m], lag
+ *                 m = -(n_l-1)..(n_l-1), with the Toeplitz matrix
+ *                 T^l_k[a][b] = p^l_k[a-b];
+ *   convolution   W^l_k = T^l_k U^l  (the 1D convolutions p_k *_n U of
+ *                 eq. Factor_Mk_Conv, aperiodic, restricted to the box);
+ *   Grams         G^l_k = U^l^T W^l_k  (the matrices M_k^(l) of
+ *                 eq. Factor_Mk_Conv);
+ *   TEI matrix    J = sum_k c_k G^1_k o G^2_k o G^3_k  (the factorised TEI
+ *                 matrix of Section 3.2 with V = I; o = Hadamard product).
+ *
+ * Conventions for every call:
+ *   - All numbers crossing the ABI are IEEE binary64 (double).  The
+ *     precision argument selects only the arithmetic of the Toeplitz and Gram
+ *     contractions inside the library; kernel generation, the Hadamard/sum
+ *     over k, and the adjoint's D formation are always binary64.
+ *   - Layouts are row-major and dense:
+ *       U   [R_f][n]       row j = column j of U^l (contiguous over cells)
+ *       p   [R_N][2n-1]    lag m of term k at p[k*(2n-1) + m + n - 1]
+ *       W   [R_N][R_f][n]
+ *       G   [3][R_N][R_f][R_f]
+ *       J   [R_f][R_f]     both triangles written
+ *   - "device" pointers are HIP device allocations (or managed/host-mapped
+ *     memory the device can read); "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer.  The library never allocates, frees or
+ *     synchronises: scratch memory comes from the caller's workspace (size
+ *     from tc_workspace_bytes), and all work is enqueued on the caller's
+ *     stream (a hipStream_t passed as void*; NULL = the default stream).
+ *   - Arguments are validated before anything is enqueued; on any error no
+ *     output is written.  Launch failures return TC_ERR_HIP.  Faults during
+ *     execution surface at the caller's next synchronisation.
+ *   - Results are bitwise reproducible for a given device, precision and
+ *     problem size (no floating-point atomics; fixed reduction orders).
+ *   - Calls on different streams may run concurrently if their outputs and
+ *     workspaces do not overlap.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_OK = 0,
+    TC_ERR_INVALID_ARG = 1, /* null pointer, size out of range, non-finite parameter */
+    TC_ERR_WORKSPACE = 2,   /* workspace missing or smaller than tc_workspace_bytes */
+    TC_ERR_UNSUPPORTED = 3, /* precision or size this build does not implement */
+    TC_ERR_HIP = 4          /* a HIP launch or runtime call failed */
+} tc_status;
+
+/* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions. */
+typedef enum {
+    TC_FP64 = 0,  /* binary64 matrix cores: error ~1e-15 relative           */
+    TC_FP32 = 1,  /* binary32 operands on matrix cores, binary32 partial sums
+                     over short K-chunks, binary64 accumulation across them  */
+    TC_SPLIT3 = 2 /* operands split into three bfloat16 slices with a common
+                     exponent per row/column, slice products accumulated
+                     exactly in binary32 within K-chunks, binary64 across
+                     them (an Ozaki-type error-free splitting)                */
+} tc_precision;
+
+/* Largest supported sizes (guards for index arithmetic). */
+#define TC_MAX_N 65536
+#define TC_MAX_RF 65536
+#define TC_MAX_RN 256
+
+/* One TEI problem.  Arrays of these form a batch. */
+typedef struct {
+    int n[3];            /* cells per mode, 1 <= n_l <= TC_MAX_N             */
+    int R_f;             /* number of product functions (columns of U)       */
+    int R_N;             /* number of kernel terms                           */
+    const double *c;     /* [R_N] device: weights c_k = a_k h_1 h_2 h_3 > 0  */
+    const double *p[3];  /* [R_N][2 n_l - 1] device; may alias across modes  */
+    const double *U[3];  /* [R_f][n_l] device                                */
+    double *J;           /* [R_f][R_f] device, output                        */
+    double *G_saved;     /* [3][R_N][R_f][R_f] device output, or NULL        */
+} tc_instance;
+
+/* Operation codes for tc_workspace_bytes. */
+#define TC_OP_CONVOLVE 0
+#define TC_OP_TEI_GRAM 1
+#define TC_OP_TEI_GRAM_BACKWARD 2
+
+/*
+ * tc_newton_kernel -- rank-R_N canonical Newton kernel on an n-cell grid of
+ * width h (Appendix 3).  Sinc rule for the Laplace-Gauss transform of 1/r
+ * (eq. sinc_Newt) in the variable u = log t: nodes t_k = exp(u0 + k hu),
+ * weights a_k = (2/sqrt(pi)) hu t_k, k = 0..R_N-1.  Kernel vectors are the
+ * Galerkin projections onto the piecewise-constant cells (eq. galten and the
+ * vectors b(t_k)):  p_k[m] = integral of exp(-t_k^2 s^2) over
+ * [(m-1/2)h, (m+1/2)h], m = -(n-1)..(n-1).
+ *   n      1..TC_MAX_N;  h > 0;  R_N 1..TC_MAX_RN;  u0, hu finite, hu > 0.
+ *   t_host [R_N] host output (may be NULL): the nodes t_k.
+ *   c_host [R_N] host output (may be NULL): c_k = a_k h^3 (isotropic grid;
+ *          for unequal modes use a_k = c_k / h^3 times h_1 h_2 h_3).
+ *   p_dev  [R_N][2n-1] device output.
+ *   The nodes are computed on the host, the vectors on the device.
+ */
+tc_status tc_newton_kernel(int n, double h, int R_N, double u0, double hu,
+                           double *t_host, double *c_host, double *p_dev,
+                           void *stream);
+
+/*
+ * tc_convolve -- potential factors W_k = T_k U for one mode (Section 2.5
+ * eq. conv; the factors of the canonical Hartree potential of each
+ * function):  W[k][j][a] = sum_b p[k][a-b+n-1] U[j][b].
+ *   p_dev [R_N][2n-1] device;  U_dev [R_f][n] device;
+ *   W_dev [R_N][R_f][n] device output (must not overlap the inputs).
+ *   prec  contraction arithmetic; ws/ws_bytes workspace
+ *         (tc_workspace_bytes(TC_OP_CONVOLVE, ...)).
+ */
+tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev,
+                      const double *U_dev, double *W_dev, tc_precision prec,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tc_tei_gram -- the TEI/Coulomb matrix of every instance (Section 3.2):
+ * J = sum_k c_k G^1_k o G^2_k o G^3_k with G^l_k = U^l^T T^l_k U^l.
+ * Instances are independent; their buffers must not overlap one another.
+ * When G_saved is non-NULL the Grams are also written there (the backward
+ * pass can then skip recomputing them).
+ *   inst  host array of count descriptors (pointers inside are device).
+ *   count >= 1.   ws: tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec).
+ */
+tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tc_tei_gram_backward -- adjoint of f = <Jbar, J> with respect to the side
+ * matrices: with S = (Jbar + Jbar^T)/2 and D^l_k = c_k S o G^{l+1}_k o
+ * G^{l+2}_k (modes cyclic), dU^l = 2 sum_k T^l_k U^l D^l_k = 2 sum_k W^l_k D^l_k
+ * (T_k and the Grams are symmetric).  For Jbar = w w^T this is the gradient
+ * of w^T J w.
+ *   Jbar  host array [count] of device pointers, each [R_f][R_f].
+ *   dU    host array [3*count] of device pointers: dU[3*i + l] is [R_f][n_l]
+ *         output for instance i, mode l.
+ *   Uses inst[i].G_saved when non-NULL (as written by tc_tei_gram with the
+ *   same inputs), otherwise recomputes the Grams.  inst[i].J is not touched.
+ */
+tc_status tc_tei_gram_backward(const tc_instance *inst, int count,
+                               const double *const *Jbar, double *const *dU,
+                               tc_precision prec, void *ws, size_t ws_bytes,
+                               void *stream);
+
+/*
+ * Workspace size in bytes for op (TC_OP_*) on the given problem(s); for
+ * TC_OP_CONVOLVE only inst[0].n[0], R_f and R_N are read.  Returns 0 when no
+ * workspace is needed and (size_t)-1 for invalid arguments.
+ */
+size_t tc_workspace_bytes(int op, const tc_instance *inst, int count,
+                          tc_precision prec);
+
+/* Static description of a status code (never NULL). */
+const char *tc_status_string(tc_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TC_H */

@@ -1,0 +1,6 @@
+"""MI355X (gfx950) library for the grid-based Newton-kernel convolution and
+two-electron-integral Gram assembly of Khoromskaia & Khoromskij
+(arXiv:1504.06289).  The C ABI is include/tc.h; this package is its thin
+Python binding (see api.py) plus the seeded synthetic workloads."""
+from .api import (TeiGram, convolve, newton_kernel, tei_gram, tei_gram_backward,  # noqa: F401
+                  tei_gram_batched)

@@ -1,0 +1,96 @@
+"""ctypes loader for libtc.so (the HIP library declared in include/tc.h).
+
+Loading fails loudly when the shared library has not been built: there is no
+fallback implementation anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK = 0
+TC_ERR_INVALID_ARG = 1
+TC_ERR_WORKSPACE = 2
+TC_ERR_UNSUPPORTED = 3
+TC_ERR_HIP = 4
+
+TC_FP64 = 0
+TC_FP32 = 1
+TC_SPLIT3 = 2
+PRECISIONS = {"fp64": TC_FP64, "fp32": TC_FP32, "split3": TC_SPLIT3}
+
+TC_OP_CONVOLVE = 0
+TC_OP_TEI_GRAM = 1
+TC_OP_TEI_GRAM_BACKWARD = 2
+
+# the ABI symbols declared in include/tc.h
+EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
+           "tc_workspace_bytes", "tc_status_string", "tc_version")
+
+
+class TcInstance(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3),
+        ("R_f", ctypes.c_int),
+        ("R_N", ctypes.c_int),
+        ("c", ctypes.c_void_p),
+        ("p", ctypes.c_void_p * 3),
+        ("U", ctypes.c_void_p * 3),
+        ("J", ctypes.c_void_p),
+        ("G_saved", ctypes.c_void_p),
+    ]
+
+
+class TcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}")
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_1504_06289_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        pd = ctypes.POINTER(ctypes.c_double)
+        L.tc_newton_kernel.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, pd, pd, vp, vp]
+        L.tc_newton_kernel.restype = ctypes.c_int
+        L.tc_convolve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                  ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.tc_convolve.restype = ctypes.c_int
+        L.tc_tei_gram.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int, vp,
+                                  ctypes.c_size_t, vp]
+        L.tc_tei_gram.restype = ctypes.c_int
+        L.tc_tei_gram_backward.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int,
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
+                                           vp, ctypes.c_size_t, vp]
+        L.tc_tei_gram_backward.restype = ctypes.c_int
+        L.tc_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(TcInstance), ctypes.c_int,
+                                         ctypes.c_int]
+        L.tc_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_status_string.argtypes = [ctypes.c_int]
+        L.tc_status_string.restype = ctypes.c_char_p
+        L.tc_version.argtypes = []
+        L.tc_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().tc_status_string(s).decode()
+
+
+def check(status: int, where: str):
+    if status != TC_OK:
+        raise TcError(status, where)

@@ -1,0 +1,192 @@
+"""Python binding of the tc C ABI (include/tc.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch supplies the
+device memory (float64 CUDA/HIP tensors) and the current stream.  Names
+follow the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PRECISIONS, TcInstance, check
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, int):
+        return prec
+    try:
+        return PRECISIONS[prec]
+    except KeyError:
+        raise ValueError(f"unknown precision {prec!r}; expected one of {list(PRECISIONS)}")
+
+
+def _dev_f64(x: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _ptr(x: Optional[torch.Tensor]):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def newton_kernel(n: int, h: float, R_N: int, u0: float, hu: float, device="cuda"):
+    """Canonical Newton kernel: returns (t [R_N] numpy, c [R_N] numpy with
+    c_k = a_k h^3, p [R_N][2n-1] float64 device tensor)."""
+    device = torch.device(device)
+    t = np.empty(R_N)
+    c = np.empty(R_N)
+    p = torch.empty((R_N, 2 * n - 1), dtype=torch.float64, device=device)
+    pd = ctypes.POINTER(ctypes.c_double)
+    check(_lib.lib().tc_newton_kernel(int(n), float(h), int(R_N), float(u0), float(hu),
+                                      t.ctypes.data_as(pd), c.ctypes.data_as(pd), _ptr(p),
+                                      _stream(device)), "tc_newton_kernel")
+    return t, c, p
+
+
+def convolve(p: torch.Tensor, U: torch.Tensor, prec="fp64",
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Potential factors W[k][j][a] = sum_b p[k][a-b+n-1] U[j][b]."""
+    _dev_f64(p, "p")
+    _dev_f64(U, "U")
+    R_N, L = p.shape
+    R_f, n = U.shape
+    if L != 2 * n - 1:
+        raise ValueError("p must have 2n-1 columns")
+    W = out if out is not None else torch.empty((R_N, R_f, n), dtype=torch.float64,
+                                                device=U.device)
+    _dev_f64(W, "out")
+    inst = TcInstance()
+    inst.n[0], inst.R_f, inst.R_N = n, R_f, R_N
+    ws_bytes = _lib.lib().tc_workspace_bytes(_lib.TC_OP_CONVOLVE, ctypes.byref(inst), 1,
+                                             _prec(prec))
+    ws = _workspace(ws_bytes, U.device) if ws_bytes else None
+    check(_lib.lib().tc_convolve(n, R_f, R_N, _ptr(p), _ptr(U), _ptr(W), _prec(prec), _ptr(ws),
+                                 ws_bytes, _stream(U.device)), "tc_convolve")
+    return W
+
+
+def make_instance(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],
+                  J: torch.Tensor, G: Optional[torch.Tensor] = None) -> TcInstance:
+    _dev_f64(c, "c")
+    inst = TcInstance()
+    R_f = U3[0].shape[0]
+    inst.R_f = R_f
+    inst.R_N = c.shape[0]
+    for l in range(3):
+        _dev_f64(p3[l], f"p[{l}]")
+        _dev_f64(U3[l], f"U[{l}]")
+        if U3[l].shape[0] != R_f:
+            raise ValueError("all modes must have R_f columns")
+        inst.n[l] = U3[l].shape[1]
+        if p3[l].shape != (inst.R_N, 2 * inst.n[l] - 1):
+            raise ValueError(f"p[{l}] must be [R_N][2n-1]")
+        inst.p[l] = p3[l].data_ptr()
+        inst.U[l] = U3[l].data_ptr()
+    _dev_f64(J, "J")
+    inst.c = c.data_ptr()
+    inst.J = J.data_ptr()
+    inst.G_saved = G.data_ptr() if G is not None else None
+    return inst
+
+
+def tei_gram(c: torch.Tensor, p3, U3, prec="fp64", save_G: bool = False):
+    """J = sum_k c_k G1_k o G2_k o G3_k.  Returns J, or (J, G) with
+    G [3][R_N][R_f][R_f] when save_G."""
+    dev = U3[0].device
+    R_f = U3[0].shape[0]
+    R_N = c.shape[0]
+    J = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+    G = torch.empty((3, R_N, R_f, R_f), dtype=torch.float64, device=dev) if save_G else None
+    inst = make_instance(c, p3, U3, J, G)
+    _run_gram([inst], prec, dev)
+    return (J, G) if save_G else J
+
+
+def tei_gram_batched(instances, prec="fp64", save_G: bool = False):
+    """instances: sequence of (c, p3, U3).  Returns the list of J (and Gs)."""
+    dev = instances[0][2][0].device
+    Js, Gs, arr = [], [], (TcInstance * len(instances))()
+    for i, (c, p3, U3) in enumerate(instances):
+        R_f = U3[0].shape[0]
+        J = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+        G = (torch.empty((3, c.shape[0], R_f, R_f), dtype=torch.float64, device=dev)
+             if save_G else None)
+        arr[i] = make_instance(c, p3, U3, J, G)
+        Js.append(J)
+        Gs.append(G)
+    _run_gram(arr, prec, dev)
+    return (Js, Gs) if save_G else Js
+
+
+def _run_gram(insts, prec, dev):
+    if isinstance(insts, list):
+        arr = (TcInstance * len(insts))(*insts)
+    else:
+        arr = insts
+    count = len(arr)
+    L = _lib.lib()
+    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, count, _prec(prec))
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("invalid problem sizes")
+    ws = _workspace(ws_bytes, dev) if ws_bytes else None
+    check(L.tc_tei_gram(arr, count, _prec(prec), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_tei_gram")
+
+
+def tei_gram_backward(c: torch.Tensor, p3, U3, Jbar: torch.Tensor,
+                      G: Optional[torch.Tensor] = None, prec="fp64"):
+    """dU^l = 2 sum_k T_k U^l D^l_k for f = <Jbar, J>.  Returns [dU1, dU2, dU3]."""
+    dev = U3[0].device
+    R_f = U3[0].shape[0]
+    _dev_f64(Jbar, "Jbar")
+    if Jbar.shape != (R_f, R_f):
+        raise ValueError("Jbar must be [R_f][R_f]")
+    dummyJ = torch.empty((1, 1), dtype=torch.float64, device=dev)
+    inst = make_instance(c, p3, U3, dummyJ, G)
+    dU = [torch.empty_like(U3[l]) for l in range(3)]
+    arr = (TcInstance * 1)(inst)
+    jb = (ctypes.c_void_p * 1)(Jbar.data_ptr())
+    du = (ctypes.c_void_p * 3)(*[d.data_ptr() for d in dU])
+    L = _lib.lib()
+    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _prec(prec))
+    ws = _workspace(ws_bytes, dev)
+    check(L.tc_tei_gram_backward(arr, 1, jb, du, _prec(prec), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_tei_gram_backward")
+    return dU
+
+
+class TeiGram(torch.autograd.Function):
+    """J = TeiGram.apply(c, p1, p2, p3, U1, U2, U3, prec): differentiable in
+    U1..U3 through the hand-written adjoint (tc_tei_gram_backward)."""
+
+    @staticmethod
+    def forward(ctx, c, p1, p2, p3, U1, U2, U3, prec="fp64"):
+        J, G = tei_gram(c, (p1, p2, p3), (U1, U2, U3), prec=prec, save_G=True)
+        ctx.save_for_backward(c, p1, p2, p3, U1, U2, U3, G)
+        ctx.prec = prec
+        return J
+
+    @staticmethod
+    def backward(ctx, Jbar):
+        c, p1, p2, p3, U1, U2, U3, G = ctx.saved_tensors
+        dU = tei_gram_backward(c, (p1, p2, p3), (U1, U2, U3), Jbar.contiguous(), G=G,
+                               prec=ctx.prec)
+        return None, None, None, None, dU[0], dU[1], dU[2], None

@@ -1,0 +1,43 @@
+// Internal interface between the C-ABI layer (tc_api.cpp) and the kernel
+// translation units.  Every launcher enqueues on `stream` and returns the
+// hipError_t of the launch; none allocates or synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tc {
+
+// ---- kernel generation (kernel_gen.hip) ----------------------------------
+// p[k][m+n-1] = integral of exp(-t_k^2 s^2) over cell m, for k < R_N.
+hipError_t launch_newton_kernel(const double *t_host, int R_N, int n, double h,
+                                double *p_dev, hipStream_t stream);
+
+// ---- Toeplitz products (toeplitz.hip) -------------------------------------
+// W[k][j][a] = sum_b p[k][a-b+n-1] U[j][b] in binary64 on matrix cores.
+hipError_t launch_toeplitz_f64(const double *p, const double *U, double *W, int n,
+                               int R_f, int R_N, hipStream_t stream);
+
+// ---- Grams (gram.hip) -----------------------------------------------------
+// G[k][i][j] = sum_a U[i][a] W[k][j][a] for all k < R_N, exactly symmetric
+// (upper-triangle tiles computed, mirrored).
+hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n,
+                           int R_f, int R_N, hipStream_t stream);
+
+// ---- Hadamard product across modes and sum over k (reduce.hip) -----------
+// J[e] = sum_k c[k] G0[k][e] G1[k][e] G2[k][e], e < R_f*R_f.
+hipError_t launch_hadamard_sum(const double *c, const double *G0, const double *G1,
+                               const double *G2, double *J, int R_f, int R_N,
+                               hipStream_t stream);
+
+// ---- Adjoint pieces (reduce.hip, gemm.hip) --------------------------------
+// D[k][e] = c[k] * 0.5*(Jbar[e] + Jbar[e^T]) * Ga[k][e] * Gb[k][e]
+hipError_t launch_adjoint_d(const double *c, const double *Jbar, const double *Ga,
+                            const double *Gb, double *D, int R_f, int R_N,
+                            hipStream_t stream);
+// dU[i][a] = scale * sum_k sum_j D[k][j][i] W[k][j][a]
+hipError_t launch_adjoint_gemm_f64(const double *D, const double *W, double *dU, int n,
+                                   int R_f, int R_N, double scale, hipStream_t stream);
+
+}  // namespace tc

@@ -9,11 +9,16 @@ import numpy as np
 
 
 def e_J(J, J_ref):
+    """Normalised error.  Entries whose reference diagonals vanish (a
+    function that is zero on the whole grid) must match exactly."""
     J = np.asarray(J, dtype=np.float64)
     J_ref = np.asarray(J_ref, dtype=np.float64)
     d = np.sqrt(np.abs(np.diag(J_ref)))
     scale = np.outer(d, d)
-    return float(np.max(np.abs(J - J_ref) / scale))
+    diff = np.abs(J - J_ref)
+    zero = scale == 0
+    err = np.where(zero, np.where(diff == 0, 0.0, np.inf), diff / np.where(zero, 1.0, scale))
+    return float(np.max(err))
 
 
 def e_J_block(Jblock, Jref_block, diag_rows, diag_cols):

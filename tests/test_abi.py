@@ -1,0 +1,150 @@
+"""The C-ABI library loads and exports every symbol include/tc.h declares, and
+its host-side validation rejects bad arguments before touching the GPU
+(CPU only: none of these calls reaches a kernel launch)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1504_06289_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libtc.so is not built (python -m paper_1504_06289_amd.build)")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTS), names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    for s in range(5):
+        assert L.tc_status_string(s).decode().startswith("TC_")
+    assert b"unknown" in L.tc_status_string(99)
+    assert L.tc_version() >= 100
+
+
+def _inst(n=64, R_f=8, R_N=4, null=None):
+    I = _lib.TcInstance()
+    for l in range(3):
+        I.n[l] = n
+        I.p[l] = 0x1000
+        I.U[l] = 0x2000
+    I.R_f, I.R_N = R_f, R_N
+    I.c = 0x3000
+    I.J = 0x4000
+    I.G_saved = None
+    if null:
+        setattr(I, null, None)
+    return I
+
+
+def test_workspace_bytes(L):
+    I = _inst(n=100, R_f=10, R_N=3)
+    arr = (_lib.TcInstance * 1)(I)
+    w = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
+    # W of one mode + the three modes' Grams, each rounded up to 256 bytes
+    up = lambda x: (x + 255) // 256 * 256
+    assert w == up(8 * 3 * 10 * 100) + up(8 * 3 * 3 * 100)
+    I.G_saved = 0x5000
+    arr = (_lib.TcInstance * 1)(I)
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == up(8 * 3 * 10 * 100)
+    wb = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_FP64)
+    assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100)
+    bad = (_lib.TcInstance * 1)(_inst(n=0))
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, bad, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
+    assert L.tc_workspace_bytes(7, arr, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, 42) == ctypes.c_size_t(-1).value
+
+
+@pytest.mark.parametrize("kw", [dict(n=0), dict(n=70000), dict(R_f=0), dict(R_N=0),
+                                dict(R_N=1000), dict(null="c"), dict(null="J")])
+def test_tei_gram_rejects_bad_instances(L, kw):
+    arr = (_lib.TcInstance * 1)(_inst(**kw))
+    s = L.tc_tei_gram(arr, 1, _lib.TC_FP64, None, 0, None)
+    assert s == _lib.TC_ERR_INVALID_ARG
+
+
+def test_tei_gram_rejects_null_mode_pointers(L):
+    I = _inst()
+    I.U[1] = None
+    assert L.tc_tei_gram((_lib.TcInstance * 1)(I), 1, _lib.TC_FP64, None, 0, None) == \
+        _lib.TC_ERR_INVALID_ARG
+    I = _inst()
+    I.p[2] = None
+    assert L.tc_tei_gram((_lib.TcInstance * 1)(I), 1, _lib.TC_FP64, None, 0, None) == \
+        _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tei_gram(None, 1, _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    arr = (_lib.TcInstance * 1)(_inst())
+    assert L.tc_tei_gram(arr, 0, _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tei_gram(arr, 1, 17, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_tei_gram_workspace_checked_before_launch(L):
+    arr = (_lib.TcInstance * 1)(_inst())
+    need = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
+    assert need > 0
+    assert L.tc_tei_gram(arr, 1, _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_tei_gram(arr, 1, _lib.TC_FP64, ctypes.c_void_p(0x6000), need - 1, None) == \
+        _lib.TC_ERR_WORKSPACE
+
+
+def test_newton_kernel_rejects(L):
+    pd = ctypes.POINTER(ctypes.c_double)
+    nul = ctypes.cast(None, pd)
+    p = ctypes.c_void_p(0x1000)
+    nan = float("nan")
+    cases = [(0, 0.1, 4, -1.0, 0.5, p), (64, 0.0, 4, -1.0, 0.5, p), (64, -1.0, 4, -1.0, 0.5, p),
+             (64, 0.1, 0, -1.0, 0.5, p), (64, 0.1, 4, nan, 0.5, p), (64, 0.1, 4, -1.0, 0.0, p),
+             (64, 0.1, 4, -1.0, float("inf"), p), (64, 0.1, 4, -1.0, 0.5, None),
+             (64, 0.1, 4, 800.0, 0.5, p)]  # exp overflows: t_k not finite
+    for n, h, R_N, u0, hu, pp in cases:
+        assert L.tc_newton_kernel(n, h, R_N, u0, hu, nul, nul, pp, None) == \
+            _lib.TC_ERR_INVALID_ARG, (n, h, R_N, u0, hu)
+
+
+def test_convolve_rejects(L):
+    v = ctypes.c_void_p(0x1000)
+    assert L.tc_convolve(0, 4, 4, v, v, v, 0, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_convolve(8, 4, 4, None, v, v, 0, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_convolve(8, 4, 4, v, v, None, 0, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_convolve(8, 4, 4, v, v, v, 9, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_backward_rejects(L):
+    arr = (_lib.TcInstance * 1)(_inst())
+    jb = (ctypes.c_void_p * 1)(0x7000)
+    du = (ctypes.c_void_p * 3)(0x8000, 0x9000, None)
+    assert L.tc_tei_gram_backward(arr, 1, jb, du, _lib.TC_FP64, None, 0, None) == \
+        _lib.TC_ERR_INVALID_ARG
+    du = (ctypes.c_void_p * 3)(0x8000, 0x9000, 0xa000)
+    assert L.tc_tei_gram_backward(arr, 1, jb, du, _lib.TC_FP64, None, 0, None) == \
+        _lib.TC_ERR_WORKSPACE
+    jb0 = (ctypes.c_void_p * 1)(None)
+    assert L.tc_tei_gram_backward(arr, 1, jb0, du, _lib.TC_FP64, None, 0, None) == \
+        _lib.TC_ERR_INVALID_ARG
+
+
+def test_product_path_has_no_fallback():
+    """The package never imports the oracle and fails loudly without libtc.so."""
+    pkg = os.path.join(ROOT, "paper_1504_06289_amd")
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert not re.search(r"^\s*(from\s+oracle|import\s+oracle)", src, flags=re.M), f
+            assert "liboracle" not in src, f

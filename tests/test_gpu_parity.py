@@ -1,0 +1,241 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
+
+Every GPU result is compared element by element with the oracle on the same
+seeded inputs, at sizes spanning several tiles with ragged tails, plus the
+degenerate sizes.  Tolerances (FP64 path):
+  * kernel vectors p: relative 1e-14 plus the conditioning of exp(-x^2) at
+    x = t(|m|+1/2)h (rounding the argument moves the value by ~2x^2 ulp);
+  * W = T U: |dW| <= 1e-13 (|T| |U|)  (a rounding-error bound of the product);
+  * J: normalised error max |dJ_ij| / sqrt(J_ii J_jj) <= 1e-12;
+  * adjoint: relative Frobenius error <= 1e-12 per mode.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1504_06289_amd import workloads as wl
+from tests.metrics import e_J, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1504_06289_amd as tc
+    return tc
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+def kernel_tol(t, h, n):
+    m = np.abs(np.arange(-(n - 1), n))
+    x = np.outer(t, (m + 0.5) * h)
+    return 1e-14 + 9e-16 * 2 * x * x
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("R_N,n,b", [(20, 128, 10.0), (30, 1024, 10.0), (32, 4096, 12.0),
+                                     (7, 1, 3.0), (3, 2, 1.0), (150, 300, 10.0)])
+def test_newton_kernel_parity(tc, orc, R_N, n, b):
+    say(f"newton_kernel R_N={R_N} n={n} b={b}")
+    h = 2 * b / n
+    u0, hu = wl.sinc_params(R_N, n, b)
+    t, c, p = tc.newton_kernel(n, h, R_N, u0, hu)
+    tr, ar, cr, pr = orc.newton_kernel(n, h, R_N, u0, hu)
+    np.testing.assert_allclose(t, tr, rtol=2e-16, atol=0)
+    np.testing.assert_allclose(c, cr, rtol=4e-16, atol=0)
+    pg = host(p)
+    tiny = (np.abs(pr) < 1e-300) & (np.abs(pg) < 1e-300)
+    rel = np.abs(pg - pr) / np.where(tiny, 1.0, np.abs(pr))
+    rel[tiny] = 0.0
+    assert np.all(rel <= kernel_tol(tr, h, n)), float(rel.max())
+    np.testing.assert_array_equal(pg, pg[:, ::-1])
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,R_f,R_N", [(1, 1, 1), (5, 3, 2), (64, 64, 3), (100, 7, 4),
+                                       (257, 130, 5), (1024, 33, 2)])
+def test_convolve_parity(tc, orc, n, R_f, R_N):
+    say(f"convolve n={n} R_f={R_f} R_N={R_N}")
+    b = 6.0
+    h = 2 * b / n
+    u0, hu = wl.sinc_params(R_N, n, b)
+    U, _ = wl.gaussian_products(n, b, R_f, seed=n + R_f)
+    t, a, c, pr = orc.newton_kernel(n, h, R_N, u0, hu)
+    W = host(tc.convolve(dev(pr), dev(U[0])))
+    Wr = orc.convolve(pr, U[0])
+    bound = orc.convolve(np.abs(pr), np.abs(U[0]))
+    assert np.all(np.abs(W - Wr) <= 1e-13 * bound + 1e-300)
+
+
+def test_convolve_asymmetric_kernel_lag_direction(tc, orc):
+    """A non-symmetric p pins the lag direction W[a] = sum_b p[a-b] u[b]."""
+    say("convolve asymmetric p")
+    rng = np.random.default_rng(1)
+    n, R_f, R_N = 77, 19, 3
+    p = rng.standard_normal((R_N, 2 * n - 1))
+    U = rng.standard_normal((R_f, n))
+    W = host(tc.convolve(dev(p), dev(U)))
+    Wr = orc.convolve(p, U)
+    bound = orc.convolve(np.abs(p), np.abs(U))
+    assert np.all(np.abs(W - Wr) <= 1e-13 * bound)
+
+
+# --------------------------------------------------------------------------
+def _setup(orc, w):
+    ps = []
+    for l in range(3):
+        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
+        ps.append(p)
+    c = a * w.h[0] * w.h[1] * w.h[2]
+    return c, ps
+
+
+SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100, 100), 33, 7),
+         ((40, 33, 47), 9, 4), ((257, 257, 257), 70, 12), ((130, 64, 200), 65, 6)]
+
+
+@pytest.mark.parametrize("n,R_f,R_N", SMALL)
+def test_tei_gram_parity_small(tc, orc, n, R_f, R_N):
+    say(f"tei_gram n={n} R_f={R_f} R_N={R_N}")
+    w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=sum(n) + R_f)
+    c, ps = _setup(orc, w)
+    J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], save_G=True)
+    Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
+    J, G = host(J), host(G)
+    assert e_J(J, Jr) <= 1e-12
+    np.testing.assert_array_equal(J, J.T)
+    # each Gram entry within a rounding-error bound of the product U^T T U:
+    # |dG| <= 1e-13 |U|^T |T| |U| (p-type columns make G_ii much smaller than
+    # that bound for the wide kernel terms, so a G_ii-relative bound is wrong)
+    for l in range(3):
+        absG = orc.gram(np.abs(w.U[l]), orc.convolve(np.abs(ps[l]), np.abs(w.U[l])))
+        assert np.all(np.abs(G[l] - Gr[l]) <= 1e-13 * absG + 1e-300)
+
+
+def test_tei_gram_single_cell(tc, orc):
+    """n = 1 in every mode: each Gram is the single product u p[0] u."""
+    say("tei_gram single cell")
+    U, _ = wl.s_gaussians(1, 2.0, 3, alphas=[0.5, 1.0, 2.0], centres=np.zeros((3, 3)))
+    R_N = 5
+    t, a, cc, p = orc.newton_kernel(1, 4.0, R_N, -2.0, 0.7)
+    c = a * 4.0 ** 3
+    J = host(tc.tei_gram(dev(c), [dev(p)] * 3, [dev(u) for u in U]))
+    Jr = orc.tei_gram(c, [p] * 3, U)
+    assert e_J(J, Jr) <= 1e-14
+
+
+def test_tei_gram_parity_c1(tc, orc):
+    """The 128-cell, 8-function s-Gaussian workload, with its potential factors."""
+    say("tei_gram c1")
+    w = wl.config("c1")
+    c, ps = _setup(orc, w)
+    t, cg, pg = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu)
+    J = host(tc.tei_gram(torch.from_numpy(cg).cuda(), [pg, pg, pg], [dev(u) for u in w.U]))
+    Jr = orc.tei_gram(c, ps, w.U)
+    assert e_J(J, Jr) <= 1e-12
+    for l in range(3):
+        W = host(tc.convolve(pg, dev(w.U[l])))
+        Wr = orc.convolve(ps[l], w.U[l])
+        bound = orc.convolve(np.abs(ps[l]), np.abs(w.U[l]))
+        assert np.all(np.abs(W - Wr) <= 1e-13 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("name,ncols", [("c2", 12), ("c5", 6), ("c3", 4)])
+def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols):
+    """Full-size workloads: the GPU J (whole matrix) against oracle columns
+    on a seeded sample S; the S x S block is compared with the normalised
+    metric using oracle diagonals only."""
+    say(f"tei_gram sampled {name}")
+    w = wl.config(name)
+    c, ps = _setup(orc, w)
+    J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
+    rng = np.random.default_rng(123)
+    S = np.sort(rng.choice(w.R_f, size=ncols, replace=False))
+    Jc = orc.tei_gram_columns(c, ps, w.U, S)          # [ncols][R_f]
+    block = Jc[:, S]                                  # J[S_q, S_r] = Jc[r][S_q]
+    d = np.diag(block)
+    err = np.max(np.abs(J[np.ix_(S, S)] - block.T) / np.sqrt(np.outer(d, d)))
+    assert err <= 1e-12, err
+    # whole sampled columns, scaled by the GPU diagonal for rows outside S
+    dg = np.sqrt(np.abs(np.diag(J)))
+    err_cols = np.max(np.abs(J[:, S] - Jc.T) / np.outer(dg, np.sqrt(d)))
+    assert err_cols <= 1e-12, err_cols
+    # structure at full size
+    np.testing.assert_array_equal(J, J.T)
+    assert np.all(np.diag(J) > 0)
+
+
+def test_tei_gram_deterministic(tc, orc):
+    say("tei_gram determinism")
+    w = wl.small_products(300, 100, R_N=9, b=6.0, seed=4)
+    c, ps = _setup(orc, w)
+    args = (dev(c), [dev(p) for p in ps], [dev(u) for u in w.U])
+    J1 = host(tc.tei_gram(*args))
+    J2 = host(tc.tei_gram(*args))
+    np.testing.assert_array_equal(J1, J2)
+
+
+def test_tei_gram_batched_matches_single(tc, orc):
+    say("tei_gram batched vs single")
+    insts = []
+    for i, (n, R_f, R_N) in enumerate([(64, 10, 4), (130, 37, 6), (33, 5, 3)]):
+        w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=i)
+        c, ps = _setup(orc, w)
+        insts.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
+    Js = [host(J) for J in tc.tei_gram_batched(insts)]
+    for (c, ps, Us), Jb in zip(insts, Js):
+        np.testing.assert_array_equal(Jb, host(tc.tei_gram(c, ps, Us)))
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,R_f,R_N", [((24, 19, 28), 6, 6), ((100, 100, 100), 40, 5),
+                                       ((70, 130, 65), 67, 4)])
+def test_backward_parity(tc, orc, n, R_f, R_N):
+    say(f"backward n={n} R_f={R_f} R_N={R_N}")
+    w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
+    c, ps = _setup(orc, w)
+    rng = np.random.default_rng(5)
+    Jb = rng.standard_normal((R_f, R_f))
+    dUr = orc.tei_gram_backward(c, ps, w.U, Jb)
+    cd, pd, Ud = dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]
+    dU = tc.tei_gram_backward(cd, pd, Ud, dev(Jb))
+    for l in range(3):
+        assert rel_fro(host(dU[l]), dUr[l]) <= 1e-12
+    # with saved Grams
+    J, G = tc.tei_gram(cd, pd, Ud, save_G=True)
+    dU2 = tc.tei_gram_backward(cd, pd, Ud, dev(Jb), G=G)
+    for l in range(3):
+        assert rel_fro(host(dU2[l]), dUr[l]) <= 1e-12
+
+
+def test_autograd_function(tc, orc):
+    say("autograd TeiGram")
+    w = wl.small_products(90, 20, R_N=6, b=6.0, seed=3)
+    c, ps = _setup(orc, w)
+    rng = np.random.default_rng(8)
+    wv = rng.standard_normal(w.R_f)
+    Us = [dev(u).requires_grad_(True) for u in w.U]
+    J = tc.TeiGram.apply(dev(c), dev(ps[0]), dev(ps[1]), dev(ps[2]), *Us)
+    wt = dev(wv)
+    f = wt @ J @ wt
+    f.backward()
+    dUr = orc.tei_gram_backward(c, ps, w.U, np.outer(wv, wv))
+    for l in range(3):
+        assert rel_fro(host(Us[l].grad), dUr[l]) <= 1e-12
