@@ -6,7 +6,7 @@ G1_k o G2_k o G3_k (tc_tei_gram: Toeplitz products, Grams, Hadamard/sum over
 k), with the side matrices already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
-                    [--prec fp64|fp32|split3|auto] [--no-cpu-baseline]
+                    [--prec fp64|ozaki8] [--no-cpu-baseline]
 
 Prints ONE JSON line.  GFLOP/s counts the algorithmic flops of the
 Toeplitz-Gram method, F = sum_l R_N (2 n^2 R_f + 2 n R_f^2).
@@ -30,9 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # published MI355X peaks (dense), TFLOP/s
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "split3": "bf16"}
-PREC_PEAK = {"fp64": "fp64", "fp32": "fp32", "split3": "bf16"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "ozaki8": "i8"}
+PREC_PEAK = {"fp64": "fp64", "fp32": "fp32", "ozaki8": "int8"}
 WORKLOAD_DESC = {
     "c1": "128-cell grid on [-10,10]^3, R_N=20 sinc terms, R_f=8 s-Gaussians",
     "c2": "1024-cell grid on [-10,10]^3, R_N=30 sinc terms, R_f=256 s/p Gaussian products",

@@ -65,13 +65,15 @@ typedef enum {
 
 /* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions. */
 typedef enum {
-    TC_FP64 = 0,  /* binary64 matrix cores: error ~1e-15 relative           */
-    TC_FP32 = 1,  /* binary32 operands on matrix cores, binary32 partial sums
-                     over short K-chunks, binary64 accumulation across them  */
-    TC_SPLIT3 = 2 /* operands split into three bfloat16 slices with a common
-                     exponent per row/column, slice products accumulated
-                     exactly in binary32 within K-chunks, binary64 across
-                     them (an Ozaki-type error-free splitting)                */
+    TC_FP64 = 0,     /* binary64 matrix cores (v_mfma_f64_16x16x4)           */
+    TC_FP32 = 1,     /* operands rounded to binary32, binary32 matrix cores
+                        with binary32 partial sums over K-chunks of 64 and
+                        binary64 accumulation across chunks                   */
+    TC_OZAKI_I8 = 2  /* error-free splitting of each operand into four int8
+                        slices with one exponent per row (28 bits relative to
+                        the row maximum), the ten leading slice products on
+                        int8 matrix cores with exact int32 accumulation, and
+                        binary64 recombination (Ozaki scheme)                 */
 } tc_precision;
 
 /* Largest supported sizes (guards for index arithmetic). */

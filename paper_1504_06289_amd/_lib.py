@@ -19,8 +19,8 @@ TC_ERR_HIP = 4
 
 TC_FP64 = 0
 TC_FP32 = 1
-TC_SPLIT3 = 2
-PRECISIONS = {"fp64": TC_FP64, "fp32": TC_FP32, "split3": TC_SPLIT3}
+TC_OZAKI_I8 = 2
+PRECISIONS = {"fp64": TC_FP64, "fp32": TC_FP32, "ozaki8": TC_OZAKI_I8}
 
 TC_OP_CONVOLVE = 0
 TC_OP_TEI_GRAM = 1

@@ -1,0 +1,460 @@
+// Error-free int8 splitting (Ozaki scheme on integer matrix cores) for the
+// Toeplitz products and the Grams.
+//
+// Splitting.  Each row r of an operand gets one exponent E_r chosen so that
+// max_b |x_rb| 2^-E_r lies in [63.5, 127]; every entry is then written as
+//   x = 2^E_r (s1 + s2 2^-7 + s3 2^-14 + s4 2^-21) + residual,
+// s1 in [-127, 127], s2..s4 in [-64, 64] (each a rounding of the scaled
+// residual), |residual| <= 2^(E_r - 22), i.e. 28 bits relative to the row
+// maximum.  Every step of the split is exact in binary64.
+//
+// Products.  With A = 2^Ea sum_i a_i 2^-7(i-1) and B likewise, the slice
+// products a_i b_j with i + j <= 5 (ten of them) are summed on
+// v_mfma_i32_16x16x64_i8 into four int32 accumulators, one per d = i+j-2
+// (all pairs with equal d share the scale 2^-7d).  Integer accumulation is
+// exact: |acc_d| <= 24448 K < 2^31 for K <= 65536.  The binary64 result is
+//   2^(Ea+Eb) (acc_0 + acc_1 2^-7 + acc_2 2^-14 + acc_3 2^-21).
+//
+// The Toeplitz operand keeps the implicit form: the kernel vector p_k is
+// split once with one exponent per term (its maximum, p_k[0], appears in
+// every row of T_k), stored lag-reversed, and each K-step stages the
+// contiguous window of lags the tile needs; a lane's 16-byte B-fragment is a
+// byte-shifted run of that window, assembled with v_alignbyte_b32 from
+// dword-aligned LDS reads.
+//
+// v_mfma_i32_16x16x64_i8: lane l supplies A[l%16][k in 16(l/16)+0..15] and
+// B[k in 16(l/16)+0..15][l%16] (any k order works as long as A and B agree),
+// and receives D[4(l/16)+r][l%16], r = 0..3.
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// splitting
+// ---------------------------------------------------------------------------
+__device__ inline int row_exponent(double amax)
+{
+    if (!(amax > 0.0))
+        return 0;
+    int E = ilogb(amax) - 6;  // amax 2^-E in [64, 128)
+    if (ldexp(amax, -E) > 127.0)
+        ++E;  // then in [63.5, 64)
+    return E;
+}
+
+__device__ inline void split4(double x, int E, int8_t s[4])
+{
+    double y = ldexp(x, -E);
+    double q = rint(y);
+    s[0] = (int8_t)q;
+    y = (y - q) * 128.0;
+    q = rint(y);
+    s[1] = (int8_t)q;
+    y = (y - q) * 128.0;
+    q = rint(y);
+    s[2] = (int8_t)q;
+    y = (y - q) * 128.0;
+    q = rint(y);
+    s[3] = (int8_t)q;
+}
+
+__device__ inline double block_max_abs(double v, double *red)
+{
+    // 256 threads
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return v;
+}
+
+// Rows of a [groups][rows][len] FP64 array (row stride len) -> slices
+// S[4][groups][rows_pad][len_pad] int8 and exponents E[groups][rows_pad].
+// One workgroup per output row; rows >= rows and columns >= len are zero.
+__global__ __launch_bounds__(256) void split_rows_kernel(const double *__restrict__ X, int rows,
+                                                         int len, int rows_pad, int len_pad,
+                                                         long plane, int8_t *__restrict__ S,
+                                                         int *__restrict__ E)
+{
+    __shared__ double red[4];
+    const int grp = blockIdx.y;
+    const int r = blockIdx.x;  // < rows_pad
+    const long orow = (long)grp * rows_pad + r;
+    int8_t *s0 = S + orow * len_pad;
+    if (r >= rows) {
+        for (int b = threadIdx.x; b < len_pad; b += 256)
+            for (int q = 0; q < 4; ++q)
+                s0[q * plane + b] = 0;
+        if (threadIdx.x == 0)
+            E[orow] = 0;
+        return;
+    }
+    const double *x = X + ((long)grp * rows + r) * len;
+    double m = 0.0;
+    for (int b = threadIdx.x; b < len; b += 256)
+        m = fmax(m, fabs(x[b]));
+    m = block_max_abs(m, red);
+    const int e = row_exponent(m);
+    if (threadIdx.x == 0)
+        E[orow] = e;
+    for (int b = threadIdx.x; b < len_pad; b += 256) {
+        int8_t s[4] = {0, 0, 0, 0};
+        if (b < len)
+            split4(x[b], e, s);
+        for (int q = 0; q < 4; ++q)
+            s0[q * plane + b] = s[q];
+    }
+}
+
+// Kernel vectors p [R_N][2n-1] -> lag-reversed slices PS[4][R_N][LP] with
+// PS[.][k][x] holding lag m = (n-1) + off - x, off = ozaki_p_offset(n), zero
+// outside the lag range; exponents EP[R_N].  One workgroup per term.
+__global__ __launch_bounds__(256) void split_kernel_vectors(const double *__restrict__ p, int n,
+                                                            int LP, int off, long plane,
+                                                            int8_t *__restrict__ PS,
+                                                            int *__restrict__ EP)
+{
+    __shared__ double red[4];
+    const int k = blockIdx.x;
+    const long L = 2L * n - 1;
+    const double *pk = p + k * L;  // pk[m + n - 1]
+    double m = 0.0;
+    for (long i = threadIdx.x; i < L; i += 256)
+        m = fmax(m, fabs(pk[i]));
+    m = block_max_abs(m, red);
+    const int e = row_exponent(m);
+    if (threadIdx.x == 0)
+        EP[k] = e;
+    int8_t *out = PS + (long)k * LP;
+    for (int x = threadIdx.x; x < LP; x += 256) {
+        const long lag = (long)(n - 1) + off - x;
+        int8_t s[4] = {0, 0, 0, 0};
+        if (lag > -n && lag < n)
+            split4(pk[lag + n - 1], e, s);
+        for (int q = 0; q < 4; ++q)
+            out[q * plane + x] = s[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// implicit-Toeplitz product on int8 matrix cores
+//   W[k][j][a] = sum_b U[j][b] p_k[a-b]
+// Workgroup tile 64 (j) x 128 (a), K-step 64; waves 2 x 2 with 32 x 64 wave
+// tiles (2 x 4 MFMA blocks, four int32 accumulators each).
+// ---------------------------------------------------------------------------
+constexpr int TJ = 64, TA = 128, TK = 64;
+constexpr int AROW = 80;                  // LDS row stride (bytes): conflict-free b128 reads
+constexpr int WLEN = 256;                 // window bytes per slice (>= TA + TK - 1 + 16)
+constexpr int A_BYTES = 4 * TJ * AROW;    // 20480
+constexpr int W_BYTES = 4 * WLEN;         // 1024
+
+__device__ inline double combine(const v4i *acc, int r, int E)
+{
+    // sum from the smallest scale up; each term is exact
+    double v = ldexp((double)acc[3][r], -21);
+    v += ldexp((double)acc[2][r], -14);
+    v += ldexp((double)acc[1][r], -7);
+    v += (double)acc[0][r];
+    return ldexp(v, E);
+}
+
+__global__ __launch_bounds__(256) void toeplitz_i8_kernel(
+    const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane, int n_pad,
+    const int8_t *__restrict__ PS, const int *__restrict__ EP, long pplane, int LP, int off,
+    double *__restrict__ W, int n, int R_f)
+{
+    __shared__ __attribute__((aligned(16))) int8_t As[A_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Pw[W_BYTES];
+
+    const int k = blockIdx.z;
+    const int a0 = blockIdx.x * TA;
+    const int j0 = blockIdx.y * TJ;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wj = (wave >> 1) * 32, wa = (wave & 1) * 64;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    // reversed-window start for K-step b0: x = off + n - TA - a0 + b0 (16-aligned)
+    const long xs0 = (long)off + n - TA - a0;
+    const int8_t *pk = PS + (long)k * LP;
+
+    // staging registers: A = 1024 chunks of 16 B (4 per thread); window 4 x 16 chunks
+    v4i areg[4];
+    v4i preg;
+    auto load_stage = [&](int b0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q;  // slice = c/256, row = (c%256)/4, col16 = c%4
+            const int sl = c >> 8, row = (c & 255) >> 2, c16 = c & 3;
+            areg[q] = *reinterpret_cast<const v4i *>(US + sl * uplane + (long)(j0 + row) * n_pad +
+                                                     b0 + 16 * c16);
+        }
+        if (tid < 64) {
+            const int sl = tid >> 4, c16 = tid & 15;
+            preg = *reinterpret_cast<const v4i *>(pk + sl * pplane + xs0 + b0 + 16 * c16);
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q;
+            const int sl = c >> 8, row = (c & 255) >> 2, c16 = c & 3;
+            *reinterpret_cast<v4i *>(As + sl * (TJ * AROW) + row * AROW + 16 * c16) = areg[q];
+        }
+        if (tid < 64) {
+            const int sl = tid >> 4, c16 = tid & 15;
+            *reinterpret_cast<v4i *>(Pw + sl * WLEN + 16 * c16) = preg;
+        }
+    };
+
+    v4i acc[2][4][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                acc[x][y][d] = v4i{0, 0, 0, 0};
+
+    // window offsets of this lane: frag y starts at o_y = o3 + 16 (3 - y)
+    const int o3 = TA - 1 - wa - l16 + 16 * g - 48;  // >= 0
+    const int dw0 = o3 >> 2, sh = o3 & 3;
+
+    const int nsteps = n_pad / TK;
+    load_stage(0);
+    for (int s = 0; s < nsteps; ++s) {
+        __syncthreads();  // previous compute done before overwriting LDS
+        store_stage();
+        __syncthreads();
+        if (s + 1 < nsteps)
+            load_stage((s + 1) * TK);
+
+        v4i afr[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl)
+                afr[x][sl] = *reinterpret_cast<const v4i *>(
+                    As + sl * (TJ * AROW) + (wj + 16 * x + l16) * AROW + 16 * g);
+
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+            const unsigned *w32 = reinterpret_cast<const unsigned *>(Pw + sl * WLEN);
+            unsigned dw[17];
+#pragma unroll
+            for (int i = 0; i < 17; ++i)
+                dw[i] = w32[dw0 + i];
+            v4i bfr[4];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int base = 4 * (3 - y);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    bfr[y][q] = (int)__builtin_amdgcn_alignbyte(dw[base + q + 1], dw[base + q],
+                                                                (unsigned)sh);
+            }
+            // slice sl of B pairs with A slices i such that i + sl <= 3
+#pragma unroll
+            for (int i = 0; i + sl <= 3; ++i)
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y][i + sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            afr[x][i], bfr[y], acc[x][y][i + sl], 0, 0, 0);
+        }
+    }
+
+    const int Ep = EP[k];
+    double *Wk = W + (long)k * R_f * n;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = j0 + wj + 16 * x + 4 * g + r;
+            if (j >= R_f)
+                continue;
+            const int Ej = EU[j] + Ep;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int a = a0 + wa + 16 * y + l16;
+                if (a < n)
+                    Wk[(long)j * n + a] = combine(acc[x][y], r, Ej);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grams on int8 matrix cores: G[k][i][j] = sum_a U[i][a] W[k][j][a]
+// Upper-triangle 64 x 64 tiles, waves 2 x 2 of 32 x 32, K-step 64.
+// ---------------------------------------------------------------------------
+constexpr int GT = 64;
+constexpr int G_BYTES = 4 * GT * AROW;  // 20480 per operand
+
+__global__ __launch_bounds__(256) void gram_i8_kernel(
+    const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
+    const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
+    int R_f_pad, double *__restrict__ G, int R_f, int ntiles)
+{
+    __shared__ __attribute__((aligned(16))) int8_t As[G_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[G_BYTES];
+
+    int t = blockIdx.x;
+    int ti = 0;
+    while (t >= ntiles - ti) {
+        t -= ntiles - ti;
+        ++ti;
+    }
+    const int tj = ti + t;
+    const int k = blockIdx.y;
+    const int i0 = ti * GT, j0 = tj * GT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int8_t *Wk = WS + (long)k * R_f_pad * n_pad;
+
+    v4i areg[4], breg[4];
+    auto load_stage = [&](int a0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q;
+            const int sl = c >> 8, row = (c & 255) >> 2, c16 = c & 3;
+            areg[q] = *reinterpret_cast<const v4i *>(US + sl * uplane + (long)(i0 + row) * n_pad +
+                                                     a0 + 16 * c16);
+            breg[q] = *reinterpret_cast<const v4i *>(Wk + sl * wplane + (long)(j0 + row) * n_pad +
+                                                     a0 + 16 * c16);
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 256 * q;
+            const int sl = c >> 8, row = (c & 255) >> 2, c16 = c & 3;
+            const int o = sl * (GT * AROW) + row * AROW + 16 * c16;
+            *reinterpret_cast<v4i *>(As + o) = areg[q];
+            *reinterpret_cast<v4i *>(Bs + o) = breg[q];
+        }
+    };
+
+    v4i acc[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                acc[x][y][d] = v4i{0, 0, 0, 0};
+
+    const int nsteps = n_pad / TK;
+    load_stage(0);
+    for (int s = 0; s < nsteps; ++s) {
+        __syncthreads();
+        store_stage();
+        __syncthreads();
+        if (s + 1 < nsteps)
+            load_stage((s + 1) * TK);
+        v4i afr[2][4], bfr[2][4];
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                afr[x][sl] = *reinterpret_cast<const v4i *>(
+                    As + sl * (GT * AROW) + (wi + 16 * x + l16) * AROW + 16 * g);
+                bfr[x][sl] = *reinterpret_cast<const v4i *>(
+                    Bs + sl * (GT * AROW) + (wj + 16 * x + l16) * AROW + 16 * g);
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; i + j <= 3; ++j)
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        acc[x][y][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            afr[x][i], bfr[y][j], acc[x][y][i + j], 0, 0, 0);
+    }
+
+    double *Gk = G + (long)k * R_f * R_f;
+    const int *EWk = EW + (long)k * R_f_pad;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + wi + 16 * x + 4 * g + r;
+            if (i >= R_f)
+                continue;
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int j = j0 + wj + 16 * y + l16;
+                if (j < R_f && i <= j) {
+                    const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
+                    Gk[(long)i * R_f + j] = v;
+                    Gk[(long)j * R_f + i] = v;
+                }
+            }
+        }
+}
+
+}  // namespace
+
+OzakiLayout ozaki_layout(int n, int R_f, int R_N)
+{
+    OzakiLayout L;
+    L.n_pad = (n + TA - 1) / TA * TA;  // multiple of both TA and TK
+    L.R_f_pad = (R_f + TJ - 1) / TJ * TJ;
+    L.off = ozaki_p_offset(n);
+    L.LP = ((2 * n - 1 + 2 * kOzakiPad + 16) + 15) / 16 * 16;
+    L.uplane = (long)L.R_f_pad * L.n_pad;
+    L.pplane = (long)R_N * L.LP;
+    L.wplane = (long)R_N * L.R_f_pad * L.n_pad;
+    return L;
+}
+
+hipError_t launch_split_rows(const double *X, int groups, int rows, int len, int rows_pad,
+                             int len_pad, long plane, int8_t *S, int *E, hipStream_t stream)
+{
+    hipLaunchKernelGGL(split_rows_kernel, dim3(rows_pad, groups), dim3(256), 0, stream, X, rows,
+                       len, rows_pad, len_pad, plane, S, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_kernel_vectors(const double *p, int n, int R_N, const OzakiLayout &L,
+                                       int8_t *PS, int *EP, hipStream_t stream)
+{
+    hipLaunchKernelGGL(split_kernel_vectors, dim3(R_N), dim3(256), 0, stream, p, n, L.LP, L.off,
+                       L.pplane, PS, EP);
+    return hipGetLastError();
+}
+
+hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS, const int *EP,
+                              const OzakiLayout &L, double *W, int n, int R_f, int R_N,
+                              hipStream_t stream)
+{
+    dim3 grid(L.n_pad / TA, L.R_f_pad / TJ, R_N);
+    hipLaunchKernelGGL(toeplitz_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, L.n_pad,
+                       PS, EP, L.pplane, L.LP, L.off, W, n, R_f);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
+                          const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream)
+{
+    const int nt = L.R_f_pad / GT;
+    dim3 grid(nt * (nt + 1) / 2, R_N);
+    hipLaunchKernelGGL(gram_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, WS, EW,
+                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt);
+    return hipGetLastError();
+}
+
+}  // namespace tc

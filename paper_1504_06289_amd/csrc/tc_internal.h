@@ -40,4 +40,37 @@ hipError_t launch_adjoint_d(const double *c, const double *Jbar, const double *G
 hipError_t launch_adjoint_gemm_f64(const double *D, const double *W, double *dU, int n,
                                    int R_f, int R_N, double scale, hipStream_t stream);
 
+
+// ---- int8 error-free splitting path (ozaki.hip) ---------------------------
+// Zero padding (bytes) in front of and behind the lag-reversed kernel slices.
+constexpr int kOzakiPad = 256;
+// Offset that makes every staged window of the lag-reversed slices 16-byte
+// aligned: PS[.][k][x] holds lag (n-1) + off - x.
+inline int ozaki_p_offset(int n) { return kOzakiPad + ((16 - n % 16) % 16); }
+
+struct OzakiLayout {
+    int n_pad;     // cells padded to the tile multiple (128)
+    int R_f_pad;   // functions padded to the tile multiple (64)
+    int off;       // ozaki_p_offset(n)
+    int LP;        // bytes per term of the kernel slices
+    long uplane;   // bytes per slice plane of the U slices  (R_f_pad * n_pad)
+    long pplane;   // bytes per slice plane of the p slices  (R_N * LP)
+    long wplane;   // bytes per slice plane of the W slices  (R_N * R_f_pad * n_pad)
+};
+OzakiLayout ozaki_layout(int n, int R_f, int R_N);
+
+// rows of X [groups][rows][len] -> S [4][groups][rows_pad][len_pad], E [groups][rows_pad]
+hipError_t launch_split_rows(const double *X, int groups, int rows, int len, int rows_pad,
+                             int len_pad, long plane, int8_t *S, int *E, hipStream_t stream);
+// p [R_N][2n-1] -> lag-reversed slices PS [4][R_N][LP], EP [R_N]
+hipError_t launch_split_kernel_vectors(const double *p, int n, int R_N, const OzakiLayout &L,
+                                       int8_t *PS, int *EP, hipStream_t stream);
+// W[k][j][a] = sum_b U[j][b] p_k[a-b] from the slices (binary64 output)
+hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS, const int *EP,
+                              const OzakiLayout &L, double *W, int n, int R_f, int R_N,
+                              hipStream_t stream);
+// G[k][i][j] = sum_a U[i][a] W[k][j][a] from the slices (binary64, symmetric)
+hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
+                          const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream);
+
 }  // namespace tc
