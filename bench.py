@@ -2,19 +2,23 @@
 
 A step is one pass of the hot path over the workload: the canonical Newton
 kernel (tc_newton_kernel) and the TEI/Coulomb matrix J = sum_k c_k
-G1_k o G2_k o G3_k (tc_tei_gram: Toeplitz products, Grams, Hadamard/sum over
-k), with the side matrices already resident in HBM.
+G1_k o G2_k o G3_k (tc_tei_gram: Toeplitz products or FFT convolutions,
+Grams, Hadamard/sum over k), with the side matrices already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
-                    [--prec fp64|ozaki8] [--no-cpu-baseline]
+                    [--prec ozaki8|fp64] [--no-cpu-baseline] [--no-extra]
 
-Prints ONE JSON line.  GFLOP/s counts the algorithmic flops of the
-Toeplitz-Gram method, F = sum_l R_N (2 n^2 R_f + 2 n R_f^2).
-The roofline entry is for the dominant kernel (the implicit-Toeplitz
-product): its launch (one mode, all R_N terms) is timed with HIP events on
-the stream it runs on, and compared with the matrix-core peak of its dtype.
-The cpu_baseline entry times the FP64 oracle on a bounded sample of the same
-workload (a few columns of J) on this host's cores.
+Prints ONE JSON line.
+  value       F / t, F = sum_l R_N (2 n^2 R_f + 2 n R_f^2): the algorithmic
+              flops of the Toeplitz-Gram method (the same F for every route,
+              so the FFT route shows as a higher rate of the same work).
+  routes      ms per step of each (precision, Toeplitz algorithm) pair.
+  roofline    the dominant kernel of the headline route, timed per launch with
+              HIP events recorded by the library on the launch stream
+              (tc_profile_*), against the peak of its arithmetic or of HBM.
+  rows        the adjoint (2048 cells, R_f=512, forward + backward of w^T J w)
+              and the 64-instance batched workload, per-step times.
+  cpu_baseline  the FP64 oracle on a bounded sample (columns of J).
 """
 from __future__ import annotations
 
@@ -29,10 +33,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# published MI355X peaks (dense), TFLOP/s
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}
-PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "ozaki8": "i8"}
-PREC_PEAK = {"fp64": "fp64", "fp32": "fp32", "ozaki8": "int8"}
+# published MI355X dense peaks
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}  # TFLOP/s (TOP/s)
+HBM_GBS = 8000.0
+PREC_DTYPE = {"fp64": "f64", "ozaki8": "i8"}
 WORKLOAD_DESC = {
     "c1": "128-cell grid on [-10,10]^3, R_N=20 sinc terms, R_f=8 s-Gaussians",
     "c2": "1024-cell grid on [-10,10]^3, R_N=30 sinc terms, R_f=256 s/p Gaussian products",
@@ -47,14 +51,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--prec", default="fp64")
+    ap.add_argument("--prec", default="ozaki8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the route comparison and the adjoint/batched rows")
     ap.add_argument("--cpu-cols", type=int, default=0,
                     help="columns of J in the oracle sample (0 = size for ~15 s)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the benchmark, run one device-to-device copy of MIB MiB (a "
+                         "plain copy kernel of known size, used to scale HBM byte counters)")
     return ap.parse_args()
 
 
-def timed_steps(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -70,7 +79,7 @@ def timed_steps(fn, steps, warmup, torch):
 
 def cpu_baseline(w, cols_req):
     from oracle import oracle
-    c, ps = None, []
+    ps = []
     for l in range(3):
         t, a, cc, p = oracle.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
         ps.append(p)
@@ -79,7 +88,6 @@ def cpu_baseline(w, cols_req):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rng = np.random.default_rng(0)
     if cols_req <= 0:
-        # calibrate on one column, then size the sample for ~15 s
         t0 = time.perf_counter()
         oracle.tei_gram_columns(c, ps, w.U, [0])
         dt = time.perf_counter() - t0
@@ -89,11 +97,49 @@ def cpu_baseline(w, cols_req):
     oracle.tei_gram_columns(c, ps, w.U, cols)
     dt = time.perf_counter() - t0
     flops = per_col * len(cols)
-    return {
-        "value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-        "sample": (f"{len(cols)} of {w.R_f} columns of J ({flops:.3g} algorithmic flops, "
-                   f"{dt:.1f} s), compensated FP64 oracle"),
-    }
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{len(cols)} of {w.R_f} columns of J ({flops:.3g} algorithmic flops, "
+                       f"{dt:.1f} s), compensated FP64 oracle")}
+
+
+def kernel_roofline(name, per_launch_ms, w, prec):
+    """Algorithmic work of one launch of `name` on workload w (one mode, all
+    terms) and the matching roofline."""
+    n, R_f, R_N = w.n[0], w.R_f, w.R_N
+    s = per_launch_ms * 1e-3
+    if name in ("gram_i8", "gram_f64"):
+        flops = 2.0 * n * R_f * R_f * R_N            # U^T W_k for every k
+        out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s",
+               "peak": PEAK["int8" if name == "gram_i8" else "fp64"],
+               "work": f"2 n R_f^2 R_N = {flops:.4g} flops per launch"}
+        if name == "gram_i8":
+            # executed: 10 slice products, upper-triangle tiles only
+            ex = 10 * flops / 2.0
+            out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"]}
+    elif name in ("toeplitz_i8", "toeplitz_f64"):
+        flops = 2.0 * n * n * R_f * R_N
+        out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s",
+               "peak": PEAK["int8" if name == "toeplitz_i8" else "fp64"],
+               "work": f"2 n^2 R_f R_N = {flops:.4g} flops per launch"}
+        if name == "toeplitz_i8":
+            ex = 10 * flops
+            out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"]}
+    elif name in ("fft_conv", "fft_conv_split"):
+        M = 1
+        while 2 * M < 2 * n - 1:
+            M *= 2
+        out_bytes = (4 if name == "fft_conv_split" else 8) * R_N * R_f * n
+        in_bytes = 16 * (M + 1) * (R_f + R_N)
+        byts = out_bytes + in_bytes
+        out = {"bound": "hbm", "achieved": byts / s / 1e9, "unit": "GB/s", "peak": HBM_GBS,
+               "work": f"W written once + spectra read once = {byts:.4g} bytes per launch"}
+    else:
+        return None
+    out["frac"] = out["achieved"] / out["peak"]
+    out["kernel"] = name
+    out["kernel_ms"] = per_launch_ms
+    out["traffic"] = None
+    return out
 
 
 def main():
@@ -108,31 +154,41 @@ def main():
     from paper_1504_06289_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = wl.config(args.workload)
     dev = torch.device("cuda:0")
+    w = wl.config(args.workload)
     U = [torch.from_numpy(u).to(dev) for u in w.U]
-    prec = args.prec
     F = w.flops()
+    shapes = sorted(set((nl, w.R_f, w.R_N) for nl in w.n))
 
-    # kernel vectors per mode (equal h in all modes -> one set, aliased)
-    state = {}
-
-    def step(prec=prec):
+    def step(prec):
         t, c, p = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu, device=dev)
-        cd = torch.from_numpy(c).to(dev, non_blocking=False)
-        state["J"] = tc.tei_gram(cd, [p, p, p], U, prec=prec)
+        cd = torch.from_numpy(c).to(dev)
+        return tc.tei_gram(cd, [p, p, p], U, prec=prec)
 
-    ms = timed_steps(step, args.steps, args.warmup, torch)
+    def with_algo(prec, algo, fn):
+        for s in shapes:
+            tc.tune_set(*s, prec, algo)
+        try:
+            return fn()
+        finally:
+            for s in shapes:
+                tc.tune_set(*s, prec, "auto")
+
+    # headline: the chosen precision, algorithm picked by the autotuner
+    t, c, p = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu, device=dev)
+    tuned = tc.autotune(torch.from_numpy(c).to(dev), [p, p, p], U, prec=args.prec)
+    ms = timed(lambda: step(args.prec), args.steps, args.warmup, torch)
     value = F / (ms * 1e-3) / 1e9
 
-    # dominant kernel: one implicit-Toeplitz launch (one mode, all R_N terms)
-    t, c, p = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu, device=dev)
-    Wbuf = torch.empty((w.R_N, w.R_f, w.n[0]), dtype=torch.float64, device=dev)
-    ms_toep = timed_steps(lambda: tc.convolve(p, U[0], prec=prec, out=Wbuf),
-                          max(args.steps, 5), 2, torch)
-    toep_flops = 2.0 * w.n[0] * w.n[0] * w.R_f * w.R_N
-    achieved = toep_flops / (ms_toep * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[PREC_PEAK[prec]]
+    # per-kernel times of one step (library-recorded HIP events)
+    tc.profile_enable(True)
+    step(args.prec)
+    prof = tc.profile_read()
+    tc.profile_enable(False)
+    kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1]} for k, v in prof.items()}
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    roof = kernel_roofline(dom[0], dom[1][0] / dom[1][1], w, args.prec)
+
     out = {
         "metric": "TEI Gram assembly GFLOP/s (mixed vs FP64, normalised error <= 1e-7)",
         "value": round(value, 3),
@@ -144,19 +200,77 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": PREC_DTYPE[prec],
+        "dtype": PREC_DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
-                   "n": w.n[0], "R_N": w.R_N, "R_f": w.R_f, "precision": prec,
+                   "n": w.n[0], "R_N": w.R_N, "R_f": w.R_f, "precision": args.prec,
+                   "algorithm": tc.tune_get(w.n[0], w.R_f, w.R_N, args.prec),
                    "flops_per_step": F},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "toeplitz (W = T_k U, one mode, all terms)",
-                     "kernel_ms": round(ms_toep, 4)},
+        "roofline": roof,
+        "kernels_one_step": kernels,
+        "autotune_ms_per_mode": {"direct": round(tuned[0][0], 4), "fft": round(tuned[0][1], 4)},
     }
+    for s in shapes:
+        tc.tune_set(*s, args.prec, "auto")
+
+    if not args.no_extra:
+        routes = {}
+        for prec in ("fp64", "ozaki8"):
+            for algo in ("direct", "fft"):
+                k = max(2, args.steps // 3)
+                routes[f"{prec}/{algo}"] = round(
+                    with_algo(prec, algo, lambda: timed(lambda: step(prec), k, 1, torch)), 4)
+        out["routes_ms_per_step"] = routes
+        best64 = min(routes["fp64/direct"], routes["fp64/fft"])
+        out["speedup_mixed_vs_fp64"] = {
+            "direct": round(routes["fp64/direct"] / routes["ozaki8/direct"], 3),
+            "best_route": round(best64 / min(routes["ozaki8/direct"], routes["ozaki8/fft"]), 3)}
+        out["rows"] = extra_rows(tc, wl, torch, dev, args)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_cols)
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+
+def extra_rows(tc, wl, torch, dev, args):
+    rows = {}
+    # adjoint: forward (Grams saved) + backward of f = w^T J w, 2048 cells, R_f = 512
+    w5 = wl.config("c5")
+    U5 = [torch.from_numpy(u).to(dev) for u in w5.U]
+    t, c, p = tc.newton_kernel(w5.n[0], w5.h[0], w5.R_N, w5.u0, w5.hu, device=dev)
+    cd = torch.from_numpy(c).to(dev)
+    wv = torch.from_numpy(w5.meta["w"]).to(dev)
+    Jbar = torch.outer(wv, wv).contiguous()
+    for prec in ("fp64", "ozaki8"):
+        def fb():
+            J, G = tc.tei_gram(cd, [p, p, p], U5, prec=prec, save_G=True)
+            return tc.tei_gram_backward(cd, [p, p, p], U5, Jbar, G=G, prec=prec)
+        rows[f"adjoint_c5_{prec}_ms"] = round(timed(fb, 3, 1, torch), 4)
+    # batched: 64 independent instances in one call
+    insts = wl.batched_instances(64, seed=0)
+    kern = {}
+    batch = []
+    for wi in insts:
+        key = wi.n[0]
+        if key not in kern:
+            t, c, p = tc.newton_kernel(wi.n[0], wi.h[0], wi.R_N, wi.u0, wi.hu, device=dev)
+            kern[key] = (torch.from_numpy(c).to(dev), p)
+        c, p = kern[key]
+        batch.append((c, [p, p, p], [torch.from_numpy(u).to(dev) for u in wi.U]))
+    Fb = sum(wi.flops() for wi in insts)
+    for prec in ("fp64", "ozaki8"):
+        msb = timed(lambda: tc.tei_gram_batched(batch, prec=prec), 2, 1, torch)
+        rows[f"batched_c4_{prec}_ms"] = round(msb, 3)
+        rows[f"batched_c4_{prec}_GFLOPs"] = round(Fb / (msb * 1e-3) / 1e9, 1)
+    rows["batched_c4_flops"] = Fb
+    return rows
 
 
 if __name__ == "__main__":

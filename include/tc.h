@@ -76,6 +76,18 @@ typedef enum {
                         binary64 recombination (Ozaki scheme)                 */
 } tc_precision;
 
+/* How the Toeplitz products W_k = T_k U are formed.  TC_ALGO_DIRECT: the
+ * implicit-Toeplitz matrix-core product in the arithmetic selected by
+ * tc_precision.  TC_ALGO_FFT: aperiodic convolution through a circulant
+ * embedding of length N >= 2n-1 with binary64 FFTs (n <= 4096); the Grams then
+ * use the tc_precision arithmetic.  TC_ALGO_AUTO: the entry of the tuning
+ * table for the mode's (n, R_f, R_N, precision), else a built-in rule. */
+typedef enum {
+    TC_ALGO_AUTO = 0,
+    TC_ALGO_DIRECT = 1,
+    TC_ALGO_FFT = 2
+} tc_algorithm;
+
 /* Largest supported sizes (guards for index arithmetic). */
 #define TC_MAX_N 65536
 #define TC_MAX_RF 65536
@@ -166,6 +178,41 @@ tc_status tc_tei_gram_backward(const tc_instance *inst, int count,
  */
 size_t tc_workspace_bytes(int op, const tc_instance *inst, int count,
                           tc_precision prec);
+
+/*
+ * Tuning table (process-wide, thread-safe): the algorithm TC_ALGO_AUTO uses
+ * for a mode of n cells with R_f functions and R_N terms at precision prec.
+ * tc_tune_set with TC_ALGO_AUTO removes the entry.  tc_tune_get returns the
+ * algorithm a call would use now (the table entry or the built-in rule).
+ */
+tc_status tc_tune_set(int n, int R_f, int R_N, tc_precision prec, tc_algorithm algo);
+tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec);
+
+/*
+ * tc_autotune -- measure every algorithm available for each distinct mode
+ * shape of the instances (one warm-up and three timed runs of the mode's
+ * Toeplitz products and Grams, HIP events on `stream`) and record the fastest
+ * in the tuning table.  Unlike every other call it synchronises `stream`.
+ * Writes scratch data into the workspace (tc_workspace_bytes(TC_OP_TEI_GRAM,
+ * ...)) and leaves inst[i].J untouched.  ms_out (host, may be NULL) receives
+ * 2 entries per instance and mode: [ (i*3 + l)*2 + a ] = milliseconds of
+ * algorithm a (0 = direct, 1 = FFT; negative if unavailable).
+ */
+tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, void *ws,
+                      size_t ws_bytes, void *stream, double *ms_out);
+
+/*
+ * Kernel timing (diagnostics).  tc_profile_enable(1) makes every kernel
+ * launch of the library record a pair of HIP events on its stream (events
+ * are created on demand, so do not enable it during graph capture).
+ * tc_profile_read synchronises the recorded events, writes up to
+ * max_kernels entries (kernel name, total milliseconds, number of launches)
+ * accumulated since the previous read, clears them, and returns the number
+ * of distinct kernels (or -1 if an event query failed).  Any output pointer
+ * may be NULL.
+ */
+tc_status tc_profile_enable(int on);
+int tc_profile_read(int max_kernels, char (*names)[64], double *total_ms, long *calls);
 
 /* Static description of a status code (never NULL). */
 const char *tc_status_string(tc_status s);

@@ -28,7 +28,13 @@ TC_OP_TEI_GRAM_BACKWARD = 2
 
 # the ABI symbols declared in include/tc.h
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
-           "tc_workspace_bytes", "tc_status_string", "tc_version")
+           "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
+           "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read")
+
+TC_ALGO_AUTO = 0
+TC_ALGO_DIRECT = 1
+TC_ALGO_FFT = 2
+ALGORITHMS = {"auto": TC_ALGO_AUTO, "direct": TC_ALGO_DIRECT, "fft": TC_ALGO_FFT}
 
 
 class TcInstance(ctypes.Structure):
@@ -83,6 +89,18 @@ def lib() -> ctypes.CDLL:
         L.tc_status_string.restype = ctypes.c_char_p
         L.tc_version.argtypes = []
         L.tc_version.restype = ctypes.c_int
+        L.tc_tune_set.argtypes = [ctypes.c_int] * 5
+        L.tc_tune_set.restype = ctypes.c_int
+        L.tc_tune_get.argtypes = [ctypes.c_int] * 4
+        L.tc_tune_get.restype = ctypes.c_int
+        L.tc_autotune.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int, vp,
+                                  ctypes.c_size_t, vp, pd]
+        L.tc_autotune.restype = ctypes.c_int
+        L.tc_profile_enable.argtypes = [ctypes.c_int]
+        L.tc_profile_enable.restype = ctypes.c_int
+        L.tc_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, pd,
+                                      ctypes.POINTER(ctypes.c_long)]
+        L.tc_profile_read.restype = ctypes.c_int
         _lib = L
     return _lib
 

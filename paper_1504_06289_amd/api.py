@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PRECISIONS, TcInstance, check
+from ._lib import ALGORITHMS, PRECISIONS, TcInstance, check
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:
@@ -190,3 +190,58 @@ class TeiGram(torch.autograd.Function):
         dU = tei_gram_backward(c, (p1, p2, p3), (U1, U2, U3), Jbar.contiguous(), G=G,
                                prec=ctx.prec)
         return None, None, None, None, dU[0], dU[1], dU[2], None
+
+
+def _algo(algo) -> int:
+    if isinstance(algo, int):
+        return algo
+    try:
+        return ALGORITHMS[algo]
+    except KeyError:
+        raise ValueError(f"unknown algorithm {algo!r}; expected one of {list(ALGORITHMS)}")
+
+
+def tune_set(n: int, R_f: int, R_N: int, prec, algo) -> None:
+    """Pin the Toeplitz algorithm ("direct", "fft" or "auto" to clear) used for
+    modes of n cells with R_f functions and R_N terms at precision prec."""
+    check(_lib.lib().tc_tune_set(n, R_f, R_N, _prec(prec), _algo(algo)), "tc_tune_set")
+
+
+def tune_get(n: int, R_f: int, R_N: int, prec) -> str:
+    a = _lib.lib().tc_tune_get(n, R_f, R_N, _prec(prec))
+    return {v: k for k, v in ALGORITHMS.items()}[a]
+
+
+def autotune(c: torch.Tensor, p3, U3, prec="fp64"):
+    """Time both Toeplitz algorithms on this problem's modes (tc_autotune),
+    record the faster per mode shape, and return {mode: (ms_direct, ms_fft)}."""
+    dev = U3[0].device
+    R_f = U3[0].shape[0]
+    J = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+    inst = make_instance(c, p3, U3, J, None)
+    arr = (TcInstance * 1)(inst)
+    L = _lib.lib()
+    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _prec(prec))
+    ws = _workspace(ws_bytes, dev)
+    ms = np.zeros(6)
+    check(L.tc_autotune(arr, 1, _prec(prec), _ptr(ws), ws_bytes, _stream(dev),
+                        ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tc_autotune")
+    return {l: (float(ms[2 * l]), float(ms[2 * l + 1])) for l in range(3)}
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every kernel launch of the library with HIP events."""
+    check(_lib.lib().tc_profile_enable(1 if on else 0), "tc_profile_enable")
+
+
+def profile_read(max_kernels: int = 64) -> dict:
+    """Synchronise the recorded events and return {kernel: (total_ms, launches)}
+    accumulated since the previous read."""
+    names = (ctypes.c_char * 64 * max_kernels)()
+    ms = np.zeros(max_kernels)
+    calls = np.zeros(max_kernels, dtype=np.int64)
+    nk = _lib.lib().tc_profile_read(max_kernels, names, ms.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), calls.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    if nk < 0:
+        raise RuntimeError("tc_profile_read: event query failed")
+    return {names[i].value.decode(): (float(ms[i]), int(calls[i])) for i in range(min(nk, max_kernels))}

@@ -1,0 +1,590 @@
+// FFT route for the Toeplitz products (binary64):  W_k = T_k U  computed as
+// the aperiodic convolution p_k *_n u_j through a circulant embedding of
+// length N >= 2n-1 (power of two), i.e. the 1D FFT convolution that the
+// d-dimensional FFT of Section 2.3 factors into, applied per mode.
+//
+//   c_k[t] = p_k[t] (0 <= t < n),  c_k[N-m] = p_k[-m] (1 <= m < n),  0 else
+//   W_k[j][t] = (IDFT_N(DFT_N(c_k) . DFT_N(u_j zero-padded)))[t],  t < n
+//
+// Real transforms of length N use one complex transform of length M = N/2
+// (even samples as real part, odd as imaginary part) plus the standard
+// split/merge step with the twiddles e^(-2 pi i f / N).  The complex
+// transform runs in LDS with 256 threads as a Stockham autosort FFT
+// (radix 16, last pass radix 8/4/2); after each pass the sub-transform size
+// Ns grows by the radix R, butterfly j reads entries j + r M/R, multiplies
+// entry r by e^(sign 2 pi i (j mod Ns) r / (Ns R)), does an R-point DFT and
+// writes entries (j/Ns) Ns R + (j mod Ns) + r Ns.  LDS entry i is stored at
+// i ^ ((i >> 4) & 15) (a permutation inside each aligned group of 16), which
+// makes the strided reads and writes of every pass hit distinct banks and
+// keeps the buffer at exactly M entries (64 KB for M = 4096).
+//
+// Kernels:
+//   fft_twiddles       e^(-2 pi i t / N), t < N, for one N (sincospi)
+//   rfft_rows          half spectra of the zero-padded rows of U
+//   rfft_kernel_embed  half spectra of the circulant embeddings of the p_k
+//   fft_conv           for one function j and every term k: product of the
+//                      spectra, inverse transform, first n samples written
+//                      either as binary64 W or directly as the int8 slices
+//                      (one exponent per row) that the Gram consumes.
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+typedef double2 cplx;
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kMaxM = 4096;                  // complex length: N <= 8192, n <= 4096
+constexpr int kPairs = (kMaxM / 2 + 1 + kThreads - 1) / kThreads;  // 9
+
+__device__ inline cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline cplx cmul(cplx a, cplx b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+__device__ inline cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by SIGN * i
+template <int SIGN> __device__ inline cplx mul_si(cplx a)
+{
+    return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+__device__ inline int pad(int i) { return i ^ ((i >> 4) & 15); }
+
+// ---- small DFTs: X[q] = sum_r v[r] exp(SIGN 2 pi i r q / R) ----------------
+template <int SIGN> __device__ inline void dft2(cplx *v)
+{
+    const cplx a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int SIGN> __device__ inline void dft4(cplx *v)
+{
+    const cplx a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const cplx b0 = cadd(v[1], v[3]), b1 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, b1);
+    v[3] = csub(a1, b1);
+}
+
+template <int SIGN> __device__ inline void dft8(cplx *v)
+{
+    const double h = 0.70710678118654752440;  // cos(pi/4)
+    cplx e[4] = {v[0], v[2], v[4], v[6]};
+    cplx o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<SIGN>(e);
+    dft4<SIGN>(o);
+    // w8^q = exp(SIGN 2 pi i q / 8)
+    const cplx w[4] = {make_double2(1.0, 0.0), make_double2(h, SIGN * h),
+                       make_double2(0.0, (double)SIGN), make_double2(-h, SIGN * h)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const cplx t = cmul(w[q], o[q]);
+        v[q] = cadd(e[q], t);
+        v[q + 4] = csub(e[q], t);
+    }
+}
+
+template <int SIGN> __device__ inline void dft16(cplx *v)
+{
+    const double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;  // pi/8
+    const double h = 0.70710678118654752440;
+    cplx e[8], o[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        e[r] = v[2 * r];
+        o[r] = v[2 * r + 1];
+    }
+    dft8<SIGN>(e);
+    dft8<SIGN>(o);
+    // w16^q = cos(2 pi q/16) + SIGN i sin(2 pi q/16)
+    const double cs[8] = {1.0, c1, h, s1, 0.0, -s1, -h, -c1};
+    const double sn[8] = {0.0, s1, h, c1, 1.0, c1, h, s1};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const cplx t = cmul(make_double2(cs[q], SIGN * sn[q]), o[q]);
+        v[q] = cadd(e[q], t);
+        v[q + 8] = csub(e[q], t);
+    }
+}
+
+template <int R, int SIGN> __device__ inline void dft_small(cplx *v)
+{
+    if constexpr (R == 16)
+        dft16<SIGN>(v);
+    else if constexpr (R == 8)
+        dft8<SIGN>(v);
+    else if constexpr (R == 4)
+        dft4<SIGN>(v);
+    else if constexpr (R == 2)
+        dft2<SIGN>(v);
+}
+
+// One Stockham pass of radix R on buf (M complex, padded addressing), in
+// place: every thread loads its butterfly, the block synchronises, then
+// stores.  M/R <= 256 (one butterfly per thread at most).
+// twN: e^(-2 pi i t / N) with N = 2M, so e^(-2 pi i s / M) = twN[2s].
+template <int R, int SIGN>
+__device__ void stockham_pass(cplx *buf, int M, int Ns, const cplx *__restrict__ twN)
+{
+    const int nb = M / R;
+    const int j = threadIdx.x;
+    cplx v[R];
+    const bool active = j < nb;
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = buf[pad(j + r * nb)];
+        const int jm = j % Ns;
+        if (Ns > 1) {
+            // twiddle of entry r: e^(SIGN 2 pi i jm r / (Ns R)) = w1^r
+            const int step = jm * (M / (Ns * R));  // index into the M-point table
+            cplx w[R];
+            w[0] = make_double2(1.0, 0.0);
+            auto tw = [&](int s) {
+                const cplx x = twN[2 * s];
+                return SIGN > 0 ? cconj(x) : x;
+            };
+            w[1] = tw(step);
+            if constexpr (R >= 4) {
+                w[2] = tw(2 * step);
+                w[3] = cmul(w[2], w[1]);
+            }
+            if constexpr (R >= 8) {
+                w[4] = tw(4 * step);
+                w[5] = cmul(w[4], w[1]);
+                w[6] = cmul(w[4], w[2]);
+                w[7] = cmul(w[4], w[3]);
+            }
+            if constexpr (R >= 16) {
+                w[8] = tw(8 * step);
+#pragma unroll
+                for (int r = 9; r < 16; ++r)
+                    w[r] = cmul(w[8], w[r - 8]);
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                v[r] = cmul(v[r], w[r]);
+        }
+        dft_small<R, SIGN>(v);
+    }
+    __syncthreads();
+    if (active) {
+        const int jm = j % Ns;
+        const int base = (j / Ns) * Ns * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            buf[pad(base + r * Ns)] = v[r];
+    }
+    __syncthreads();
+}
+
+// Complex FFT of length M (power of two, 1..kMaxM) on buf, SIGN = -1
+// forward, +1 inverse (unnormalised).  Caller synchronises before the call.
+template <int SIGN> __device__ void fft_lds(cplx *buf, int M, const cplx *__restrict__ twN)
+{
+    int Ns = 1;
+    while (Ns < M) {
+        const int rem = M / Ns;
+        if (rem >= 16) {
+            stockham_pass<16, SIGN>(buf, M, Ns, twN);
+            Ns *= 16;
+        } else if (rem == 8) {
+            stockham_pass<8, SIGN>(buf, M, Ns, twN);
+            Ns *= 8;
+        } else if (rem == 4) {
+            stockham_pass<4, SIGN>(buf, M, Ns, twN);
+            Ns *= 4;
+        } else {
+            stockham_pass<2, SIGN>(buf, M, Ns, twN);
+            Ns *= 2;
+        }
+    }
+}
+
+// ---- FFT with the pass structure fixed at compile time ----------------------
+// Used by the per-term inverse transforms, where the same transform runs for
+// every kernel term: each thread loads the twiddle bases of its butterfly in
+// every pass once (e^(SIGN 2 pi i s/M) for s = step, 2 step, 4 step, 8 step)
+// and keeps them in registers, so the passes touch only LDS.
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+template <int M> struct FftShape {
+    static constexpr int LOG = ilog2c(M);
+    static constexpr int N16 = LOG / 4;
+    static constexpr int REM = LOG % 4;
+    static constexpr int NP = N16 + (REM ? 1 : 0);
+    static constexpr int radix(int p) { return p < N16 ? 16 : (1 << REM); }
+    static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * radix(p - 1); }
+};
+
+template <int M, int SIGN> struct FftTwiddles {
+    cplx w[FftShape<M>::NP > 0 ? FftShape<M>::NP : 1][4];
+};
+
+template <int M, int SIGN, int P>
+__device__ inline void load_twiddles_pass(FftTwiddles<M, SIGN> &T, const cplx *__restrict__ twN)
+{
+    using F = FftShape<M>;
+    if constexpr (P < F::NP) {
+        constexpr int R = F::radix(P), Ns = F::ns(P);
+        if constexpr (Ns > 1) {
+            const int j = threadIdx.x;
+            if (j < M / R) {
+                const int step = (j % Ns) * (M / (Ns * R));
+                auto tw = [&](int s) {
+                    const cplx x = twN[2 * s];
+                    return SIGN > 0 ? cconj(x) : x;
+                };
+                T.w[P][0] = tw(step);
+                if constexpr (R >= 4)
+                    T.w[P][1] = tw(2 * step);
+                if constexpr (R >= 8)
+                    T.w[P][2] = tw(4 * step);
+                if constexpr (R >= 16)
+                    T.w[P][3] = tw(8 * step);
+            }
+        }
+        load_twiddles_pass<M, SIGN, P + 1>(T, twN);
+    }
+}
+
+template <int M, int R, int Ns, int SIGN>
+__device__ inline void pass_fixed(cplx *buf, const cplx *wb)
+{
+    constexpr int nb = M / R;
+    const int j = threadIdx.x;
+    const bool active = nb >= kThreads || j < nb;
+    cplx v[R];
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = buf[pad(j + r * nb)];
+        if constexpr (Ns > 1) {
+            // w^r from the bases w^1, w^2, w^4, w^8 (binary digits of r),
+            // applied as soon as it is formed to keep few values live
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cplx w = (r & 1) ? wb[0] : make_double2(1.0, 0.0);
+                if constexpr (R >= 4)
+                    if (r & 2)
+                        w = (r & 1) ? cmul(w, wb[1]) : wb[1];
+                if constexpr (R >= 8)
+                    if (r & 4)
+                        w = (r & 3) ? cmul(w, wb[2]) : wb[2];
+                if constexpr (R >= 16)
+                    if (r & 8)
+                        w = (r & 7) ? cmul(w, wb[3]) : wb[3];
+                v[r] = cmul(v[r], w);
+            }
+        }
+        dft_small<R, SIGN>(v);
+    }
+    __syncthreads();
+    if (active) {
+        const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            buf[pad(base + r * Ns)] = v[r];
+    }
+    __syncthreads();
+}
+
+template <int M, int SIGN, int P>
+__device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, SIGN> &T)
+{
+    using F = FftShape<M>;
+    if constexpr (P < F::NP) {
+        pass_fixed<M, F::radix(P), F::ns(P), SIGN>(buf, T.w[P]);
+        fft_fixed<M, SIGN, P + 1>(buf, T);
+    }
+}
+
+__global__ __launch_bounds__(256) void fft_twiddles_kernel(cplx *twN, int N)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) {
+        double s, c;
+        sincospi(2.0 * (double)t / (double)N, &s, &c);
+        twN[t] = make_double2(c, -s);
+    }
+}
+
+// Half spectrum X[0..M] of a real length-N sequence given as z (M complex:
+// even samples real, odd imaginary) after its forward M-point FFT in buf.
+__device__ void rfft_finish(const cplx *buf, int M, const cplx *__restrict__ twN,
+                            cplx *__restrict__ out)
+{
+    for (int f = threadIdx.x; f <= M; f += blockDim.x) {
+        const cplx a = buf[pad(f % M)];
+        const cplx b = cconj(buf[pad((M - f) % M)]);
+        const cplx E = cscale(cadd(a, b), 0.5);
+        const cplx d = csub(a, b);
+        const cplx O = make_double2(0.5 * d.y, -0.5 * d.x);  // (a - b) / (2i)
+        const cplx w = f < 2 * M ? twN[f] : make_double2(1.0, 0.0);
+        out[f] = cadd(E, cmul(w, O));
+    }
+}
+
+// rows of X [rows][len] (zero-padded to N) -> half spectra [rows][M+1]
+__global__ __launch_bounds__(256) void rfft_rows_kernel(const double *__restrict__ X, int len,
+                                                        int M, const cplx *__restrict__ twN,
+                                                        cplx *__restrict__ spec)
+{
+    extern __shared__ cplx buf[];
+    const long row = blockIdx.x;
+    const double *x = X + row * len;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        const int t0 = 2 * m, t1 = 2 * m + 1;
+        buf[pad(m)] = make_double2(t0 < len ? x[t0] : 0.0, t1 < len ? x[t1] : 0.0);
+    }
+    __syncthreads();
+    fft_lds<-1>(buf, M, twN);
+    rfft_finish(buf, M, twN, spec + row * (M + 1));
+}
+
+// circulant embeddings of p [R_N][2n-1] (length N = 2M) -> half spectra [R_N][M+1]
+__global__ __launch_bounds__(256) void rfft_kernel_embed(const double *__restrict__ p, int n,
+                                                         int M, const cplx *__restrict__ twN,
+                                                         cplx *__restrict__ spec)
+{
+    extern __shared__ cplx buf[];
+    const int k = blockIdx.x;
+    const int N = 2 * M;
+    const double *pk = p + (long)k * (2L * n - 1) + (n - 1);  // pk[lag]
+    auto emb = [&](int t) -> double {
+        if (t < n)
+            return pk[t];
+        if (t > N - n)
+            return pk[t - N];
+        return 0.0;
+    };
+    for (int m = threadIdx.x; m < M; m += blockDim.x)
+        buf[pad(m)] = make_double2(emb(2 * m), emb(2 * m + 1));
+    __syncthreads();
+    fft_lds<-1>(buf, M, twN);
+    rfft_finish(buf, M, twN, spec + (long)k * (M + 1));
+}
+
+__device__ inline int row_exp(double amax)
+{
+    if (!(amax > 0.0))
+        return 0;
+    int E = ilogb(amax) - 6;
+    if (ldexp(amax, -E) > 127.0)
+        ++E;
+    return E;
+}
+
+// Four int8 digits of x 2^-E (|x 2^-E| <= 127) at weights 1, 2^-7, 2^-14,
+// 2^-21: round x 2^(21-E) to the integer q (|q| < 2^28, error <= 2^(E-22)),
+// then split q exactly into balanced base-128 digits (the leading digit in
+// [-127, 127], the others in [-64, 64]) with integer shifts.
+__device__ inline void split4_i8(double x, int E, int8_t s[4])
+{
+    int q = (int)rint(ldexp(x, 21 - E));
+    const int d0 = (q + (1 << 20)) >> 21;
+    q -= d0 << 21;
+    const int d1 = (q + (1 << 13)) >> 14;
+    q -= d1 << 14;
+    const int d2 = (q + (1 << 6)) >> 7;
+    q -= d2 << 7;
+    s[0] = (int8_t)d0;
+    s[1] = (int8_t)d1;
+    s[2] = (int8_t)d2;
+    s[3] = (int8_t)q;
+}
+
+// For function j (blockIdx.x) and every term k: W_k[j][t], t < n, from the
+// product of the spectra.  Output either binary64 rows (W != nullptr, layout
+// [R_N][R_f][n]) or int8 slices (WS != nullptr, layout [4][R_N][R_f_pad][n_pad]
+// with exponents EW [R_N][R_f_pad]); blocks with j >= R_f write zero slices.
+// Each thread owns the frequency pairs (f, M - f), f = tid + 256 q <= M/2; the
+// spectrum of u_j is re-read (from cache) for every term.
+template <int M>
+__global__ __launch_bounds__(256, 2) void fft_conv_kernel(
+    const cplx *__restrict__ Uspec, const cplx *__restrict__ Cspec, int n, int R_f, int R_N,
+    const cplx *__restrict__ twN, double *__restrict__ W, int8_t *__restrict__ WS,
+    int *__restrict__ EW, int R_f_pad, int n_pad, long wplane)
+{
+    constexpr int PAIRS = (M / 2 + 1 + kThreads - 1) / kThreads;
+    extern __shared__ cplx buf[];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+
+    if (j >= R_f) {  // zero padding rows of the slices
+        for (int k = 0; k < R_N; ++k) {
+            int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
+            for (int t = tid; t < n_pad; t += blockDim.x)
+                for (int s = 0; s < 4; ++s)
+                    row[s * wplane + t] = 0;
+            if (tid == 0)
+                EW[(long)k * R_f_pad + j] = 0;
+        }
+        return;
+    }
+
+    FftTwiddles<M, +1> T;
+    load_twiddles_pass<M, +1, 0>(T, twN);
+
+    const cplx *Uj = Uspec + (long)j * (M + 1);
+    constexpr double invM = 1.0 / (double)M;
+
+    for (int k = 0; k < R_N; ++k) {
+        const cplx *Ck = Cspec + (long)k * (M + 1);
+#pragma unroll 3
+        for (int q = 0; q < PAIRS; ++q) {
+            const int f = tid + kThreads * q;
+            if (f <= M / 2) {
+                const int g = M - f;
+                const cplx wf = twN[f];
+                const cplx yf = cmul(Ck[f], Uj[f]);
+                const cplx yg = cmul(Ck[g], Uj[g]);
+                // Z[f] = E + i O,  E = (Y[f] + conj Y[g]) / 2,  O = (Y[f] - conj Y[g]) conj(w^f) / 2
+                {
+                    const cplx E = cscale(cadd(yf, cconj(yg)), 0.5);
+                    const cplx O = cscale(cmul(csub(yf, cconj(yg)), cconj(wf)), 0.5);
+                    buf[pad(f)] = make_double2(E.x - O.y, E.y + O.x);
+                }
+                if (g < M && g != f) {
+                    const cplx wg = make_double2(-wf.x, wf.y);  // w^(M-f) = -conj(w^f)
+                    const cplx E = cscale(cadd(yg, cconj(yf)), 0.5);
+                    const cplx O = cscale(cmul(csub(yg, cconj(yf)), cconj(wg)), 0.5);
+                    buf[pad(g)] = make_double2(E.x - O.y, E.y + O.x);
+                }
+            }
+        }
+        __syncthreads();
+        fft_fixed<M, +1, 0>(buf, T);
+
+        if (W) {
+            double *Wrow = W + ((long)k * R_f + j) * n;
+            for (int m = tid; m < M; m += blockDim.x) {
+                const cplx z = buf[pad(m)];
+                const int t = 2 * m;
+                if (t < n)
+                    Wrow[t] = z.x * invM;
+                if (t + 1 < n)
+                    Wrow[t + 1] = z.y * invM;
+            }
+        } else {
+            double amax = 0.0;
+            for (int m = tid; m < M; m += blockDim.x) {
+                const cplx z = buf[pad(m)];
+                const int t = 2 * m;
+                if (t < n)
+                    amax = fmax(amax, fabs(z.x));
+                if (t + 1 < n)
+                    amax = fmax(amax, fabs(z.y));
+            }
+            // block maximum through a small static array (the FFT buffer is still read below)
+            __shared__ double red[4];
+            for (int o = 32; o > 0; o >>= 1)
+                amax = fmax(amax, __shfl_xor(amax, o));
+            if ((tid & 63) == 0)
+                red[tid >> 6] = amax;
+            __syncthreads();
+            amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * invM;
+            const int E = row_exp(amax);
+            if (tid == 0)
+                EW[(long)k * R_f_pad + j] = E;
+            int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
+            for (int m = tid; 2 * m < n_pad; m += blockDim.x) {
+                const int t = 2 * m;
+                int8_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+                if (m < M) {
+                    const cplx z = buf[pad(m)];
+                    if (t < n)
+                        split4_i8(z.x * invM, E, s0);
+                    if (t + 1 < n)
+                        split4_i8(z.y * invM, E, s1);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const unsigned short two = (unsigned short)((unsigned char)s0[s] |
+                                                                ((unsigned)(unsigned char)s1[s] << 8));
+                    *reinterpret_cast<unsigned short *>(row + s * wplane + t) = two;
+                }
+            }
+        }
+        __syncthreads();  // buf and red are rewritten by the next term
+    }
+}
+
+size_t lds_bytes(int M) { return sizeof(cplx) * (size_t)(M < 4 ? 4 : M); }
+
+}  // namespace
+
+int fft_length(int n)
+{
+    int N = 2;
+    while (N < 2 * n - 1)
+        N *= 2;
+    return N;
+}
+
+bool fft_supported(int n) { return n >= 1 && fft_length(n) / 2 <= kMaxM; }
+
+hipError_t launch_fft_twiddles(cplx *twN, int N, hipStream_t stream)
+{
+    hipLaunchKernelGGL(fft_twiddles_kernel, dim3((N + 255) / 256), dim3(256), 0, stream, twN, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_rfft_rows(const double *X, int rows, int len, int N, const cplx *twN,
+                            cplx *spec, hipStream_t stream)
+{
+    const int M = N / 2;
+    hipLaunchKernelGGL(rfft_rows_kernel, dim3(rows), dim3(256), lds_bytes(M), stream, X, len, M,
+                       twN, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, const cplx *twN,
+                                    cplx *spec, hipStream_t stream)
+{
+    const int M = N / 2;
+    hipLaunchKernelGGL(rfft_kernel_embed, dim3(R_N), dim3(256), lds_bytes(M), stream, p, n, M,
+                       twN, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, int R_f, int R_N,
+                           const cplx *twN, double *W, int8_t *WS, int *EW, int R_f_pad,
+                           int n_pad, long wplane, hipStream_t stream)
+{
+    const int M = N / 2;
+    const int blocks = W ? R_f : R_f_pad;
+#define TC_FFT_CONV_CASE(MM)                                                                    \
+    case MM:                                                                                    \
+        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(256), lds_bytes(MM), stream, \
+                           Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane);  \
+        break;
+    switch (M) {
+        TC_FFT_CONV_CASE(1)
+        TC_FFT_CONV_CASE(2)
+        TC_FFT_CONV_CASE(4)
+        TC_FFT_CONV_CASE(8)
+        TC_FFT_CONV_CASE(16)
+        TC_FFT_CONV_CASE(32)
+        TC_FFT_CONV_CASE(64)
+        TC_FFT_CONV_CASE(128)
+        TC_FFT_CONV_CASE(256)
+        TC_FFT_CONV_CASE(512)
+        TC_FFT_CONV_CASE(1024)
+        TC_FFT_CONV_CASE(2048)
+        TC_FFT_CONV_CASE(4096)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef TC_FFT_CONV_CASE
+    return hipGetLastError();
+}
+
+}  // namespace tc

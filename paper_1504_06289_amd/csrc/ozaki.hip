@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
     const int8_t *__restrict__ PS, const int *__restrict__ EP, long pplane, int LP, int off,
     double *__restrict__ W, int n, int R_f)
 {
-    __shared__ __attribute__((aligned(16))) int8_t As[A_BYTES];
-    __shared__ __attribute__((aligned(16))) int8_t Pw[W_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t As[2][A_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Pw[2][W_BYTES];
 
     const int k = blockIdx.z;
     const int a0 = blockIdx.x * TA;
@@ -202,16 +202,17 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
             preg = *reinterpret_cast<const v4i *>(pk + sl * pplane + xs0 + b0 + 16 * c16);
         }
     };
-    auto store_stage = [&]() {
+    auto store_stage = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = tid + 256 * q;
             const int sl = c >> 8, row = (c & 255) >> 2, c16 = c & 3;
-            *reinterpret_cast<v4i *>(As + sl * (TJ * AROW) + row * AROW + 16 * c16) = areg[q];
+            *reinterpret_cast<v4i *>(As[buf] + sl * (TJ * AROW) + row * AROW + 16 * c16) =
+                areg[q];
         }
         if (tid < 64) {
             const int sl = tid >> 4, c16 = tid & 15;
-            *reinterpret_cast<v4i *>(Pw + sl * WLEN + 16 * c16) = preg;
+            *reinterpret_cast<v4i *>(Pw[buf] + sl * WLEN + 16 * c16) = preg;
         }
     };
 
@@ -230,10 +231,10 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
 
     const int nsteps = n_pad / TK;
     load_stage(0);
+    store_stage(0);
+    __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
-        __syncthreads();  // previous compute done before overwriting LDS
-        store_stage();
-        __syncthreads();
+        const int cur = s & 1;
         if (s + 1 < nsteps)
             load_stage((s + 1) * TK);
 
@@ -243,11 +244,11 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
 #pragma unroll
             for (int sl = 0; sl < 4; ++sl)
                 afr[x][sl] = *reinterpret_cast<const v4i *>(
-                    As + sl * (TJ * AROW) + (wj + 16 * x + l16) * AROW + 16 * g);
+                    As[cur] + sl * (TJ * AROW) + (wj + 16 * x + l16) * AROW + 16 * g);
 
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl) {
-            const unsigned *w32 = reinterpret_cast<const unsigned *>(Pw + sl * WLEN);
+            const unsigned *w32 = reinterpret_cast<const unsigned *>(Pw[cur] + sl * WLEN);
             unsigned dw[17];
 #pragma unroll
             for (int i = 0; i < 17; ++i)
@@ -271,6 +272,9 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
                         acc[x][y][i + sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                             afr[x][i], bfr[y], acc[x][y][i + sl], 0, 0, 0);
         }
+        if (s + 1 < nsteps)
+            store_stage(cur ^ 1);
+        __syncthreads();
     }
 
     const int Ep = EP[k];
@@ -406,6 +410,136 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
         }
 }
 
+// Large-tile variant for R_f >= 256: 128 x 128 tiles, waves 2 x 2 of
+// 64 x 64 (4 x 4 MFMA blocks, 256 accumulator registers), K-step 64.  The
+// per-workgroup operand traffic per multiply-add halves compared with the
+// 64 x 64 tiles.  Work items are (tile, k) with k grouped by XCD (work item
+// w runs on XCD w mod 8), so the workgroups of one term run on one XCD and
+// re-read that term's W slices from its L2.
+constexpr int GT2 = 128;
+constexpr int G2_BYTES = 4 * GT2 * AROW;  // 40960 per operand
+
+__global__ __launch_bounds__(256) void gram_i8_big_kernel(
+    const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
+    const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
+    int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntiles, int ntri)
+{
+    // two LDS stages of both operands: 4 x 40 KB = 160 KB
+    __shared__ __attribute__((aligned(16))) int8_t As[2][G2_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][G2_BYTES];
+
+    // work item -> (k, tile): XCD x = w % 8 takes the terms k = x, x+8, ...
+    const int w = blockIdx.x;
+    const int xcd = w & 7, local = w >> 3;
+    const int per_k = ntri;
+    int k = xcd + 8 * (local / per_k);
+    int t = local % per_k;
+    if (k >= R_N)
+        return;
+    int ti = 0;
+    while (t >= ntiles - ti) {
+        t -= ntiles - ti;
+        ++ti;
+    }
+    const int tj = ti + t;
+    const int i0 = ti * GT2, j0 = tj * GT2;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int8_t *Wk = WS + (long)k * R_f_pad * n_pad;
+
+    // staging: per operand 4 slices x 128 rows x 4 chunks of 16 B = 2048 chunks, 8 per thread
+    v4i areg[8], breg[8];
+    auto load_stage = [&](int a0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = tid + 256 * q;  // slice = c/512, row = (c%512)/4, col16 = c%4
+            const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
+            areg[q] = *reinterpret_cast<const v4i *>(US + sl * uplane + (long)(i0 + row) * n_pad +
+                                                     a0 + 16 * c16);
+            breg[q] = *reinterpret_cast<const v4i *>(Wk + sl * wplane + (long)(j0 + row) * n_pad +
+                                                     a0 + 16 * c16);
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = tid + 256 * q;
+            const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
+            const int o = sl * (GT2 * AROW) + row * AROW + 16 * c16;
+            *reinterpret_cast<v4i *>(As[buf] + o) = areg[q];
+            *reinterpret_cast<v4i *>(Bs[buf] + o) = breg[q];
+        }
+    };
+
+    v4i acc[4][4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                acc[x][y][d] = v4i{0, 0, 0, 0};
+
+    const int nsteps = n_pad / TK;
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < nsteps)
+            load_stage((s + 1) * TK);
+        v4i afr[4][4];
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                afr[x][sl] = *reinterpret_cast<const v4i *>(
+                    As[cur] + sl * (GT2 * AROW) + (wi + 16 * x + l16) * AROW + 16 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v4i bfr[4];
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                bfr[y] = *reinterpret_cast<const v4i *>(
+                    Bs[cur] + j * (GT2 * AROW) + (wj + 16 * y + l16) * AROW + 16 * g);
+#pragma unroll
+            for (int i = 0; i + j <= 3; ++i)
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            afr[x][i], bfr[y], acc[x][y][i + j], 0, 0, 0);
+        }
+        // the other stage was last read in step s-1, before the barrier that ended it
+        if (s + 1 < nsteps)
+            store_stage(cur ^ 1);
+        __syncthreads();
+    }
+
+    double *Gk = G + (long)k * R_f * R_f;
+    const int *EWk = EW + (long)k * R_f_pad;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + wi + 16 * x + 4 * g + r;
+            if (i >= R_f)
+                continue;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int j = j0 + wj + 16 * y + l16;
+                if (j < R_f && i <= j) {
+                    const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
+                    Gk[(long)i * R_f + j] = v;
+                    Gk[(long)j * R_f + i] = v;
+                }
+            }
+        }
+}
+
 }  // namespace
 
 OzakiLayout ozaki_layout(int n, int R_f, int R_N)
@@ -450,6 +584,17 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream)
 {
+    if (R_f >= 256 && L.R_f_pad % GT2 == 0) {
+        const int nt = L.R_f_pad / GT2;
+        const int ntri = nt * (nt + 1) / 2;
+        // items: for every XCD x, the terms k = x, x + 8, ... each with ntri tiles
+        const int kgroups = (R_N + 7) / 8;
+        const int items = 8 * kgroups * ntri;
+        hipLaunchKernelGGL(gram_i8_big_kernel, dim3(items), dim3(256), 0, stream, US, EU,
+                           L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, nt,
+                           ntri);
+        return hipGetLastError();
+    }
     const int nt = L.R_f_pad / GT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
     hipLaunchKernelGGL(gram_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, WS, EW,

@@ -1,11 +1,17 @@
-// C-ABI layer (include/tc.h): argument validation, workspace layout and
-// kernel dispatch.  Nothing here allocates, frees or synchronises; every
-// launch goes to the caller's stream, so a call can be captured in a HIP
-// graph.
+// C-ABI layer (include/tc.h): argument validation, workspace layout,
+// algorithm choice (tuning table) and kernel dispatch.  Apart from
+// tc_autotune nothing here allocates, frees or synchronises; every launch goes
+// to the caller's stream, so a call can be captured in a HIP graph.
 #include "tc.h"
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <string>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
 #include <vector>
 
 #include "tc_internal.h"
@@ -40,6 +46,35 @@ bool instance_ok(const tc_instance &I)
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// tuning table
+// ---------------------------------------------------------------------------
+using TuneKey = std::tuple<int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+// Built-in rule: the FFT route once the grid is long enough for the n^2
+// Toeplitz product to dominate (measured crossover on MI355X, refined by
+// tc_autotune), the direct matrix-core product otherwise.
+constexpr int kFftMinN = 256;
+
+tc_algorithm resolve(int n, int R_f, int R_N, tc_precision prec)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey(n, R_f, R_N, (int)prec));
+        if (it != g_tune.end()) {
+            const tc_algorithm a = (tc_algorithm)it->second;
+            if (a != TC_ALGO_FFT || fft_supported(n))
+                return a;
+        }
+    }
+    return (fft_supported(n) && n >= kFftMinN) ? TC_ALGO_FFT : TC_ALGO_DIRECT;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
 // Bump allocator over the caller's workspace.  With base == nullptr it only
 // measures, so the same code computes tc_workspace_bytes and the layout.
 struct Carver {
@@ -54,75 +89,172 @@ struct Carver {
     }
 };
 
-// Scratch of one mode's Toeplitz product (slices of U and of the kernel).
-struct ToeplitzScratch {
-    int8_t *US = nullptr;
+// Scratch of one mode (every buffer any algorithm/precision may need).
+struct ModeScratch {
+    int8_t *US = nullptr;  // int8 slices of U
     int *EU = nullptr;
-    int8_t *PS = nullptr;
+    int8_t *PS = nullptr;  // int8 slices of the kernel vectors (direct route)
     int *EP = nullptr;
+    int8_t *WS = nullptr;  // int8 slices of W
+    int *EW = nullptr;
+    double2 *twN = nullptr;    // FFT twiddles
+    double2 *Uspec = nullptr;  // half spectra of U rows
+    double2 *Cspec = nullptr;  // half spectra of the kernel embeddings
 };
 
-ToeplitzScratch carve_toeplitz(Carver &c, tc_precision prec, int n, int R_f, int R_N)
+ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram)
 {
-    ToeplitzScratch s;
+    ModeScratch s;
     if (prec == TC_OZAKI_I8) {
         const OzakiLayout L = ozaki_layout(n, R_f, R_N);
         s.US = c.take<int8_t>(4 * (size_t)L.uplane);
         s.EU = c.take<int>(L.R_f_pad);
         s.PS = c.take<int8_t>(4 * (size_t)L.pplane);
         s.EP = c.take<int>(R_N);
+        if (gram) {
+            s.WS = c.take<int8_t>(4 * (size_t)L.wplane);
+            s.EW = c.take<int>((size_t)R_N * L.R_f_pad);
+        }
+    }
+    if (fft_supported(n)) {
+        const int N = fft_length(n);
+        s.twN = c.take<double2>(N);
+        s.Uspec = c.take<double2>((size_t)R_f * (N / 2 + 1));
+        s.Cspec = c.take<double2>((size_t)R_N * (N / 2 + 1));
     }
     return s;
 }
 
-// Scratch of one mode's Gram on top of the Toeplitz scratch (slices of W).
-struct GramScratch {
-    int8_t *WS = nullptr;
-    int *EW = nullptr;
+// ---------------------------------------------------------------------------
+// kernel timing (tc_profile_*): when enabled, every launch is bracketed by a
+// pair of HIP events recorded on the launch stream; tc_profile_read
+// synchronises the recorded events and returns per-kernel totals.
+// ---------------------------------------------------------------------------
+struct ProfRecord {
+    const char *name;
+    hipEvent_t e0, e1;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    const char *name;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    ProfScope(const char *n, hipStream_t s) : name(n), st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on)
+            return;
+        e0 = prof_event();
+        if (e0 && hipEventRecord(e0, st) != hipSuccess) {
+            g_prof_pool.push_back(e0);
+            e0 = nullptr;
+        }
+    }
+    void end()
+    {
+        if (!e0)
+            return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        hipEvent_t e1 = prof_event();
+        if (e1 && hipEventRecord(e1, st) == hipSuccess) {
+            g_prof_pending.push_back({name, e0, e1});
+        } else {
+            g_prof_pool.push_back(e0);
+            if (e1)
+                g_prof_pool.push_back(e1);
+        }
+        e0 = nullptr;
+    }
 };
 
-GramScratch carve_gram(Carver &c, tc_precision prec, int n, int R_f, int R_N)
+// launch `expr` (returns hipError_t) under the kernel name `name` on stream st
+#define TRYK(name, expr)                                                                       \
+    do {                                                                                       \
+        ProfScope ps_(name, st);                                                               \
+        if ((expr) != hipSuccess)                                                              \
+            return TC_ERR_HIP;                                                                 \
+        ps_.end();                                                                             \
+    } while (0)
+
+// spectra of U's rows and of the kernel embeddings (FFT route)
+tc_status fft_spectra(int n, int R_f, int R_N, const double *p, const double *U,
+                      const ModeScratch &s, hipStream_t st)
 {
-    GramScratch s;
-    if (prec == TC_OZAKI_I8) {
-        const OzakiLayout L = ozaki_layout(n, R_f, R_N);
-        s.WS = c.take<int8_t>(4 * (size_t)L.wplane);
-        s.EW = c.take<int>((size_t)R_N * L.R_f_pad);
+    const int N = fft_length(n);
+    TRYK("fft_twiddles", launch_fft_twiddles(s.twN, N, st));
+    TRYK("rfft_rows", launch_rfft_rows(U, R_f, n, N, s.twN, s.Uspec, st));
+    TRYK("rfft_kernel_embed", launch_rfft_kernel_embed(p, n, R_N, N, s.twN, s.Cspec, st));
+    return TC_OK;
+}
+
+// W = T_k U (binary64 output) for all k of one mode.
+tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, const double *p,
+                 const double *U, double *W, const ModeScratch &s, hipStream_t st)
+{
+    if (algo == TC_ALGO_FFT) {
+        const tc_status r = fft_spectra(n, R_f, R_N, p, U, s, st);
+        if (r != TC_OK)
+            return r;
+        TRYK("fft_conv", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN, W,
+                                         nullptr, nullptr, 0, 0, 0, st));
+        return TC_OK;
     }
-    return s;
+    if (prec == TC_FP64) {
+        TRYK("toeplitz_f64", launch_toeplitz_f64(p, U, W, n, R_f, R_N, st));
+        return TC_OK;
+    }
+    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
+    TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
+    TRYK("split_kernel_vectors", launch_split_kernel_vectors(p, n, R_N, L, s.PS, s.EP, st));
+    TRYK("toeplitz_i8", launch_toeplitz_i8(s.US, s.EU, s.PS, s.EP, L, W, n, R_f, R_N, st));
+    return TC_OK;
 }
 
-// W = T_k U for all k of one mode.  For the int8 path the slices of U are
-// left in `ts` for a following Gram.
-hipError_t mode_toeplitz(tc_precision prec, int n, int R_f, int R_N, const double *p,
-                         const double *U, double *W, const ToeplitzScratch &ts, hipStream_t st)
+// G_k = U^T T_k U for all k of one mode (W is scratch).
+tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N,
+                     const double *p, const double *U, double *W, double *G,
+                     const ModeScratch &s, hipStream_t st)
 {
-    if (prec == TC_FP64)
-        return launch_toeplitz_f64(p, U, W, n, R_f, R_N, st);
+    if (prec == TC_FP64) {
+        const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
+        if (r != TC_OK)
+            return r;
+        TRYK("gram_f64", launch_gram_f64(U, W, G, n, R_f, R_N, st));
+        return TC_OK;
+    }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
-    hipError_t e =
-        launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, ts.US, ts.EU, st);
-    if (e != hipSuccess)
-        return e;
-    e = launch_split_kernel_vectors(p, n, R_N, L, ts.PS, ts.EP, st);
-    if (e != hipSuccess)
-        return e;
-    return launch_toeplitz_i8(ts.US, ts.EU, ts.PS, ts.EP, L, W, n, R_f, R_N, st);
-}
-
-// G_k = U^T W_k for all k of one mode (W from mode_toeplitz with the same ts).
-hipError_t mode_gram(tc_precision prec, int n, int R_f, int R_N, const double *U,
-                     const double *W, double *G, const ToeplitzScratch &ts,
-                     const GramScratch &gs, hipStream_t st)
-{
-    if (prec == TC_FP64)
-        return launch_gram_f64(U, W, G, n, R_f, R_N, st);
-    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
-    hipError_t e =
-        launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, gs.WS, gs.EW, st);
-    if (e != hipSuccess)
-        return e;
-    return launch_gram_i8(ts.US, ts.EU, gs.WS, gs.EW, L, G, R_f, R_N, st);
+    if (algo == TC_ALGO_FFT) {
+        const tc_status r = fft_spectra(n, R_f, R_N, p, U, s, st);
+        if (r != TC_OK)
+            return r;
+        TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
+        TRYK("fft_conv_split", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN,
+                                               nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, st));
+    } else {
+        const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
+        if (r != TC_OK)
+            return r;
+        TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
+    }
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, st));
+    return TC_OK;
 }
 
 int max_n(const tc_instance &I)
@@ -138,8 +270,7 @@ int max_n(const tc_instance &I)
 // the per-mode scratch is sized for the largest mode and reused.
 struct InstancePlan {
     double *W, *G, *D;
-    ToeplitzScratch ts[3];
-    GramScratch gs[3];
+    ModeScratch ms[3];
     size_t bytes;
 };
 
@@ -155,8 +286,7 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
     size_t scratch_max = 0;
     for (int l = 0; l < 3; ++l) {
         c.used = scratch0;
-        P.ts[l] = carve_toeplitz(c, prec, I.n[l], I.R_f, I.R_N);
-        P.gs[l] = carve_gram(c, prec, I.n[l], I.R_f, I.R_N);
+        P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true);
         if (c.used - scratch0 > scratch_max)
             scratch_max = c.used - scratch0;
     }
@@ -167,7 +297,7 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
 size_t convolve_ws(int n, int R_f, int R_N, tc_precision prec)
 {
     Carver c(nullptr);
-    carve_toeplitz(c, prec, n, R_f, R_N);
+    carve_mode(c, prec, n, R_f, R_N, false);
     return c.used;
 }
 
@@ -176,17 +306,14 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
     const InstancePlan P = plan_instance(ws, I, prec, false);
     const size_t F2 = (size_t)I.R_f * I.R_f;
     for (int l = 0; l < 3; ++l) {
-        double *Gl = P.G + (size_t)l * I.R_N * F2;
-        if (mode_toeplitz(prec, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W, P.ts[l], st) !=
-            hipSuccess)
-            return TC_ERR_HIP;
-        if (mode_gram(prec, I.n[l], I.R_f, I.R_N, I.U[l], P.W, Gl, P.ts[l], P.gs[l], st) !=
-            hipSuccess)
-            return TC_ERR_HIP;
+        const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
+        const tc_status r = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W,
+                                       P.G + (size_t)l * I.R_N * F2, P.ms[l], st);
+        if (r != TC_OK)
+            return r;
     }
-    if (launch_hadamard_sum(I.c, P.G, P.G + (size_t)I.R_N * F2, P.G + 2 * (size_t)I.R_N * F2,
-                            I.J, I.R_f, I.R_N, st) != hipSuccess)
-        return TC_ERR_HIP;
+    TRYK("hadamard_sum", launch_hadamard_sum(I.c, P.G, P.G + (size_t)I.R_N * F2,
+                                             P.G + 2 * (size_t)I.R_N * F2, I.J, I.R_f, I.R_N, st));
     return TC_OK;
 }
 
@@ -197,25 +324,22 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
     const size_t F2 = (size_t)I.R_f * I.R_f;
     if (!I.G_saved) {
         for (int l = 0; l < 3; ++l) {
-            if (mode_toeplitz(prec, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W, P.ts[l], st) !=
-                hipSuccess)
-                return TC_ERR_HIP;
-            if (mode_gram(prec, I.n[l], I.R_f, I.R_N, I.U[l], P.W, P.G + (size_t)l * I.R_N * F2,
-                          P.ts[l], P.gs[l], st) != hipSuccess)
-                return TC_ERR_HIP;
+            const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
+            const tc_status r = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W,
+                                           P.G + (size_t)l * I.R_N * F2, P.ms[l], st);
+            if (r != TC_OK)
+                return r;
         }
     }
     for (int l = 0; l < 3; ++l) {
         const double *Ga = P.G + (size_t)((l + 1) % 3) * I.R_N * F2;
         const double *Gb = P.G + (size_t)((l + 2) % 3) * I.R_N * F2;
-        if (launch_adjoint_d(I.c, Jbar, Ga, Gb, P.D, I.R_f, I.R_N, st) != hipSuccess)
-            return TC_ERR_HIP;
-        if (mode_toeplitz(prec, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W, P.ts[l], st) !=
-            hipSuccess)
-            return TC_ERR_HIP;
-        if (launch_adjoint_gemm_f64(P.D, P.W, dU[l], I.n[l], I.R_f, I.R_N, 2.0, st) !=
-            hipSuccess)
-            return TC_ERR_HIP;
+        TRYK("adjoint_d", launch_adjoint_d(I.c, Jbar, Ga, Gb, P.D, I.R_f, I.R_N, st));
+        const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
+        const tc_status r = mode_W(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W, P.ms[l], st);
+        if (r != TC_OK)
+            return r;
+        TRYK("adjoint_gemm_f64", launch_adjoint_gemm_f64(P.D, P.W, dU[l], I.n[l], I.R_f, I.R_N, 2.0, st));
     }
     return TC_OK;
 }
@@ -241,7 +365,7 @@ const char *tc_status_string(tc_status s)
     return "unknown tc_status";
 }
 
-int tc_version(void) { return 200; }
+int tc_version(void) { return 300; }
 
 size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precision prec)
 {
@@ -267,6 +391,30 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
     return w;
 }
 
+tc_status tc_tune_set(int n, int R_f, int R_N, tc_precision prec, tc_algorithm algo)
+{
+    if (!size_ok(n, R_f, R_N) || !prec_known(prec))
+        return TC_ERR_INVALID_ARG;
+    if (algo != TC_ALGO_AUTO && algo != TC_ALGO_DIRECT && algo != TC_ALGO_FFT)
+        return TC_ERR_INVALID_ARG;
+    if (algo == TC_ALGO_FFT && !fft_supported(n))
+        return TC_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneKey key(n, R_f, R_N, (int)prec);
+    if (algo == TC_ALGO_AUTO)
+        g_tune.erase(key);
+    else
+        g_tune[key] = (int)algo;
+    return TC_OK;
+}
+
+tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec)
+{
+    if (!size_ok(n, R_f, R_N) || !prec_known(prec))
+        return TC_ALGO_AUTO;
+    return resolve(n, R_f, R_N, prec);
+}
+
 tc_status tc_newton_kernel(int n, double h, int R_N, double u0, double hu, double *t_host,
                            double *c_host, double *p_dev, void *stream)
 {
@@ -282,8 +430,8 @@ tc_status tc_newton_kernel(int n, double h, int R_N, double u0, double hu, doubl
             return TC_ERR_INVALID_ARG;
     }
     const double two_over_sqrtpi = 1.1283791670955125739;
-    if (launch_newton_kernel(t.data(), R_N, n, h, p_dev, (hipStream_t)stream) != hipSuccess)
-        return TC_ERR_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    TRYK("newton_kernel", launch_newton_kernel(t.data(), R_N, n, h, p_dev, st));
     for (int k = 0; k < R_N; ++k) {
         if (t_host)
             t_host[k] = t[k];
@@ -304,11 +452,9 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double
     if (need > 0 && (!ws || ws_bytes < need))
         return TC_ERR_WORKSPACE;
     Carver c(ws);
-    const ToeplitzScratch ts = carve_toeplitz(c, prec, n, R_f, R_N);
-    if (mode_toeplitz(prec, n, R_f, R_N, p_dev, U_dev, W_dev, ts, (hipStream_t)stream) !=
-        hipSuccess)
-        return TC_ERR_HIP;
-    return TC_OK;
+    const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false);
+    return mode_W(prec, resolve(n, R_f, R_N, prec), n, R_f, R_N, p_dev, U_dev, W_dev, s,
+                  (hipStream_t)stream);
 }
 
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec, void *ws,
@@ -358,6 +504,136 @@ tc_status tc_tei_gram_backward(const tc_instance *inst, int count, const double 
             return s;
     }
     return TC_OK;
+}
+
+tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, void *ws,
+                      size_t ws_bytes, void *stream, double *ms_out)
+{
+    if (!inst || count < 1 || !prec_known(prec))
+        return TC_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i)
+        if (!instance_ok(inst[i]))
+            return TC_ERR_INVALID_ARG;
+    if (!prec_supported(prec))
+        return TC_ERR_UNSUPPORTED;
+    // the Grams of the measurement runs go to the workspace, never to G_saved
+    size_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        tc_instance scratchI = inst[i];
+        scratchI.G_saved = nullptr;
+        const size_t wi = plan_instance(nullptr, scratchI, prec, false).bytes;
+        if (wi > need)
+            need = wi;
+    }
+    if (!ws || ws_bytes < need)
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return TC_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return TC_ERR_HIP;
+    }
+    tc_status status = TC_OK;
+    std::map<TuneKey, std::pair<double, double>> measured;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const tc_instance &I = inst[i];
+        // scratch Grams: never the caller's G_saved
+        tc_instance scratchI = I;
+        scratchI.G_saved = nullptr;
+        const InstancePlan P = plan_instance(ws, scratchI, prec, false);
+        for (int l = 0; l < 3 && status == TC_OK; ++l) {
+            const TuneKey key(I.n[l], I.R_f, I.R_N, (int)prec);
+            auto it = measured.find(key);
+            if (it == measured.end()) {
+                double ms[2] = {-1.0, -1.0};
+                const tc_algorithm cand[2] = {TC_ALGO_DIRECT, TC_ALGO_FFT};
+                for (int a = 0; a < 2 && status == TC_OK; ++a) {
+                    if (cand[a] == TC_ALGO_FFT && !fft_supported(I.n[l]))
+                        continue;
+                    for (int rep = 0; rep < 4 && status == TC_OK; ++rep) {
+                        if (rep == 1 && hipEventRecord(e0, st) != hipSuccess)
+                            status = TC_ERR_HIP;
+                        if (status == TC_OK)
+                            status = mode_grams(prec, cand[a], I.n[l], I.R_f, I.R_N, I.p[l],
+                                                I.U[l], P.W, P.G, P.ms[l], st);
+                    }
+                    float t = 0.0f;
+                    if (status == TC_OK &&
+                        (hipEventRecord(e1, st) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                        status = TC_ERR_HIP;
+                    ms[a] = t / 3.0;
+                }
+                it = measured.emplace(key, std::make_pair(ms[0], ms[1])).first;
+                if (status == TC_OK) {
+                    const bool fft_wins = ms[1] >= 0.0 && ms[1] < ms[0];
+                    std::lock_guard<std::mutex> lk(g_tune_mu);
+                    g_tune[key] = fft_wins ? (int)TC_ALGO_FFT : (int)TC_ALGO_DIRECT;
+                }
+            }
+            if (ms_out) {
+                ms_out[(i * 3 + l) * 2 + 0] = it->second.first;
+                ms_out[(i * 3 + l) * 2 + 1] = it->second.second;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
+}
+
+
+tc_status tc_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return TC_OK;
+}
+
+int tc_profile_read(int max_kernels, char (*names)[64], double *total_ms, long *calls)
+{
+    std::vector<ProfRecord> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof_pending);
+    }
+    std::map<std::string, std::pair<double, long>> tot;
+    int status = 0;
+    for (const ProfRecord &r : recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+            status = -1;
+        auto &e = tot[r.name];
+        e.first += ms;
+        e.second += 1;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (const ProfRecord &r : recs) {
+            g_prof_pool.push_back(r.e0);
+            g_prof_pool.push_back(r.e1);
+        }
+    }
+    if (status != 0)
+        return -1;
+    int i = 0;
+    for (const auto &kv : tot) {
+        if (i >= max_kernels)
+            break;
+        if (names) {
+            std::snprintf(names[i], 64, "%s", kv.first.c_str());
+        }
+        if (total_ms)
+            total_ms[i] = kv.second.first;
+        if (calls)
+            calls[i] = kv.second.second;
+        ++i;
+    }
+    return (int)tot.size();
 }
 
 }  // extern "C"

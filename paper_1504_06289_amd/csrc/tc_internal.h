@@ -73,4 +73,22 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream);
 
+// ---- FFT route (fft.hip) ---------------------------------------------------
+// N = smallest power of two >= 2n-1; the route needs N/2 <= 4096 (n <= 4096).
+int fft_length(int n);
+bool fft_supported(int n);
+hipError_t launch_fft_twiddles(double2 *twN, int N, hipStream_t stream);
+// half spectra [rows][N/2+1] of the zero-padded rows of X [rows][len]
+hipError_t launch_rfft_rows(const double *X, int rows, int len, int N, const double2 *twN,
+                            double2 *spec, hipStream_t stream);
+// half spectra [R_N][N/2+1] of the circulant embeddings of p [R_N][2n-1]
+hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, const double2 *twN,
+                                    double2 *spec, hipStream_t stream);
+// W_k[j][t] (t < n) for all j, k from the spectra; output binary64 W
+// [R_N][R_f][n] (W != nullptr) or int8 slices WS [4][R_N][R_f_pad][n_pad] with
+// exponents EW [R_N][R_f_pad] (W == nullptr; padding rows zeroed)
+hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, int N, int R_f,
+                           int R_N, const double2 *twN, double *W, int8_t *WS, int *EW,
+                           int R_f_pad, int n_pad, long wplane, hipStream_t stream);
+
 }  // namespace tc

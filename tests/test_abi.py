@@ -58,14 +58,23 @@ def test_workspace_bytes(L):
     I = _inst(n=100, R_f=10, R_N=3)
     arr = (_lib.TcInstance * 1)(I)
     w = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
-    # W of one mode + the three modes' Grams, each rounded up to 256 bytes
+    # W of one mode + the three modes' Grams + the FFT scratch of one mode
+    # (twiddles [N], spectra of U [R_f][N/2+1] and of the kernel [R_N][N/2+1],
+    # N = 256 for n = 100), each rounded up to 256 bytes
     up = lambda x: (x + 255) // 256 * 256
-    assert w == up(8 * 3 * 10 * 100) + up(8 * 3 * 3 * 100)
+    fft = up(16 * 256) + up(16 * 10 * 129) + up(16 * 3 * 129)
+    assert w == up(8 * 3 * 10 * 100) + up(8 * 3 * 3 * 100) + fft
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
-    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == up(8 * 3 * 10 * 100)
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
+        up(8 * 3 * 10 * 100) + fft
     wb = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_FP64)
-    assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100)
+    assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100) + fft
+    # no FFT scratch beyond the FFT route's size limit (n > 4096)
+    I = _inst(n=5000, R_f=2, R_N=1)
+    I.G_saved = 0x5000
+    arr = (_lib.TcInstance * 1)(I)
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == up(8 * 2 * 5000)
     bad = (_lib.TcInstance * 1)(_inst(n=0))
     assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, bad, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
     assert L.tc_workspace_bytes(7, arr, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
@@ -148,3 +157,27 @@ def test_product_path_has_no_fallback():
             src = open(os.path.join(pkg, f)).read()
             assert not re.search(r"^\s*(from\s+oracle|import\s+oracle)", src, flags=re.M), f
             assert "liboracle" not in src, f
+
+
+def test_tuning_table(L):
+    A = _lib.ALGORITHMS
+    # built-in rule: FFT from 256 cells up to the FFT size limit, direct otherwise
+    assert L.tc_tune_get(128, 8, 20, _lib.TC_FP64) == A["direct"]
+    assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["fft"]
+    assert L.tc_tune_get(5000, 8, 20, _lib.TC_FP64) == A["direct"]
+    assert L.tc_tune_set(1024, 8, 20, _lib.TC_FP64, A["direct"]) == _lib.TC_OK
+    assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["direct"]
+    assert L.tc_tune_get(1024, 8, 20, _lib.TC_OZAKI_I8) == A["fft"]   # other key untouched
+    assert L.tc_tune_set(1024, 8, 20, _lib.TC_FP64, A["auto"]) == _lib.TC_OK
+    assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["fft"]
+    assert L.tc_tune_set(5000, 8, 20, _lib.TC_FP64, A["fft"]) == _lib.TC_ERR_UNSUPPORTED
+    assert L.tc_tune_set(0, 8, 20, _lib.TC_FP64, A["fft"]) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tune_set(64, 8, 20, _lib.TC_FP64, 9) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_autotune_rejects(L):
+    arr = (_lib.TcInstance * 1)(_inst())
+    assert L.tc_autotune(arr, 1, _lib.TC_FP64, None, 0, None, None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_autotune(arr, 0, _lib.TC_FP64, None, 0, None, None) == _lib.TC_ERR_INVALID_ARG
+    bad = (_lib.TcInstance * 1)(_inst(null="J"))
+    assert L.tc_autotune(bad, 1, _lib.TC_FP64, None, 0, None, None) == _lib.TC_ERR_INVALID_ARG

@@ -8,6 +8,7 @@ at most about 2^-26 (max|x| |y|_1 + max|y| |x|_1); these tests use that bound
 for W = T U and for the Grams, and the target 1e-7 for the normalised error
 of J and for the relative error of the adjoint.
 """
+import contextlib
 import sys
 
 import numpy as np
@@ -18,6 +19,28 @@ from paper_1504_06289_amd import workloads as wl
 from tests.metrics import e_J, rel_fro
 
 pytestmark = pytest.mark.gpu
+
+
+ALGOS = ["direct", "fft"]
+
+
+@contextlib.contextmanager
+def algorithm(tc, algo, shapes, prec):
+    """Force the Toeplitz algorithm for the given (n, R_f, R_N) mode shapes."""
+    keys = sorted(set(shapes))
+    for key in keys:
+        if algo == "fft" and key[0] > 4096:
+            continue
+        tc.tune_set(*key, prec, algo)
+    try:
+        yield
+    finally:
+        for key in keys:
+            tc.tune_set(*key, prec, "auto")
+
+
+def shapes_of(w):
+    return [(nl, w.R_f, w.R_N) for nl in w.n]
 PREC = "ozaki8"
 TOL_J = 1e-7
 
@@ -65,13 +88,16 @@ def _setup(orc, w):
 @pytest.mark.parametrize("n,R_f,R_N", [(1, 1, 1), (5, 3, 2), (64, 64, 3), (100, 7, 4),
                                        (257, 130, 5), (1000, 65, 3)])
 def test_convolve_ozaki(tc, orc, n, R_f, R_N):
+    """The direct int8 route (the FFT route computes W in binary64 and is
+    covered by the FP64 parity tests)."""
     say(f"ozaki convolve n={n} R_f={R_f} R_N={R_N}")
     b = 6.0
     h = 2 * b / n
     u0, hu = wl.sinc_params(R_N, n, b)
     U, _ = wl.gaussian_products(n, b, R_f, seed=n + R_f)
     t, a, c, p = orc.newton_kernel(n, h, R_N, u0, hu)
-    W = host(tc.convolve(dev(p), dev(U[0]), prec=PREC))
+    with algorithm(tc, "direct", [(n, R_f, R_N)], PREC):
+        W = host(tc.convolve(dev(p), dev(U[0]), prec=PREC))
     Wr = orc.convolve(p, U[0])
     bound = split_bound_W(p, U[0])                    # [R_N][R_f]
     err = np.abs(W - Wr).max(axis=2)
@@ -84,7 +110,8 @@ def test_convolve_ozaki_asymmetric(tc, orc):
     n, R_f, R_N = 200, 19, 3
     p = rng.standard_normal((R_N, 2 * n - 1))
     U = rng.standard_normal((R_f, n))
-    W = host(tc.convolve(dev(p), dev(U), prec=PREC))
+    with algorithm(tc, "direct", [(n, R_f, R_N)], PREC):
+        W = host(tc.convolve(dev(p), dev(U), prec=PREC))
     Wr = orc.convolve(p, U)
     assert np.all(np.abs(W - Wr).max(axis=2) <= split_bound_W(p, U))
 
@@ -94,13 +121,15 @@ SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100
          ((300, 300, 300), 129, 8)]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", SMALL)
-def test_tei_gram_ozaki_small(tc, orc, n, R_f, R_N):
-    say(f"ozaki tei_gram n={n} R_f={R_f} R_N={R_N}")
+def test_tei_gram_ozaki_small(tc, orc, n, R_f, R_N, algo):
+    say(f"ozaki tei_gram n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=sum(n) + R_f)
     c, ps = _setup(orc, w)
-    J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC,
-                       save_G=True)
+    with algorithm(tc, algo, shapes_of(w), PREC):
+        J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC,
+                           save_G=True)
     Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
     J, G = host(J), host(G)
     err = e_J(J, Jr)
@@ -119,12 +148,14 @@ def test_tei_gram_ozaki_small(tc, orc, n, R_f, R_N):
         assert np.all(np.abs(G[l] - Gr[l]) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("name,ncols", [("c1", 8), ("c2", 12), ("c5", 6), ("c3", 6)])
-def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols):
-    say(f"ozaki tei_gram sampled {name}")
+def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols, algo):
+    say(f"ozaki tei_gram sampled {name} {algo}")
     w = wl.config(name)
     c, ps = _setup(orc, w)
-    J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC))
+    with algorithm(tc, algo, shapes_of(w), PREC):
+        J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC))
     rng = np.random.default_rng(321)
     S = np.sort(rng.choice(w.R_f, size=min(ncols, w.R_f), replace=False))
     Jc = orc.tei_gram_columns(c, ps, w.U, S)
@@ -147,18 +178,20 @@ def test_tei_gram_ozaki_deterministic(tc, orc):
                                   host(tc.tei_gram(*args, prec=PREC)))
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", [((24, 19, 28), 6, 6), ((100, 100, 100), 40, 5),
-                                       ((70, 130, 65), 67, 4)])
-def test_backward_ozaki(tc, orc, n, R_f, R_N):
-    say(f"ozaki backward n={n} R_f={R_f} R_N={R_N}")
+                                       ((70, 130, 300), 67, 4)])
+def test_backward_ozaki(tc, orc, n, R_f, R_N, algo):
+    say(f"ozaki backward n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
     c, ps = _setup(orc, w)
     rng = np.random.default_rng(5)
     wv = rng.standard_normal(R_f)
     Jb = np.outer(wv, wv)
     dUr = orc.tei_gram_backward(c, ps, w.U, Jb)
-    dU = tc.tei_gram_backward(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], dev(Jb),
-                              prec=PREC)
+    with algorithm(tc, algo, shapes_of(w), PREC):
+        dU = tc.tei_gram_backward(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], dev(Jb),
+                                  prec=PREC)
     for l in range(3):
         err = rel_fro(host(dU[l]), dUr[l])
         say(f"   mode {l}: rel err {err:.2e}")

@@ -9,6 +9,7 @@ degenerate sizes.  Tolerances (FP64 path):
   * J: normalised error max |dJ_ij| / sqrt(J_ii J_jj) <= 1e-12;
   * adjoint: relative Frobenius error <= 1e-12 per mode.
 """
+import contextlib
 import sys
 
 import numpy as np
@@ -19,6 +20,28 @@ from paper_1504_06289_amd import workloads as wl
 from tests.metrics import e_J, rel_fro
 
 pytestmark = pytest.mark.gpu
+
+
+ALGOS = ["direct", "fft"]
+
+
+@contextlib.contextmanager
+def algorithm(tc, algo, shapes, prec):
+    """Force the Toeplitz algorithm for the given (n, R_f, R_N) mode shapes."""
+    keys = sorted(set(shapes))
+    for key in keys:
+        if algo == "fft" and key[0] > 4096:
+            continue
+        tc.tune_set(*key, prec, algo)
+    try:
+        yield
+    finally:
+        for key in keys:
+            tc.tune_set(*key, prec, "auto")
+
+
+def shapes_of(w):
+    return [(nl, w.R_f, w.R_N) for nl in w.n]
 
 
 def say(*a):
@@ -69,32 +92,42 @@ def test_newton_kernel_parity(tc, orc, R_N, n, b):
 
 
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", [(1, 1, 1), (5, 3, 2), (64, 64, 3), (100, 7, 4),
-                                       (257, 130, 5), (1024, 33, 2)])
-def test_convolve_parity(tc, orc, n, R_f, R_N):
-    say(f"convolve n={n} R_f={R_f} R_N={R_N}")
+                                       (257, 130, 5), (1024, 33, 2), (4096, 9, 2)])
+def test_convolve_parity(tc, orc, n, R_f, R_N, algo):
+    say(f"convolve n={n} R_f={R_f} R_N={R_N} {algo}")
     b = 6.0
     h = 2 * b / n
     u0, hu = wl.sinc_params(R_N, n, b)
     U, _ = wl.gaussian_products(n, b, R_f, seed=n + R_f)
     t, a, c, pr = orc.newton_kernel(n, h, R_N, u0, hu)
-    W = host(tc.convolve(dev(pr), dev(U[0])))
+    with algorithm(tc, algo, [(n, R_f, R_N)], "fp64"):
+        W = host(tc.convolve(dev(pr), dev(U[0])))
     Wr = orc.convolve(pr, U[0])
-    bound = orc.convolve(np.abs(pr), np.abs(U[0]))
-    assert np.all(np.abs(W - Wr) <= 1e-13 * bound + 1e-300)
+    if algo == "direct":
+        bound = orc.convolve(np.abs(pr), np.abs(U[0]))
+        assert np.all(np.abs(W - Wr) <= 1e-13 * bound + 1e-300)
+    else:
+        # FFT rounding is spread over the row: |dW| <= 1e-14 |p|_2 |u|_2 log2(N) per row
+        scale = (np.linalg.norm(pr, axis=1)[:, None] * np.linalg.norm(U[0], axis=1)[None, :]
+                 * np.log2(2 * n + 2))[:, :, None]
+        assert np.all(np.abs(W - Wr) <= 1e-14 * scale + 1e-300)
 
 
-def test_convolve_asymmetric_kernel_lag_direction(tc, orc):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_convolve_asymmetric_kernel_lag_direction(tc, orc, algo):
     """A non-symmetric p pins the lag direction W[a] = sum_b p[a-b] u[b]."""
-    say("convolve asymmetric p")
+    say(f"convolve asymmetric p {algo}")
     rng = np.random.default_rng(1)
     n, R_f, R_N = 77, 19, 3
     p = rng.standard_normal((R_N, 2 * n - 1))
     U = rng.standard_normal((R_f, n))
-    W = host(tc.convolve(dev(p), dev(U)))
+    with algorithm(tc, algo, [(n, R_f, R_N)], "fp64"):
+        W = host(tc.convolve(dev(p), dev(U)))
     Wr = orc.convolve(p, U)
     bound = orc.convolve(np.abs(p), np.abs(U))
-    assert np.all(np.abs(W - Wr) <= 1e-13 * bound)
+    assert np.all(np.abs(W - Wr) <= 1e-13 * bound * (1 if algo == "direct" else 30))
 
 
 # --------------------------------------------------------------------------
@@ -111,12 +144,14 @@ SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100
          ((40, 33, 47), 9, 4), ((257, 257, 257), 70, 12), ((130, 64, 200), 65, 6)]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", SMALL)
-def test_tei_gram_parity_small(tc, orc, n, R_f, R_N):
-    say(f"tei_gram n={n} R_f={R_f} R_N={R_N}")
+def test_tei_gram_parity_small(tc, orc, n, R_f, R_N, algo):
+    say(f"tei_gram n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=sum(n) + R_f)
     c, ps = _setup(orc, w)
-    J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], save_G=True)
+    with algorithm(tc, algo, shapes_of(w), "fp64"):
+        J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], save_G=True)
     Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
     J, G = host(J), host(G)
     assert e_J(J, Jr) <= 1e-12
@@ -125,8 +160,14 @@ def test_tei_gram_parity_small(tc, orc, n, R_f, R_N):
     # |dG| <= 1e-13 |U|^T |T| |U| (p-type columns make G_ii much smaller than
     # that bound for the wide kernel terms, so a G_ii-relative bound is wrong)
     for l in range(3):
-        absG = orc.gram(np.abs(w.U[l]), orc.convolve(np.abs(ps[l]), np.abs(w.U[l])))
-        assert np.all(np.abs(G[l] - Gr[l]) <= 1e-13 * absG + 1e-300)
+        if algo == "direct":
+            absG = orc.gram(np.abs(w.U[l]), orc.convolve(np.abs(ps[l]), np.abs(w.U[l])))
+            assert np.all(np.abs(G[l] - Gr[l]) <= 1e-13 * absG + 1e-300)
+        else:
+            un = np.linalg.norm(w.U[l], axis=1)
+            pn = np.linalg.norm(ps[l], axis=1)
+            scale = pn[:, None, None] * un[None, :, None] * un[None, None, :]
+            assert np.all(np.abs(G[l] - Gr[l]) <= 1e-13 * scale + 1e-300)
 
 
 def test_tei_gram_single_cell(tc, orc):
@@ -157,15 +198,17 @@ def test_tei_gram_parity_c1(tc, orc):
         assert np.all(np.abs(W - Wr) <= 1e-13 * bound + 1e-300)
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("name,ncols", [("c2", 12), ("c5", 6), ("c3", 4)])
-def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols):
+def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols, algo):
     """Full-size workloads: the GPU J (whole matrix) against oracle columns
     on a seeded sample S; the S x S block is compared with the normalised
     metric using oracle diagonals only."""
-    say(f"tei_gram sampled {name}")
+    say(f"tei_gram sampled {name} {algo}")
     w = wl.config(name)
     c, ps = _setup(orc, w)
-    J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
+    with algorithm(tc, algo, shapes_of(w), "fp64"):
+        J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
     rng = np.random.default_rng(123)
     S = np.sort(rng.choice(w.R_f, size=ncols, replace=False))
     Jc = orc.tei_gram_columns(c, ps, w.U, S)          # [ncols][R_f]
@@ -182,13 +225,15 @@ def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols):
     assert np.all(np.diag(J) > 0)
 
 
-def test_tei_gram_deterministic(tc, orc):
-    say("tei_gram determinism")
+@pytest.mark.parametrize("algo", ALGOS)
+def test_tei_gram_deterministic(tc, orc, algo):
+    say(f"tei_gram determinism {algo}")
     w = wl.small_products(300, 100, R_N=9, b=6.0, seed=4)
     c, ps = _setup(orc, w)
     args = (dev(c), [dev(p) for p in ps], [dev(u) for u in w.U])
-    J1 = host(tc.tei_gram(*args))
-    J2 = host(tc.tei_gram(*args))
+    with algorithm(tc, algo, shapes_of(w), "fp64"):
+        J1 = host(tc.tei_gram(*args))
+        J2 = host(tc.tei_gram(*args))
     np.testing.assert_array_equal(J1, J2)
 
 
@@ -205,24 +250,26 @@ def test_tei_gram_batched_matches_single(tc, orc):
 
 
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", [((24, 19, 28), 6, 6), ((100, 100, 100), 40, 5),
-                                       ((70, 130, 65), 67, 4)])
-def test_backward_parity(tc, orc, n, R_f, R_N):
-    say(f"backward n={n} R_f={R_f} R_N={R_N}")
+                                       ((70, 130, 300), 67, 4)])
+def test_backward_parity(tc, orc, n, R_f, R_N, algo):
+    say(f"backward n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
     c, ps = _setup(orc, w)
     rng = np.random.default_rng(5)
     Jb = rng.standard_normal((R_f, R_f))
     dUr = orc.tei_gram_backward(c, ps, w.U, Jb)
     cd, pd, Ud = dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]
-    dU = tc.tei_gram_backward(cd, pd, Ud, dev(Jb))
-    for l in range(3):
-        assert rel_fro(host(dU[l]), dUr[l]) <= 1e-12
-    # with saved Grams
-    J, G = tc.tei_gram(cd, pd, Ud, save_G=True)
-    dU2 = tc.tei_gram_backward(cd, pd, Ud, dev(Jb), G=G)
-    for l in range(3):
-        assert rel_fro(host(dU2[l]), dUr[l]) <= 1e-12
+    with algorithm(tc, algo, shapes_of(w), "fp64"):
+        dU = tc.tei_gram_backward(cd, pd, Ud, dev(Jb))
+        for l in range(3):
+            assert rel_fro(host(dU[l]), dUr[l]) <= 1e-12
+        # with saved Grams
+        J, G = tc.tei_gram(cd, pd, Ud, save_G=True)
+        dU2 = tc.tei_gram_backward(cd, pd, Ud, dev(Jb), G=G)
+        for l in range(3):
+            assert rel_fro(host(dU2[l]), dUr[l]) <= 1e-12
 
 
 def test_autograd_function(tc, orc):
@@ -239,3 +286,16 @@ def test_autograd_function(tc, orc):
     dUr = orc.tei_gram_backward(c, ps, w.U, np.outer(wv, wv))
     for l in range(3):
         assert rel_fro(host(Us[l].grad), dUr[l]) <= 1e-12
+
+
+def test_autotune_records_a_choice(tc, orc):
+    say("autotune")
+    w = wl.small_products(512, 64, R_N=8, b=6.0, seed=12)
+    c, ps = _setup(orc, w)
+    ms = tc.autotune(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec="fp64")
+    say(f"   ms (direct, fft) per mode: {ms}")
+    for l in range(3):
+        d, f = ms[l]
+        assert d > 0 and f > 0
+        assert tc.tune_get(512, 64, 8, "fp64") == ("fft" if f < d else "direct")
+    tc.tune_set(512, 64, 8, "fp64", "auto")
