@@ -215,23 +215,24 @@ template <int SIGN> __device__ void fft_lds(cplx *buf, int M, const cplx *__rest
 // and keeps them in registers, so the passes touch only LDS.
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-template <int M> struct FftShape {
+template <int M, int RMAX> struct FftShape {
     static constexpr int LOG = ilog2c(M);
-    static constexpr int N16 = LOG / 4;
-    static constexpr int REM = LOG % 4;
-    static constexpr int NP = N16 + (REM ? 1 : 0);
-    static constexpr int radix(int p) { return p < N16 ? 16 : (1 << REM); }
+    static constexpr int LR = ilog2c(RMAX);
+    static constexpr int NFULL = LOG / LR;
+    static constexpr int REM = LOG % LR;
+    static constexpr int NP = NFULL + (REM ? 1 : 0);
+    static constexpr int radix(int p) { return p < NFULL ? RMAX : (1 << REM); }
     static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * radix(p - 1); }
 };
 
-template <int M, int SIGN> struct FftTwiddles {
-    cplx w[FftShape<M>::NP > 0 ? FftShape<M>::NP : 1][4];
+template <int M, int RMAX> struct FftTwiddles {
+    cplx w[FftShape<M, RMAX>::NP > 0 ? FftShape<M, RMAX>::NP : 1][4];
 };
 
-template <int M, int SIGN, int P>
-__device__ inline void load_twiddles_pass(FftTwiddles<M, SIGN> &T, const cplx *__restrict__ twN)
+template <int M, int RMAX, int T, int SIGN, int P>
+__device__ inline void load_twiddles_pass(FftTwiddles<M, RMAX> &Tw, const cplx *__restrict__ twN)
 {
-    using F = FftShape<M>;
+    using F = FftShape<M, RMAX>;
     if constexpr (P < F::NP) {
         constexpr int R = F::radix(P), Ns = F::ns(P);
         if constexpr (Ns > 1) {
@@ -242,25 +243,27 @@ __device__ inline void load_twiddles_pass(FftTwiddles<M, SIGN> &T, const cplx *_
                     const cplx x = twN[2 * s];
                     return SIGN > 0 ? cconj(x) : x;
                 };
-                T.w[P][0] = tw(step);
+                Tw.w[P][0] = tw(step);
                 if constexpr (R >= 4)
-                    T.w[P][1] = tw(2 * step);
+                    Tw.w[P][1] = tw(2 * step);
                 if constexpr (R >= 8)
-                    T.w[P][2] = tw(4 * step);
+                    Tw.w[P][2] = tw(4 * step);
                 if constexpr (R >= 16)
-                    T.w[P][3] = tw(8 * step);
+                    Tw.w[P][3] = tw(8 * step);
             }
         }
-        load_twiddles_pass<M, SIGN, P + 1>(T, twN);
+        load_twiddles_pass<M, RMAX, T, SIGN, P + 1>(Tw, twN);
     }
 }
 
-template <int M, int R, int Ns, int SIGN>
+// one in-place Stockham pass with T threads (M/R <= T butterflies)
+template <int M, int R, int Ns, int T, int SIGN>
 __device__ inline void pass_fixed(cplx *buf, const cplx *wb)
 {
     constexpr int nb = M / R;
+    static_assert(nb <= T, "one butterfly per thread");
     const int j = threadIdx.x;
-    const bool active = nb >= kThreads || j < nb;
+    const bool active = nb >= T || j < nb;
     cplx v[R];
     if (active) {
 #pragma unroll
@@ -296,13 +299,13 @@ __device__ inline void pass_fixed(cplx *buf, const cplx *wb)
     __syncthreads();
 }
 
-template <int M, int SIGN, int P>
-__device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, SIGN> &T)
+template <int M, int RMAX, int T, int SIGN, int P>
+__device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, RMAX> &Tw)
 {
-    using F = FftShape<M>;
+    using F = FftShape<M, RMAX>;
     if constexpr (P < F::NP) {
-        pass_fixed<M, F::radix(P), F::ns(P), SIGN>(buf, T.w[P]);
-        fft_fixed<M, SIGN, P + 1>(buf, T);
+        pass_fixed<M, F::radix(P), F::ns(P), T, SIGN>(buf, Tw.w[P]);
+        fft_fixed<M, RMAX, T, SIGN, P + 1>(buf, Tw);
     }
 }
 
@@ -405,16 +408,28 @@ __device__ inline void split4_i8(double x, int E, int8_t s[4])
 // product of the spectra.  Output either binary64 rows (W != nullptr, layout
 // [R_N][R_f][n]) or int8 slices (WS != nullptr, layout [4][R_N][R_f_pad][n_pad]
 // with exponents EW [R_N][R_f_pad]); blocks with j >= R_f write zero slices.
-// Each thread owns the frequency pairs (f, M - f), f = tid + 256 q <= M/2; the
-// spectrum of u_j is re-read (from cache) for every term.
+//
+// Each thread owns the frequency pairs (f, M - f), f = tid + 256 q <= M/2.
+// The spectrum of u_j and the split twiddles e^(-2 pi i f/N) stay in LDS for
+// all terms (with the transform buffer: 2.5 M complex = 160 KB at M = 4096),
+// and the kernel spectrum of term k+1 is loaded into registers while term k
+// is transformed, so the inner loop waits on no global load.
+constexpr int kConvThreads = 512;  // 8 waves: two per SIMD with one workgroup per CU
+constexpr int kConvRadix = 8;      // M/8 <= 512 butterflies per pass
+
 template <int M>
-__global__ __launch_bounds__(256, 2) void fft_conv_kernel(
+__global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx *__restrict__ Uspec, const cplx *__restrict__ Cspec, int n, int R_f, int R_N,
     const cplx *__restrict__ twN, double *__restrict__ W, int8_t *__restrict__ WS,
     int *__restrict__ EW, int R_f_pad, int n_pad, long wplane)
 {
-    constexpr int PAIRS = (M / 2 + 1 + kThreads - 1) / kThreads;
-    extern __shared__ cplx buf[];
+    constexpr int TT = kConvThreads;
+    constexpr int PAIRS = (M / 2 + 1 + TT - 1) / TT;
+    constexpr int HALF = M / 2 > 0 ? M / 2 : 1;
+    constexpr int SAMPLES = (M + TT - 1) / TT;
+    __shared__ cplx buf[M >= 8 ? M : 8];  // >= 8 entries for the block maximum
+    __shared__ cplx Ush[M];
+    __shared__ cplx twsh[HALF];
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
 
@@ -430,22 +445,42 @@ __global__ __launch_bounds__(256, 2) void fft_conv_kernel(
         return;
     }
 
-    FftTwiddles<M, +1> T;
-    load_twiddles_pass<M, +1, 0>(T, twN);
+    FftTwiddles<M, kConvRadix> Tw;
+    load_twiddles_pass<M, kConvRadix, TT, +1, 0>(Tw, twN);
 
     const cplx *Uj = Uspec + (long)j * (M + 1);
+    for (int f = tid; f < M; f += TT)
+        Ush[f] = Uj[f];
+    for (int f = tid; f < M / 2; f += TT)
+        twsh[f] = twN[f];
+    const cplx uM = Uj[M];  // only the pair (0, M) uses it
     constexpr double invM = 1.0 / (double)M;
 
-    for (int k = 0; k < R_N; ++k) {
+    // kernel spectrum of the current term at this thread's pairs
+    cplx cf[PAIRS], cg[PAIRS];
+    auto load_c = [&](int k) {
         const cplx *Ck = Cspec + (long)k * (M + 1);
-#pragma unroll 3
+#pragma unroll
         for (int q = 0; q < PAIRS; ++q) {
-            const int f = tid + kThreads * q;
+            const int f = tid + TT * q;
+            if (f <= M / 2) {
+                cf[q] = Ck[f];
+                cg[q] = Ck[M - f];
+            }
+        }
+    };
+    load_c(0);
+    __syncthreads();
+
+    for (int k = 0; k < R_N; ++k) {
+#pragma unroll
+        for (int q = 0; q < PAIRS; ++q) {
+            const int f = tid + TT * q;
             if (f <= M / 2) {
                 const int g = M - f;
-                const cplx wf = twN[f];
-                const cplx yf = cmul(Ck[f], Uj[f]);
-                const cplx yg = cmul(Ck[g], Uj[g]);
+                const cplx wf = f < M / 2 ? twsh[f] : make_double2(0.0, -1.0);  // w^(M/2) = -i
+                const cplx yf = cmul(cf[q], Ush[f]);
+                const cplx yg = cmul(cg[q], g < M ? Ush[g] : uM);
                 // Z[f] = E + i O,  E = (Y[f] + conj Y[g]) / 2,  O = (Y[f] - conj Y[g]) conj(w^f) / 2
                 {
                     const cplx E = cscale(cadd(yf, cconj(yg)), 0.5);
@@ -460,12 +495,14 @@ __global__ __launch_bounds__(256, 2) void fft_conv_kernel(
                 }
             }
         }
+        if (k + 1 < R_N)
+            load_c(k + 1);  // in flight during the transform
         __syncthreads();
-        fft_fixed<M, +1, 0>(buf, T);
+        fft_fixed<M, kConvRadix, TT, +1, 0>(buf, Tw);
 
         if (W) {
             double *Wrow = W + ((long)k * R_f + j) * n;
-            for (int m = tid; m < M; m += blockDim.x) {
+            for (int m = tid; m < M; m += TT) {
                 const cplx z = buf[pad(m)];
                 const int t = 2 * m;
                 if (t < n)
@@ -474,46 +511,61 @@ __global__ __launch_bounds__(256, 2) void fft_conv_kernel(
                     Wrow[t + 1] = z.y * invM;
             }
         } else {
+            cplx zs[SAMPLES];
             double amax = 0.0;
-            for (int m = tid; m < M; m += blockDim.x) {
-                const cplx z = buf[pad(m)];
-                const int t = 2 * m;
-                if (t < n)
-                    amax = fmax(amax, fabs(z.x));
-                if (t + 1 < n)
-                    amax = fmax(amax, fabs(z.y));
+#pragma unroll
+            for (int q = 0; q < SAMPLES; ++q) {
+                const int m = tid + TT * q;
+                zs[q] = make_double2(0.0, 0.0);
+                if (m < M) {
+                    const cplx z = buf[pad(m)];
+                    const int t = 2 * m;
+                    zs[q] = make_double2(t < n ? z.x * invM : 0.0, t + 1 < n ? z.y * invM : 0.0);
+                    amax = fmax(amax, fmax(fabs(zs[q].x), fabs(zs[q].y)));
+                }
             }
-            // block maximum through a small static array (the FFT buffer is still read below)
-            __shared__ double red[4];
+            // block maximum through the transform buffer (all reads above are done)
             for (int o = 32; o > 0; o >>= 1)
                 amax = fmax(amax, __shfl_xor(amax, o));
-            if ((tid & 63) == 0)
-                red[tid >> 6] = amax;
             __syncthreads();
-            amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * invM;
+            if ((tid & 63) == 0)
+                buf[tid >> 6].x = amax;
+            __syncthreads();
+            amax = buf[0].x;
+#pragma unroll
+            for (int wv = 1; wv < TT / 64; ++wv)
+                amax = fmax(amax, buf[wv].x);
             const int E = row_exp(amax);
             if (tid == 0)
                 EW[(long)k * R_f_pad + j] = E;
             int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
-            for (int m = tid; 2 * m < n_pad; m += blockDim.x) {
-                const int t = 2 * m;
-                int8_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
-                if (m < M) {
-                    const cplx z = buf[pad(m)];
-                    if (t < n)
-                        split4_i8(z.x * invM, E, s0);
-                    if (t + 1 < n)
-                        split4_i8(z.y * invM, E, s1);
-                }
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const unsigned short two = (unsigned short)((unsigned char)s0[s] |
-                                                                ((unsigned)(unsigned char)s1[s] << 8));
-                    *reinterpret_cast<unsigned short *>(row + s * wplane + t) = two;
+            for (int q = 0; q < SAMPLES; ++q) {
+                const int m = tid + TT * q;
+                const int t = 2 * m;
+                if (t < n_pad) {
+                    int8_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+                    if (m < M) {
+                        if (t < n)
+                            split4_i8(zs[q].x, E, s0);
+                        if (t + 1 < n)
+                            split4_i8(zs[q].y, E, s1);
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const unsigned short two =
+                            (unsigned short)((unsigned char)s0[s] |
+                                             ((unsigned)(unsigned char)s1[s] << 8));
+                        *reinterpret_cast<unsigned short *>(row + s * wplane + t) = two;
+                    }
                 }
             }
+            // samples beyond M (n_pad > 2M happens only for tiny grids): zero
+            for (int t = 2 * M + 2 * tid; t < n_pad; t += 2 * TT)
+                for (int s = 0; s < 4; ++s)
+                    *reinterpret_cast<unsigned short *>(row + s * wplane + t) = 0;
         }
-        __syncthreads();  // buf and red are rewritten by the next term
+        __syncthreads();  // buf is rewritten by the next term
     }
 }
 
@@ -563,8 +615,9 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
     const int blocks = W ? R_f : R_f_pad;
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
-        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(256), lds_bytes(MM), stream, \
-                           Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane);  \
+        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(kConvThreads), 0, stream,    \
+                           Uspec, Cspec,                                                        \
+                           n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane);               \
         break;
     switch (M) {
         TC_FFT_CONV_CASE(1)
