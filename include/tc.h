@@ -145,11 +145,17 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev,
 /*
  * tc_tei_gram -- the TEI/Coulomb matrix of every instance (Section 3.2):
  * J = sum_k c_k G^1_k o G^2_k o G^3_k with G^l_k = U^l^T T^l_k U^l.
- * Instances are independent; their buffers must not overlap one another.
- * When G_saved is non-NULL the Grams are also written there (the backward
- * pass can then skip recomputing them).
+ * Instances are independent; their output buffers must not overlap one
+ * another.  When G_saved is non-NULL the Grams are also written there (the
+ * backward pass can then skip recomputing them).
  *   inst  host array of count descriptors (pointers inside are device).
  *   count >= 1.   ws: tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec).
+ * With count > 1 the instances run concurrently on four internal streams of
+ * default priority (created at the first such call and kept for the life of
+ * the process) that fork from and join back into `stream` through events,
+ * so the call still completes in stream order and can be captured as one
+ * graph with parallel branches.  Calls with count > 1 from several host
+ * threads are serialised while they enqueue.
  */
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec,
                       void *ws, size_t ws_bytes, void *stream);

@@ -245,3 +245,50 @@ def profile_read(max_kernels: int = 64) -> dict:
     if nk < 0:
         raise RuntimeError("tc_profile_read: event query failed")
     return {names[i].value.decode(): (float(ms[i]), int(calls[i])) for i in range(min(nk, max_kernels))}
+
+
+class TeiGramGraph:
+    """A batch of TEI problems captured once into a HIP graph and replayed.
+
+    instances: sequence of (c, p3, U3) device tensors (as for tei_gram_batched).
+    The outputs J (one [R_f][R_f] tensor per instance) and the workspace are
+    allocated once; replay() re-runs every kernel of tc_tei_gram(count) with
+    one graph launch, reading the current contents of the input tensors.
+    The tuning table is consulted at capture time (the captured kernels are
+    fixed).  Kernel timing (profile_enable) must be off while capturing.
+    """
+
+    def __init__(self, instances, prec="fp64"):
+        self.dev = instances[0][2][0].device
+        self.prec = prec
+        self.Js = []
+        self.arr = (TcInstance * len(instances))()
+        for i, (c, p3, U3) in enumerate(instances):
+            R_f = U3[0].shape[0]
+            J = torch.empty((R_f, R_f), dtype=torch.float64, device=self.dev)
+            self.arr[i] = make_instance(c, p3, U3, J, None)
+            self.Js.append(J)
+        self._keep = instances  # the graph reads these buffers
+        L = _lib.lib()
+        self.ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, self.arr, len(instances),
+                                             _prec(prec))
+        if self.ws_bytes == ctypes.c_size_t(-1).value:
+            raise ValueError("invalid problem sizes")
+        self.ws = _workspace(self.ws_bytes, self.dev)
+        side = torch.cuda.Stream(self.dev)
+        side.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(side):
+            self._launch()  # eager warm-up on the side stream
+        torch.cuda.current_stream(self.dev).wait_stream(side)
+        torch.cuda.synchronize(self.dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._launch()
+
+    def _launch(self):
+        check(_lib.lib().tc_tei_gram(self.arr, len(self.arr), _prec(self.prec), _ptr(self.ws),
+                                     self.ws_bytes, _stream(self.dev)), "tc_tei_gram")
+
+    def replay(self):
+        self.graph.replay()
+        return self.Js

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <set>
@@ -301,6 +302,87 @@ size_t convolve_ws(int n, int R_f, int R_N, tc_precision prec)
     return c.used;
 }
 
+// ---------------------------------------------------------------------------
+// batches: independent instances run on a fixed pool of internal streams
+// (created once, default priority), forked from and joined back into the
+// caller's stream with events, so a captured batch is one graph with
+// parallel branches.  Instances are assigned greedily (largest first) to the
+// least-loaded branch; each branch owns one workspace region sized for its
+// largest instance.
+// ---------------------------------------------------------------------------
+constexpr int kBranches = 4;
+
+double instance_cost(const tc_instance &I)
+{
+    double c = 0.0;
+    for (int l = 0; l < 3; ++l) {
+        const double n = I.n[l], f = I.R_f;
+        c += I.R_N * (n * std::log2(n + 1.0) * f + n * f * f);
+    }
+    return c;
+}
+
+struct BatchPlan {
+    std::vector<int> branch;       // branch of each instance
+    size_t offset[kBranches] = {};  // workspace region of each branch
+    size_t bytes = 0;
+};
+
+BatchPlan plan_batch(const tc_instance *inst, int count, tc_precision prec)
+{
+    BatchPlan B;
+    B.branch.assign(count, 0);
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return instance_cost(inst[a]) > instance_cost(inst[b]);
+    });
+    double load[kBranches] = {};
+    size_t need[kBranches] = {};
+    for (int i : order) {
+        int best = 0;
+        for (int b = 1; b < kBranches; ++b)
+            if (load[b] < load[best])
+                best = b;
+        B.branch[i] = best;
+        load[best] += instance_cost(inst[i]);
+        const size_t wi = plan_instance(nullptr, inst[i], prec, false).bytes;
+        if (wi > need[best])
+            need[best] = wi;
+    }
+    for (int b = 0; b < kBranches; ++b) {
+        B.offset[b] = B.bytes;
+        B.bytes += align_up(need[b]);
+    }
+    return B;
+}
+
+struct BranchPool {
+    bool ok = false;
+    hipStream_t st[kBranches] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBranches] = {};
+};
+std::mutex g_pool_mu;
+BranchPool g_pool;
+
+bool pool_init()
+{
+    if (g_pool.ok)
+        return true;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamCreateWithFlags(&g_pool.st[b], hipStreamNonBlocking) != hipSuccess)
+            return false;
+    if (hipEventCreateWithFlags(&g_pool.fork, hipEventDisableTiming) != hipSuccess)
+        return false;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipEventCreateWithFlags(&g_pool.join[b], hipEventDisableTiming) != hipSuccess)
+            return false;
+    g_pool.ok = true;
+    return true;
+}
+
 tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st)
 {
     const InstancePlan P = plan_instance(ws, I, prec, false);
@@ -378,11 +460,14 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
     }
     if (op != TC_OP_TEI_GRAM && op != TC_OP_TEI_GRAM_BACKWARD)
         return (size_t)-1;
-    size_t w = 0;
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < count; ++i)
         for (int l = 0; l < 3; ++l)
             if (!size_ok(inst[i].n[l], inst[i].R_f, inst[i].R_N))
                 return (size_t)-1;
+    if (op == TC_OP_TEI_GRAM && count > 1)
+        return plan_batch(inst, count, prec).bytes;
+    size_t w = 0;
+    for (int i = 0; i < count; ++i) {
         const size_t wi =
             plan_instance(nullptr, inst[i], prec, op == TC_OP_TEI_GRAM_BACKWARD).bytes;
         if (wi > w)
@@ -470,12 +555,32 @@ tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec, voi
     const size_t need = tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec);
     if (need > 0 && (!ws || ws_bytes < need))
         return TC_ERR_WORKSPACE;
-    for (int i = 0; i < count; ++i) {
-        const tc_status s = forward_instance(inst[i], prec, ws, (hipStream_t)stream);
-        if (s != TC_OK)
-            return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (count == 1)
+        return forward_instance(inst[0], prec, ws, st);
+
+    const BatchPlan B = plan_batch(inst, count, prec);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!pool_init())
+        return TC_ERR_HIP;
+    // fork: every branch waits for the work already queued on the caller's stream
+    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
+            return TC_ERR_HIP;
+    tc_status status = TC_OK;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const int b = B.branch[i];
+        status = forward_instance(inst[i], prec, (char *)ws + B.offset[b], g_pool.st[b]);
     }
-    return TC_OK;
+    // join (also after a failed launch, so no branch is left forked)
+    for (int b = 0; b < kBranches; ++b) {
+        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+    }
+    return status;
 }
 
 tc_status tc_tei_gram_backward(const tc_instance *inst, int count, const double *const *Jbar,

@@ -181,3 +181,16 @@ def test_autotune_rejects(L):
     assert L.tc_autotune(arr, 0, _lib.TC_FP64, None, 0, None, None) == _lib.TC_ERR_INVALID_ARG
     bad = (_lib.TcInstance * 1)(_inst(null="J"))
     assert L.tc_autotune(bad, 1, _lib.TC_FP64, None, 0, None, None) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_batch_workspace_is_per_branch(L):
+    """A batch is spread over 4 branches, each with its own workspace region
+    sized for its largest instance."""
+    insts = [_inst(n=64, R_f=8, R_N=4) for _ in range(6)]
+    arr = (_lib.TcInstance * 6)(*insts)
+    one = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
+    six = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 6, _lib.TC_FP64)
+    up = lambda x: (x + 255) // 256 * 256
+    assert six == 4 * up(one)
+    two = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 2, _lib.TC_FP64)
+    assert two == 2 * up(one)
