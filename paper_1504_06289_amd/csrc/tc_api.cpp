@@ -35,7 +35,7 @@ bool prec_known(tc_precision prec)
     return prec == TC_FP64 || prec == TC_FP32 || prec == TC_OZAKI_I8;
 }
 
-bool prec_supported(tc_precision prec) { return prec == TC_FP64 || prec == TC_OZAKI_I8; }
+bool prec_supported(tc_precision prec) { return prec_known(prec); }
 
 bool instance_ok(const tc_instance &I)
 {
@@ -116,6 +116,12 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
             s.WS = c.take<int8_t>(4 * (size_t)L.wplane);
             s.EW = c.take<int>((size_t)R_N * L.R_f_pad);
         }
+    }
+    if (prec == TC_FP32) {
+        s.EU = c.take<int>(R_f);
+        s.EP = c.take<int>(R_N);
+        if (gram)
+            s.EW = c.take<int>((size_t)R_N * R_f);
     }
     if (fft_supported(n)) {
         const int N = fft_length(n);
@@ -221,6 +227,12 @@ tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, 
         TRYK("toeplitz_f64", launch_toeplitz_f64(p, U, W, n, R_f, R_N, st));
         return TC_OK;
     }
+    if (prec == TC_FP32) {
+        TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.EU, st));
+        TRYK("row_exponents", launch_row_exponents(p, R_N, 2 * n - 1, s.EP, st));
+        TRYK("toeplitz_f32", launch_toeplitz_f32(p, s.EP, U, s.EU, W, n, R_f, R_N, st));
+        return TC_OK;
+    }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
     TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
     TRYK("split_kernel_vectors", launch_split_kernel_vectors(p, n, R_N, L, s.PS, s.EP, st));
@@ -238,6 +250,15 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         if (r != TC_OK)
             return r;
         TRYK("gram_f64", launch_gram_f64(U, W, G, n, R_f, R_N, st));
+        return TC_OK;
+    }
+    if (prec == TC_FP32) {
+        const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
+        if (r != TC_OK)
+            return r;
+        TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.EU, st));
+        TRYK("row_exponents", launch_row_exponents(W, (long)R_N * R_f, n, s.EW, st));
+        TRYK("gram_f32", launch_gram_f32(U, s.EU, W, s.EW, G, n, R_f, R_N, st));
         return TC_OK;
     }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);

@@ -25,6 +25,20 @@ hipError_t launch_toeplitz_f64(const double *p, const double *U, double *W, int 
 hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n,
                            int R_f, int R_N, hipStream_t stream);
 
+// ---- binary32 matrix-core variants (fp32.hip) ------------------------------
+// E[r] = exponent of the largest |X[r][.]| (max < 2^E[r]; 0 for a zero row).
+hipError_t launch_row_exponents(const double *X, long rows, int len, int *E,
+                                hipStream_t stream);
+// Same results as launch_toeplitz_f64 / launch_gram_f64 with every operand
+// row scaled by 2^-E (E from launch_row_exponents: EU per row of U, EP per
+// kernel term, EW per row of W), rounded to binary32, binary32 partial sums
+// over K-chunks of 64, binary64 accumulation of the chunk sums, and the
+// scale put back on the binary64 result.
+hipError_t launch_toeplitz_f32(const double *p, const int *EP, const double *U, const int *EU,
+                               double *W, int n, int R_f, int R_N, hipStream_t stream);
+hipError_t launch_gram_f32(const double *U, const int *EU, const double *W, const int *EW,
+                           double *G, int n, int R_f, int R_N, hipStream_t stream);
+
 // ---- Hadamard product across modes and sum over k (reduce.hip) -----------
 // J[e] = sum_k c[k] G0[k][e] G1[k][e] G2[k][e], e < R_f*R_f.
 hipError_t launch_hadamard_sum(const double *c, const double *G0, const double *G1,

@@ -19,3 +19,13 @@ def orc():
     from oracle import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def tc():
+    """The HIP library's Python binding; a GPU test without a GPU fails."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1504_06289_amd as tc
+    return tc

@@ -8,63 +8,20 @@ at most about 2^-26 (max|x| |y|_1 + max|y| |x|_1); these tests use that bound
 for W = T U and for the Grams, and the target 1e-7 for the normalised error
 of J and for the relative error of the adjoint.
 """
-import contextlib
-import sys
 
 import numpy as np
 import pytest
-import torch
 
 from paper_1504_06289_amd import workloads as wl
+from tests.gpu_common import algorithm, dev, host, oracle_setup, say, shapes_of
 from tests.metrics import e_J, rel_fro
 
 pytestmark = pytest.mark.gpu
 
 
 ALGOS = ["direct", "fft"]
-
-
-@contextlib.contextmanager
-def algorithm(tc, algo, shapes, prec):
-    """Force the Toeplitz algorithm for the given (n, R_f, R_N) mode shapes."""
-    keys = sorted(set(shapes))
-    for key in keys:
-        if algo == "fft" and key[0] > 4096:
-            continue
-        tc.tune_set(*key, prec, algo)
-    try:
-        yield
-    finally:
-        for key in keys:
-            tc.tune_set(*key, prec, "auto")
-
-
-def shapes_of(w):
-    return [(nl, w.R_f, w.R_N) for nl in w.n]
 PREC = "ozaki8"
 TOL_J = 1e-7
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-@pytest.fixture(scope="module")
-def tc():
-    if not torch.cuda.is_available():
-        pytest.fail("no GPU visible")
-    import paper_1504_06289_amd as tc
-    return tc
-
-
-def dev(x):
-    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
-
-
-def host(x):
-    torch.cuda.synchronize()
-    return x.detach().cpu().numpy()
 
 
 def split_bound_W(p, U):
@@ -74,15 +31,6 @@ def split_bound_W(p, U):
     um = np.abs(U).max(axis=1)
     u1 = np.abs(U).sum(axis=1)
     return 2.0 ** -26 * (pm[:, None] * u1[None, :] + um[None, :] * p1[:, None])
-
-
-def _setup(orc, w):
-    ps = []
-    for l in range(3):
-        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
-        ps.append(p)
-    c = a * w.h[0] * w.h[1] * w.h[2]
-    return c, ps
 
 
 @pytest.mark.parametrize("n,R_f,R_N", [(1, 1, 1), (5, 3, 2), (64, 64, 3), (100, 7, 4),
@@ -126,7 +74,7 @@ SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100
 def test_tei_gram_ozaki_small(tc, orc, n, R_f, R_N, algo):
     say(f"ozaki tei_gram n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=sum(n) + R_f)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     with algorithm(tc, algo, shapes_of(w), PREC):
         J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC,
                            save_G=True)
@@ -153,7 +101,7 @@ def test_tei_gram_ozaki_small(tc, orc, n, R_f, R_N, algo):
 def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols, algo):
     say(f"ozaki tei_gram sampled {name} {algo}")
     w = wl.config(name)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     with algorithm(tc, algo, shapes_of(w), PREC):
         J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC))
     rng = np.random.default_rng(321)
@@ -172,7 +120,7 @@ def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols, algo):
 def test_tei_gram_ozaki_deterministic(tc, orc):
     say("ozaki determinism")
     w = wl.small_products(300, 100, R_N=9, b=6.0, seed=4)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     args = (dev(c), [dev(p) for p in ps], [dev(u) for u in w.U])
     np.testing.assert_array_equal(host(tc.tei_gram(*args, prec=PREC)),
                                   host(tc.tei_gram(*args, prec=PREC)))
@@ -184,7 +132,7 @@ def test_tei_gram_ozaki_deterministic(tc, orc):
 def test_backward_ozaki(tc, orc, n, R_f, R_N, algo):
     say(f"ozaki backward n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     rng = np.random.default_rng(5)
     wv = rng.standard_normal(R_f)
     Jb = np.outer(wv, wv)
@@ -201,7 +149,7 @@ def test_backward_ozaki(tc, orc, n, R_f, R_N, algo):
 def test_autograd_ozaki(tc, orc):
     say("ozaki autograd")
     w = wl.small_products(90, 20, R_N=6, b=6.0, seed=3)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     wv = np.random.default_rng(8).standard_normal(w.R_f)
     Us = [dev(u).requires_grad_(True) for u in w.U]
     J = tc.TeiGram.apply(dev(c), dev(ps[0]), dev(ps[1]), dev(ps[2]), *Us, PREC)

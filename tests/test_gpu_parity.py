@@ -9,61 +9,19 @@ degenerate sizes.  Tolerances (FP64 path):
   * J: normalised error max |dJ_ij| / sqrt(J_ii J_jj) <= 1e-12;
   * adjoint: relative Frobenius error <= 1e-12 per mode.
 """
-import contextlib
-import sys
 
 import numpy as np
 import pytest
 import torch
 
 from paper_1504_06289_amd import workloads as wl
+from tests.gpu_common import algorithm, dev, host, oracle_setup, say, shapes_of
 from tests.metrics import e_J, rel_fro
 
 pytestmark = pytest.mark.gpu
 
 
 ALGOS = ["direct", "fft"]
-
-
-@contextlib.contextmanager
-def algorithm(tc, algo, shapes, prec):
-    """Force the Toeplitz algorithm for the given (n, R_f, R_N) mode shapes."""
-    keys = sorted(set(shapes))
-    for key in keys:
-        if algo == "fft" and key[0] > 4096:
-            continue
-        tc.tune_set(*key, prec, algo)
-    try:
-        yield
-    finally:
-        for key in keys:
-            tc.tune_set(*key, prec, "auto")
-
-
-def shapes_of(w):
-    return [(nl, w.R_f, w.R_N) for nl in w.n]
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-@pytest.fixture(scope="module")
-def tc():
-    if not torch.cuda.is_available():
-        pytest.fail("no GPU visible")
-    import paper_1504_06289_amd as tc
-    return tc
-
-
-def dev(x):
-    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
-
-
-def host(x):
-    torch.cuda.synchronize()
-    return x.detach().cpu().numpy()
 
 
 def kernel_tol(t, h, n):
@@ -131,13 +89,6 @@ def test_convolve_asymmetric_kernel_lag_direction(tc, orc, algo):
 
 
 # --------------------------------------------------------------------------
-def _setup(orc, w):
-    ps = []
-    for l in range(3):
-        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
-        ps.append(p)
-    c = a * w.h[0] * w.h[1] * w.h[2]
-    return c, ps
 
 
 SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100, 100), 33, 7),
@@ -149,7 +100,7 @@ SMALL = [((1, 1, 1), 1, 1), ((8, 8, 8), 2, 3), ((64, 64, 64), 16, 5), ((100, 100
 def test_tei_gram_parity_small(tc, orc, n, R_f, R_N, algo):
     say(f"tei_gram n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=sum(n) + R_f)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     with algorithm(tc, algo, shapes_of(w), "fp64"):
         J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], save_G=True)
     Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
@@ -186,7 +137,7 @@ def test_tei_gram_parity_c1(tc, orc):
     """The 128-cell, 8-function s-Gaussian workload, with its potential factors."""
     say("tei_gram c1")
     w = wl.config("c1")
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     t, cg, pg = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu)
     J = host(tc.tei_gram(torch.from_numpy(cg).cuda(), [pg, pg, pg], [dev(u) for u in w.U]))
     Jr = orc.tei_gram(c, ps, w.U)
@@ -206,7 +157,7 @@ def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols, algo):
     metric using oracle diagonals only."""
     say(f"tei_gram sampled {name} {algo}")
     w = wl.config(name)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     with algorithm(tc, algo, shapes_of(w), "fp64"):
         J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
     rng = np.random.default_rng(123)
@@ -229,7 +180,7 @@ def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols, algo):
 def test_tei_gram_deterministic(tc, orc, algo):
     say(f"tei_gram determinism {algo}")
     w = wl.small_products(300, 100, R_N=9, b=6.0, seed=4)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     args = (dev(c), [dev(p) for p in ps], [dev(u) for u in w.U])
     with algorithm(tc, algo, shapes_of(w), "fp64"):
         J1 = host(tc.tei_gram(*args))
@@ -242,7 +193,7 @@ def test_tei_gram_batched_matches_single(tc, orc):
     insts = []
     for i, (n, R_f, R_N) in enumerate([(64, 10, 4), (130, 37, 6), (33, 5, 3)]):
         w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=i)
-        c, ps = _setup(orc, w)
+        c, ps = oracle_setup(orc, w)
         insts.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
     Js = [host(J) for J in tc.tei_gram_batched(insts)]
     for (c, ps, Us), Jb in zip(insts, Js):
@@ -256,7 +207,7 @@ def test_tei_gram_batched_matches_single(tc, orc):
 def test_backward_parity(tc, orc, n, R_f, R_N, algo):
     say(f"backward n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     rng = np.random.default_rng(5)
     Jb = rng.standard_normal((R_f, R_f))
     dUr = orc.tei_gram_backward(c, ps, w.U, Jb)
@@ -275,7 +226,7 @@ def test_backward_parity(tc, orc, n, R_f, R_N, algo):
 def test_autograd_function(tc, orc):
     say("autograd TeiGram")
     w = wl.small_products(90, 20, R_N=6, b=6.0, seed=3)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     rng = np.random.default_rng(8)
     wv = rng.standard_normal(w.R_f)
     Us = [dev(u).requires_grad_(True) for u in w.U]
@@ -291,7 +242,7 @@ def test_autograd_function(tc, orc):
 def test_autotune_records_a_choice(tc, orc):
     say("autotune")
     w = wl.small_products(512, 64, R_N=8, b=6.0, seed=12)
-    c, ps = _setup(orc, w)
+    c, ps = oracle_setup(orc, w)
     ms = tc.autotune(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec="fp64")
     say(f"   ms (direct, fft) per mode: {ms}")
     for l in range(3):
@@ -310,7 +261,7 @@ def test_graph_replays_match_eager(tc, orc, prec):
     insts, refs = [], []
     for i, (n, R_f, R_N) in enumerate([(300, 40, 6), (130, 70, 5), (64, 9, 4)]):
         w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=40 + i)
-        c, ps = _setup(orc, w)
+        c, ps = oracle_setup(orc, w)
         insts.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
         refs.append(orc.tei_gram(c, ps, w.U))
     eager = [host(J) for J in tc.tei_gram_batched(insts, prec=prec)]
