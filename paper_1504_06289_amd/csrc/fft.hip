@@ -426,7 +426,6 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     constexpr int TT = kConvThreads;
     constexpr int PAIRS = (M / 2 + 1 + TT - 1) / TT;
     constexpr int HALF = M / 2 > 0 ? M / 2 : 1;
-    constexpr int SAMPLES = (M + TT - 1) / TT;
     __shared__ cplx buf[M >= 8 ? M : 8];  // >= 8 entries for the block maximum
     __shared__ cplx Ush[M];
     __shared__ cplx twsh[HALF];
@@ -511,18 +510,22 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                     Wrow[t + 1] = z.y * invM;
             }
         } else {
-            cplx zs[SAMPLES];
+            // thread tid owns the eight samples t = 8 tid .. 8 tid + 7 (the
+            // complex outputs m = 4 tid .. 4 tid + 3), so each slice row gets one
+            // 8-byte store per thread; n_pad <= 8 TT on this route
+            const bool own = 8 * tid < n_pad;
+            double zs[8];
             double amax = 0.0;
 #pragma unroll
-            for (int q = 0; q < SAMPLES; ++q) {
-                const int m = tid + TT * q;
-                zs[q] = make_double2(0.0, 0.0);
-                if (m < M) {
-                    const cplx z = buf[pad(m)];
-                    const int t = 2 * m;
-                    zs[q] = make_double2(t < n ? z.x * invM : 0.0, t + 1 < n ? z.y * invM : 0.0);
-                    amax = fmax(amax, fmax(fabs(zs[q].x), fabs(zs[q].y)));
-                }
+            for (int q = 0; q < 4; ++q) {
+                const int m = 4 * tid + q;
+                const int t = 2 * m;
+                cplx z = make_double2(0.0, 0.0);
+                if (own && m < M)
+                    z = buf[pad(m)];
+                zs[2 * q] = t < n ? z.x * invM : 0.0;
+                zs[2 * q + 1] = t + 1 < n ? z.y * invM : 0.0;
+                amax = fmax(amax, fmax(fabs(zs[2 * q]), fabs(zs[2 * q + 1])));
             }
             // block maximum through the transform buffer (all reads above are done)
             for (int o = 32; o > 0; o >>= 1)
@@ -538,32 +541,21 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
             const int E = row_exp(amax);
             if (tid == 0)
                 EW[(long)k * R_f_pad + j] = E;
-            int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
+            if (own) {
+                unsigned long long packed[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < SAMPLES; ++q) {
-                const int m = tid + TT * q;
-                const int t = 2 * m;
-                if (t < n_pad) {
-                    int8_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
-                    if (m < M) {
-                        if (t < n)
-                            split4_i8(zs[q].x, E, s0);
-                        if (t + 1 < n)
-                            split4_i8(zs[q].y, E, s1);
-                    }
+                for (int q = 0; q < 8; ++q) {
+                    int8_t d[4];
+                    split4_i8(zs[q], E, d);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const unsigned short two =
-                            (unsigned short)((unsigned char)s0[s] |
-                                             ((unsigned)(unsigned char)s1[s] << 8));
-                        *reinterpret_cast<unsigned short *>(row + s * wplane + t) = two;
-                    }
+                    for (int s = 0; s < 4; ++s)
+                        packed[s] |= (unsigned long long)(unsigned char)d[s] << (8 * q);
                 }
-            }
-            // samples beyond M (n_pad > 2M happens only for tiny grids): zero
-            for (int t = 2 * M + 2 * tid; t < n_pad; t += 2 * TT)
+                int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad + 8 * tid;
+#pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    *reinterpret_cast<unsigned short *>(row + s * wplane + t) = 0;
+                    *reinterpret_cast<unsigned long long *>(row + s * wplane) = packed[s];
+            }
         }
         __syncthreads();  // buf is rewritten by the next term
     }
@@ -613,6 +605,8 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
 {
     const int M = N / 2;
     const int blocks = W ? R_f : R_f_pad;
+    if (!W && (n_pad > 8 * kConvThreads || n_pad % 8 != 0))
+        return hipErrorInvalidValue;  // one 8-byte slice chunk per thread
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
         hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(kConvThreads), 0, stream,    \

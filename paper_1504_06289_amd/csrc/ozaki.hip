@@ -410,51 +410,63 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
         }
 }
 
-// Large-tile variant for R_f >= 256: 128 x 128 tiles, waves 2 x 2 of
-// 64 x 64 (4 x 4 MFMA blocks, 256 accumulator registers), K-step 64.  The
+// Large-tile variant for R_f >= 256: 128 x 128 tiles, K-step 64, eight
+// waves (512 threads) in 4 x 2 of 32 x 64 (2 x 4 MFMA blocks, 128
+// accumulator registers), so two waves share each SIMD and one wave's LDS
+// reads and barrier waits overlap the other's matrix-core work.  The
 // per-workgroup operand traffic per multiply-add halves compared with the
-// 64 x 64 tiles.  Work items are (tile, k) with k grouped by XCD (work item
-// w runs on XCD w mod 8), so the workgroups of one term run on one XCD and
-// re-read that term's W slices from its L2.
+// 64 x 64 tiles.
+//
+// Work items are (k, tile) with k grouped by XCD (work item w runs on XCD
+// w mod 8), and the tiles of one term are enumerated column by column
+// (tj outer, ti <= tj inner), so the workgroups in flight on one XCD share
+// the W slices of one column block and re-read them from that XCD's L2.
+//
+// LDS rows are unpadded (64 B) with the 16-byte chunks of row r permuted by
+// c ^ swz(r): then the staging writes (four lanes per row) and the fragment
+// reads (sixteen consecutive rows, one chunk) hit distinct banks both for 8-
+// and for 16-lane service groups.
 constexpr int GT2 = 128;
-constexpr int G2_BYTES = 4 * GT2 * AROW;  // 40960 per operand
+constexpr int GW_ROW = 64;
+constexpr int GW_PLANE = GT2 * GW_ROW;    // one slice of one operand
+constexpr int GW_BYTES = 4 * GW_PLANE;    // 32768 per operand
+__device__ inline int gw_offset(int sl, int row, int c16)
+{
+    const int swz = ((row >> 1) ^ (row >> 2)) & 3;
+    return sl * GW_PLANE + row * GW_ROW + 16 * (c16 ^ swz);
+}
 
-__global__ __launch_bounds__(256) void gram_i8_big_kernel(
+__global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
-    int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntiles, int ntri)
+    int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri)
 {
-    // two LDS stages of both operands: 4 x 40 KB = 160 KB
-    __shared__ __attribute__((aligned(16))) int8_t As[2][G2_BYTES];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][G2_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t As[2][GW_BYTES];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][GW_BYTES];
 
-    // work item -> (k, tile): XCD x = w % 8 takes the terms k = x, x+8, ...
     const int w = blockIdx.x;
     const int xcd = w & 7, local = w >> 3;
-    const int per_k = ntri;
-    int k = xcd + 8 * (local / per_k);
-    int t = local % per_k;
+    const int k = xcd + 8 * (local / ntri);
+    const int t = local % ntri;
     if (k >= R_N)
         return;
-    int ti = 0;
-    while (t >= ntiles - ti) {
-        t -= ntiles - ti;
-        ++ti;
-    }
-    const int tj = ti + t;
+    int tj = 0;
+    while ((tj + 1) * (tj + 2) / 2 <= t)
+        ++tj;
+    const int ti = t - tj * (tj + 1) / 2;
     const int i0 = ti * GT2, j0 = tj * GT2;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 64;
     const int l16 = lane & 15, g = lane >> 4;
     const int8_t *Wk = WS + (long)k * R_f_pad * n_pad;
 
-    // staging: per operand 4 slices x 128 rows x 4 chunks of 16 B = 2048 chunks, 8 per thread
-    v4i areg[8], breg[8];
+    // staging: per operand 2048 chunks of 16 B, 4 per thread
+    v4i areg[4], breg[4];
     auto load_stage = [&](int a0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = tid + 256 * q;  // slice = c/512, row = (c%512)/4, col16 = c%4
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 512 * q;  // slice = c/512, row = (c%512)/4, col16 = c%4
             const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
             areg[q] = *reinterpret_cast<const v4i *>(US + sl * uplane + (long)(i0 + row) * n_pad +
                                                      a0 + 16 * c16);
@@ -464,18 +476,18 @@ __global__ __launch_bounds__(256) void gram_i8_big_kernel(
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int c = tid + 256 * q;
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + 512 * q;
             const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
-            const int o = sl * (GT2 * AROW) + row * AROW + 16 * c16;
+            const int o = gw_offset(sl, row, c16);
             *reinterpret_cast<v4i *>(As[buf] + o) = areg[q];
             *reinterpret_cast<v4i *>(Bs[buf] + o) = breg[q];
         }
     };
 
-    v4i acc[4][4][4];
+    v4i acc[2][4][4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -490,30 +502,29 @@ __global__ __launch_bounds__(256) void gram_i8_big_kernel(
         const int cur = s & 1;
         if (s + 1 < nsteps)
             load_stage((s + 1) * TK);
-        v4i afr[4][4];
+        v4i afr[2][4];
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
-                afr[x][sl] = *reinterpret_cast<const v4i *>(
-                    As[cur] + sl * (GT2 * AROW) + (wi + 16 * x + l16) * AROW + 16 * g);
+            for (int x = 0; x < 2; ++x)
+                afr[x][sl] = *reinterpret_cast<const v4i *>(As[cur] +
+                                                            gw_offset(sl, wi + 16 * x + l16, g));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             v4i bfr[4];
 #pragma unroll
             for (int y = 0; y < 4; ++y)
-                bfr[y] = *reinterpret_cast<const v4i *>(
-                    Bs[cur] + j * (GT2 * AROW) + (wj + 16 * y + l16) * AROW + 16 * g);
+                bfr[y] = *reinterpret_cast<const v4i *>(Bs[cur] +
+                                                        gw_offset(j, wj + 16 * y + l16, g));
 #pragma unroll
             for (int i = 0; i + j <= 3; ++i)
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int x = 0; x < 2; ++x)
 #pragma unroll
                     for (int y = 0; y < 4; ++y)
                         acc[x][y][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                             afr[x][i], bfr[y], acc[x][y][i + j], 0, 0, 0);
         }
-        // the other stage was last read in step s-1, before the barrier that ended it
         if (s + 1 < nsteps)
             store_stage(cur ^ 1);
         __syncthreads();
@@ -522,7 +533,7 @@ __global__ __launch_bounds__(256) void gram_i8_big_kernel(
     double *Gk = G + (long)k * R_f * R_f;
     const int *EWk = EW + (long)k * R_f_pad;
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = i0 + wi + 16 * x + 4 * g + r;
@@ -590,9 +601,8 @@ hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, con
         // items: for every XCD x, the terms k = x, x + 8, ... each with ntri tiles
         const int kgroups = (R_N + 7) / 8;
         const int items = 8 * kgroups * ntri;
-        hipLaunchKernelGGL(gram_i8_big_kernel, dim3(items), dim3(256), 0, stream, US, EU,
-                           L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, nt,
-                           ntri);
+        hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
+                           L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;
