@@ -256,9 +256,10 @@ __device__ inline void load_twiddles_pass(FftTwiddles<M, RMAX> &Tw, const cplx *
     }
 }
 
-// one in-place Stockham pass with T threads (M/R <= T butterflies)
+// one in-place Stockham pass with T threads (M/R <= T butterflies); outputs
+// at indices >= keep are not stored (the caller reads only [0, keep))
 template <int M, int R, int Ns, int T, int SIGN>
-__device__ inline void pass_fixed(cplx *buf, const cplx *wb)
+__device__ inline void pass_fixed(cplx *buf, const cplx *wb, int keep)
 {
     constexpr int nb = M / R;
     static_assert(nb <= T, "one butterfly per thread");
@@ -294,18 +295,20 @@ __device__ inline void pass_fixed(cplx *buf, const cplx *wb)
         const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            buf[pad(base + r * Ns)] = v[r];
+            if (base + r * Ns < keep)
+                buf[pad(base + r * Ns)] = v[r];
     }
     __syncthreads();
 }
 
+// The whole transform; only outputs [0, keep) of the last pass are stored.
 template <int M, int RMAX, int T, int SIGN, int P>
-__device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, RMAX> &Tw)
+__device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, RMAX> &Tw, int keep)
 {
     using F = FftShape<M, RMAX>;
     if constexpr (P < F::NP) {
-        pass_fixed<M, F::radix(P), F::ns(P), T, SIGN>(buf, Tw.w[P]);
-        fft_fixed<M, RMAX, T, SIGN, P + 1>(buf, Tw);
+        pass_fixed<M, F::radix(P), F::ns(P), T, SIGN>(buf, Tw.w[P], P + 1 == F::NP ? keep : M);
+        fft_fixed<M, RMAX, T, SIGN, P + 1>(buf, Tw, keep);
     }
 }
 
@@ -497,7 +500,8 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         if (k + 1 < R_N)
             load_c(k + 1);  // in flight during the transform
         __syncthreads();
-        fft_fixed<M, kConvRadix, TT, +1, 0>(buf, Tw);
+        // outputs m hold the samples 2m, 2m + 1: only m < ceil(n/2) are used
+        fft_fixed<M, kConvRadix, TT, +1, 0>(buf, Tw, (n + 1) / 2);
 
         if (W) {
             double *Wrow = W + ((long)k * R_f + j) * n;
