@@ -113,9 +113,15 @@ def kernel_roofline(name, per_launch_ms, w, prec):
         out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s", "peak": peak,
                "work": f"2 n R_f^2 R_N = {flops:.4g} flops per launch"}
         if name == "gram_i8":
-            # executed: 10 slice products, upper-triangle tiles only
-            ex = 10 * flops / 2.0
-            out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"]}
+            # executed matrix-core work: 10 slice products over the padded
+            # upper-triangle tiles (the counter SQ_INSTS_VALU_MFMA_MOPS_I8 x 512)
+            n_pad = -(-n // 128) * 128
+            R_f_pad = -(-R_f // 64) * 64
+            T = 128 if (R_f >= 256 and R_f_pad % 128 == 0) else 64
+            nt = R_f_pad // T
+            ex = 10 * 2.0 * n_pad * T * T * (nt * (nt + 1) // 2) * R_N
+            out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"],
+                               "ops": ex}
     elif name in ("toeplitz_i8", "toeplitz_f64", "toeplitz_f32"):
         flops = 2.0 * n * n * R_f * R_N
         out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s", "peak": peak,
@@ -124,14 +130,22 @@ def kernel_roofline(name, per_launch_ms, w, prec):
             ex = 10 * flops
             out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"]}
     elif name in ("fft_conv", "fft_conv_split"):
+        # FP64 vector work of the spectral product and the inverse transform:
+        # per (k, j) the complex product and the real-FFT twist over M + 1
+        # frequencies (14 flops each) and a complex M-point inverse FFT
+        # (5 M log2 M, the conventional count); bound by the FP64 vector ALUs
         M = 1
         while 2 * M < 2 * n - 1:
             M *= 2
+        lg = max(1, M.bit_length() - 1)
+        flops = R_N * R_f * (5.0 * M * lg + 14.0 * (M + 1))
+        out = {"bound": "alu", "achieved": flops / s / 1e12, "unit": "TFLOP/s",
+               "peak": PEAK["fp64"],
+               "work": f"R_N R_f (5 M log2 M + 14 (M+1)) = {flops:.4g} FP64 flops per launch"}
         out_bytes = (4 if name == "fft_conv_split" else 8) * R_N * R_f * n
         in_bytes = 16 * (M + 1) * (R_f + R_N)
-        byts = out_bytes + in_bytes
-        out = {"bound": "hbm", "achieved": byts / s / 1e9, "unit": "GB/s", "peak": HBM_GBS,
-               "work": f"W written once + spectra read once = {byts:.4g} bytes per launch"}
+        out["hbm_bytes"] = out_bytes + in_bytes
+        out["hbm_GBs"] = (out_bytes + in_bytes) / s / 1e9
     else:
         return None
     out["frac"] = out["achieved"] / out["peak"]

@@ -494,14 +494,23 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
             for (int d = 0; d < 4; ++d)
                 acc[x][y][d] = v4i{0, 0, 0, 0};
 
+    // Stage s+1 is written to LDS at the start of step s (from registers
+    // loaded during step s-1), and stage s+2 is then loaded into those
+    // registers, so the LDS writes overlap this step's matrix-core work
+    // instead of preceding the barrier.
     const int nsteps = n_pad / TK;
     load_stage(0);
     store_stage(0);
+    if (nsteps > 1)
+        load_stage(TK);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1;
+        // the other buffer was last read in step s-1, before the barrier that ended it
         if (s + 1 < nsteps)
-            load_stage((s + 1) * TK);
+            store_stage(cur ^ 1);
+        if (s + 2 < nsteps)
+            load_stage((s + 2) * TK);
         v4i afr[2][4];
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl)
@@ -525,8 +534,6 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
                         acc[x][y][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                             afr[x][i], bfr[y], acc[x][y][i + j], 0, 0, 0);
         }
-        if (s + 1 < nsteps)
-            store_stage(cur ^ 1);
         __syncthreads();
     }
 
