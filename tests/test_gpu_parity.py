@@ -105,7 +105,9 @@ def test_tei_gram_parity_small(tc, orc, n, R_f, R_N, algo):
         J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], save_G=True)
     Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
     J, G = host(J), host(G)
-    assert e_J(J, Jr) <= 1e-12
+    err = e_J(J, Jr)
+    say(f"   e_J = {err:.2e}")
+    assert err <= 1e-12
     np.testing.assert_array_equal(J, J.T)
     # each Gram entry within a rounding-error bound of the product U^T T U:
     # |dG| <= 1e-13 |U|^T |T| |U| (p-type columns make G_ii much smaller than
@@ -166,6 +168,7 @@ def test_tei_gram_parity_sampled_full_size(tc, orc, name, ncols, algo):
     block = Jc[:, S]                                  # J[S_q, S_r] = Jc[r][S_q]
     d = np.diag(block)
     err = np.max(np.abs(J[np.ix_(S, S)] - block.T) / np.sqrt(np.outer(d, d)))
+    say(f"   e_J(block) = {err:.2e}")
     assert err <= 1e-12, err
     # whole sampled columns, scaled by the GPU diagonal for rows outside S
     dg = np.sqrt(np.abs(np.diag(J)))

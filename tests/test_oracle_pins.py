@@ -368,3 +368,23 @@ def test_backward_matches_central_differences(orc):
     d2 = orc.tei_gram_backward(c, ps, w.U, 0.5 * (Jb + Jb.T))
     for l in range(3):
         np.testing.assert_allclose(d1[l], d2[l], rtol=1e-13, atol=1e-13 * np.abs(d2[l]).max())
+
+
+# --------------------------------------------------------------------------
+# Input recipe against values printed in the paper
+# --------------------------------------------------------------------------
+def test_grid_reproduces_printed_mesh_sizes():
+    """The cell-centred grid h = 2b/n on [-b, b] gives the mesh sizes that
+    Section 3.2 prints for its H2O grids in the box [-20,20]^3, to the digits
+    printed (fixture tests/golden/tei_mesh_sizes.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "tei_mesh_sizes.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 4
+    for n, printed, digits in rows:
+        n, printed, digits = int(n), float(printed), int(digits)
+        x = wl.grid(n, 20.0)
+        h = x[1] - x[0]
+        assert math.isclose(h, 40.0 / n, rel_tol=1e-12)
+        assert x[0] == pytest.approx(-20.0 + h / 2, abs=1e-12)
+        assert float(f"{h:.{digits}g}") == printed
