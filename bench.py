@@ -6,7 +6,7 @@ G1_k o G2_k o G3_k (tc_tei_gram: Toeplitz products or FFT convolutions,
 Grams, Hadamard/sum over k), with the side matrices already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
-                    [--prec ozaki8|fp64|fp32] [--no-cpu-baseline] [--no-extra]
+                    [--prec ozaki8|fp64|fp32|bf16x3|bf16x6] [--no-cpu-baseline] [--no-extra]
 
 Prints ONE JSON line.
   value       F / t, F = sum_l R_N (2 n^2 R_f + 2 n R_f^2): the algorithmic
@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 # published MI355X dense peaks
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "int8": 5000.0}  # TFLOP/s (TOP/s)
 HBM_GBS = 8000.0
-PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "ozaki8": "i8"}
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "ozaki8": "i8", "bf16x3": "bf16", "bf16x6": "bf16"}
 WORKLOAD_DESC = {
     "c1": "128-cell grid on [-10,10]^3, R_N=20 sinc terms, R_f=8 s-Gaussians",
     "c2": "1024-cell grid on [-10,10]^3, R_N=30 sinc terms, R_f=256 s/p Gaussian products",
@@ -113,8 +113,9 @@ def kernel_roofline(name, per_launch_ms, w, prec):
     terms) and the matching roofline."""
     n, R_f, R_N = w.n[0], w.R_f, w.R_N
     s = per_launch_ms * 1e-3
-    peak = PEAK["int8" if name.endswith("_i8") else "fp32" if name.endswith("_f32") else "fp64"]
-    if name in ("gram_i8", "gram_f64", "gram_f32"):
+    peak = PEAK["int8" if name.endswith("_i8") else "fp32" if name.endswith("_f32")
+                else "bf16" if name.endswith("_bf16") else "fp64"]
+    if name in ("gram_i8", "gram_f64", "gram_f32", "gram_bf16"):
         flops = 2.0 * n * R_f * R_f * R_N            # U^T W_k for every k
         out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s", "peak": peak,
                "work": f"2 n R_f^2 R_N = {flops:.4g} flops per launch"}
@@ -128,7 +129,7 @@ def kernel_roofline(name, per_launch_ms, w, prec):
             ex = 10 * 2.0 * n_pad * T * T * (nt * (nt + 1) // 2) * R_N
             out["executed"] = {"TOP/s": ex / s / 1e12, "frac": ex / s / 1e12 / PEAK["int8"],
                                "ops": ex}
-    elif name in ("toeplitz_i8", "toeplitz_f64", "toeplitz_f32"):
+    elif name in ("toeplitz_i8", "toeplitz_f64", "toeplitz_f32", "toeplitz_bf16"):
         flops = 2.0 * n * n * R_f * R_N
         out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s", "peak": peak,
                "work": f"2 n^2 R_f R_N = {flops:.4g} flops per launch"}
@@ -166,6 +167,7 @@ KERNEL_SOURCE = {"gram_i8": "ozaki.hip", "toeplitz_i8": "ozaki.hip", "split_rows
                  "fft_conv_split": "fft.hip", "fft_conv": "fft.hip", "rfft_rows": "fft.hip",
                  "gram_f64": "gram.hip", "toeplitz_f64": "toeplitz.hip",
                  "gram_f32": "fp32.hip", "toeplitz_f32": "fp32.hip",
+                 "gram_bf16": "bf16.hip", "toeplitz_bf16": "bf16.hip",
                  "hadamard_sum": "reduce.hip"}
 
 
@@ -198,7 +200,7 @@ def mfma_pct(prof, w, prec):
     step (Gram and direct Toeplitz products), from their measured times."""
     out = {}
     for name in ("gram_i8", "toeplitz_i8", "gram_f64", "toeplitz_f64", "gram_f32",
-                 "toeplitz_f32"):
+                 "toeplitz_f32", "gram_bf16", "toeplitz_bf16"):
         if name in prof:
             r = kernel_roofline(name, prof[name][0] / prof[name][1], w, prec)
             ex = r.get("executed", {"frac": r["frac"]})["frac"]
@@ -280,7 +282,7 @@ def main():
 
     if not args.no_extra:
         routes = {}
-        for prec in ("fp64", "fp32", "ozaki8"):
+        for prec in ("fp64", "fp32", "bf16x3", "bf16x6", "ozaki8"):
             for algo in ("direct", "fft"):
                 k = max(2, args.steps // 3)
                 routes[f"{prec}/{algo}"] = round(

@@ -66,14 +66,23 @@ typedef enum {
 /* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions. */
 typedef enum {
     TC_FP64 = 0,     /* binary64 matrix cores (v_mfma_f64_16x16x4)           */
-    TC_FP32 = 1,     /* operands rounded to binary32, binary32 matrix cores
-                        with binary32 partial sums over K-chunks of 64 and
-                        binary64 accumulation across chunks                   */
-    TC_OZAKI_I8 = 2  /* error-free splitting of each operand into four int8
+    TC_FP32 = 1,     /* operand rows scaled by a power of two (their maximum
+                        to [0.5, 1)), rounded to binary32, binary32 matrix
+                        cores with binary32 partial sums over K-chunks of 64
+                        and binary64 accumulation across chunks; does not
+                        reach 1e-7 on J (a measured comparison point)        */
+    TC_OZAKI_I8 = 2, /* error-free splitting of each operand into four int8
                         slices with one exponent per row (28 bits relative to
                         the row maximum), the ten leading slice products on
                         int8 matrix cores with exact int32 accumulation, and
                         binary64 recombination (Ozaki scheme)                 */
+    TC_BF16X3 = 3,   /* rows scaled as for TC_FP32, each entry split exactly
+                        into two bfloat16 pieces, the three leading piece
+                        products on bfloat16 matrix cores with binary32
+                        accumulation over K-chunks of 64, binary64 across
+                        chunks (a measured comparison point)                  */
+    TC_BF16X6 = 4    /* as TC_BF16X3 with three pieces and the six products
+                        of piece-index sum <= 2                               */
 } tc_precision;
 
 /* How the Toeplitz products W_k = T_k U are formed.  TC_ALGO_DIRECT: the

@@ -32,8 +32,17 @@ bool size_ok(int n, int R_f, int R_N)
 
 bool prec_known(tc_precision prec)
 {
-    return prec == TC_FP64 || prec == TC_FP32 || prec == TC_OZAKI_I8;
+    return prec == TC_FP64 || prec == TC_FP32 || prec == TC_OZAKI_I8 || prec == TC_BF16X3 ||
+           prec == TC_BF16X6;
 }
+
+// Precisions whose contractions read binary64 operands scaled per row by 2^-e.
+bool row_scaled(tc_precision prec)
+{
+    return prec == TC_FP32 || prec == TC_BF16X3 || prec == TC_BF16X6;
+}
+
+int bf16_pieces(tc_precision prec) { return prec == TC_BF16X6 ? 3 : 2; }
 
 bool prec_supported(tc_precision prec) { return prec_known(prec); }
 
@@ -117,7 +126,7 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
             s.EW = c.take<int>((size_t)R_N * L.R_f_pad);
         }
     }
-    if (prec == TC_FP32) {
+    if (row_scaled(prec)) {
         s.EU = c.take<int>(R_f);
         s.EP = c.take<int>(R_N);
         if (gram)
@@ -227,10 +236,14 @@ tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, 
         TRYK("toeplitz_f64", launch_toeplitz_f64(p, U, W, n, R_f, R_N, st));
         return TC_OK;
     }
-    if (prec == TC_FP32) {
+    if (row_scaled(prec)) {
         TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.EU, st));
         TRYK("row_exponents", launch_row_exponents(p, R_N, 2 * n - 1, s.EP, st));
-        TRYK("toeplitz_f32", launch_toeplitz_f32(p, s.EP, U, s.EU, W, n, R_f, R_N, st));
+        if (prec == TC_FP32)
+            TRYK("toeplitz_f32", launch_toeplitz_f32(p, s.EP, U, s.EU, W, n, R_f, R_N, st));
+        else
+            TRYK("toeplitz_bf16", launch_toeplitz_bf16(p, s.EP, U, s.EU, W, n, R_f, R_N,
+                                                       bf16_pieces(prec), st));
         return TC_OK;
     }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
@@ -252,13 +265,17 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         TRYK("gram_f64", launch_gram_f64(U, W, G, n, R_f, R_N, st));
         return TC_OK;
     }
-    if (prec == TC_FP32) {
+    if (row_scaled(prec)) {
         const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
         if (r != TC_OK)
             return r;
         TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.EU, st));
         TRYK("row_exponents", launch_row_exponents(W, (long)R_N * R_f, n, s.EW, st));
-        TRYK("gram_f32", launch_gram_f32(U, s.EU, W, s.EW, G, n, R_f, R_N, st));
+        if (prec == TC_FP32)
+            TRYK("gram_f32", launch_gram_f32(U, s.EU, W, s.EW, G, n, R_f, R_N, st));
+        else
+            TRYK("gram_bf16", launch_gram_bf16(U, s.EU, W, s.EW, G, n, R_f, R_N,
+                                               bf16_pieces(prec), st));
         return TC_OK;
     }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);

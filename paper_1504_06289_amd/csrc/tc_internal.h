@@ -39,6 +39,17 @@ hipError_t launch_toeplitz_f32(const double *p, const int *EP, const double *U, 
 hipError_t launch_gram_f32(const double *U, const int *EU, const double *W, const int *EW,
                            double *G, int n, int R_f, int R_N, hipStream_t stream);
 
+// ---- split-bfloat16 matrix-core variants (bf16.hip) ------------------------
+// As the binary32 variants, with each scaled binary64 entry split exactly into
+// `pieces` (2 or 3) bfloat16 pieces and the piece products with index sum
+// <= pieces - 1 (3 or 6 of them) on v_mfma_f32_16x16x32_bf16, binary32 sums
+// over K-chunks of 64, binary64 across chunks.
+hipError_t launch_toeplitz_bf16(const double *p, const int *EP, const double *U, const int *EU,
+                                double *W, int n, int R_f, int R_N, int pieces,
+                                hipStream_t stream);
+hipError_t launch_gram_bf16(const double *U, const int *EU, const double *W, const int *EW,
+                            double *G, int n, int R_f, int R_N, int pieces, hipStream_t stream);
+
 // ---- Hadamard product across modes and sum over k (reduce.hip) -----------
 // J[e] = sum_k c[k] G0[k][e] G1[k][e] G2[k][e], e < R_f*R_f.
 hipError_t launch_hadamard_sum(const double *c, const double *G0, const double *G1,

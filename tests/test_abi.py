@@ -64,6 +64,10 @@ def test_workspace_bytes(L):
     up = lambda x: (x + 255) // 256 * 256
     fft = up(16 * 256) + up(16 * 10 * 129) + up(16 * 3 * 129)
     assert w == up(8 * 3 * 10 * 100) + up(8 * 3 * 3 * 100) + fft
+    # row-scaled precisions add the row exponents of U [R_f], p [R_N] and W [R_N][R_f]
+    for prec in (_lib.TC_FP32, _lib.TC_BF16X3, _lib.TC_BF16X6):
+        assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, prec) == \
+            w + up(4 * 10) + up(4 * 3) + up(4 * 3 * 10)
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
     assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
