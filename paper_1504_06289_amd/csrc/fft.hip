@@ -413,8 +413,8 @@ __device__ inline void split4_i8(double x, int E, int8_t s[4])
 // with exponents EW [R_N][R_f_pad]); blocks with j >= R_f write zero slices.
 //
 // Each thread owns the frequency pairs (f, M - f), f = tid + 256 q <= M/2.
-// The spectrum of u_j and the split twiddles e^(-2 pi i f/N) stay in LDS for
-// all terms (with the transform buffer: 2.5 M complex = 160 KB at M = 4096),
+// The spectrum of u_j and the split twiddles e^(-2 pi i f/N), f <= M/4, stay
+// in LDS for all terms (with the transform buffer: 144 KB at M = 4096),
 // and the kernel spectrum of term k+1 is loaded into registers while term k
 // is transformed, so the inner loop waits on no global load.
 constexpr int kConvThreads = 512;  // 8 waves: two per SIMD with one workgroup per CU
@@ -428,10 +428,11 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
 {
     constexpr int TT = kConvThreads;
     constexpr int PAIRS = (M / 2 + 1 + TT - 1) / TT;
-    constexpr int HALF = M / 2 > 0 ? M / 2 : 1;
-    __shared__ cplx buf[M >= 8 ? M : 8];  // >= 8 entries for the block maximum
+    constexpr int QUART = M / 4 + 1;  // twiddles w^f, f <= M/4 (the rest by symmetry)
+    __shared__ cplx buf[M];
     __shared__ cplx Ush[M];
-    __shared__ cplx twsh[HALF];
+    __shared__ cplx twsh[QUART];
+    __shared__ double red[TT / 64];  // per-wave maxima
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
 
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx *Uj = Uspec + (long)j * (M + 1);
     for (int f = tid; f < M; f += TT)
         Ush[f] = Uj[f];
-    for (int f = tid; f < M / 2; f += TT)
+    for (int f = tid; f < QUART && f < M / 2; f += TT)
         twsh[f] = twN[f];
     const cplx uM = Uj[M];  // only the pair (0, M) uses it
     constexpr double invM = 1.0 / (double)M;
@@ -480,7 +481,15 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
             const int f = tid + TT * q;
             if (f <= M / 2) {
                 const int g = M - f;
-                const cplx wf = f < M / 2 ? twsh[f] : make_double2(0.0, -1.0);  // w^(M/2) = -i
+                // w^f = e^(-i pi f/M); for M/4 < f < M/2, w^f = -i conj(w^(M/2-f));
+                // w^(M/2) = -i
+                cplx wf = make_double2(0.0, -1.0);
+                if (f <= M / 4 && f < M / 2) {
+                    wf = twsh[f];
+                } else if (f < M / 2) {
+                    const cplx v = twsh[M / 2 - f];
+                    wf = make_double2(-v.y, -v.x);
+                }
                 const cplx yf = cmul(cf[q], Ush[f]);
                 const cplx yg = cmul(cg[q], g < M ? Ush[g] : uM);
                 // Z[f] = E + i O,  E = (Y[f] + conj Y[g]) / 2,  O = (Y[f] - conj Y[g]) conj(w^f) / 2
@@ -531,17 +540,17 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                 zs[2 * q + 1] = t + 1 < n ? z.y * invM : 0.0;
                 amax = fmax(amax, fmax(fabs(zs[2 * q]), fabs(zs[2 * q + 1])));
             }
-            // block maximum through the transform buffer (all reads above are done)
+            // block maximum; after this barrier every read of buf for this term is
+            // done, so the next term may overwrite buf without another barrier
             for (int o = 32; o > 0; o >>= 1)
                 amax = fmax(amax, __shfl_xor(amax, o));
-            __syncthreads();
             if ((tid & 63) == 0)
-                buf[tid >> 6].x = amax;
+                red[tid >> 6] = amax;
             __syncthreads();
-            amax = buf[0].x;
+            amax = red[0];
 #pragma unroll
             for (int wv = 1; wv < TT / 64; ++wv)
-                amax = fmax(amax, buf[wv].x);
+                amax = fmax(amax, red[wv]);
             const int E = row_exp(amax);
             if (tid == 0)
                 EW[(long)k * R_f_pad + j] = E;
@@ -561,7 +570,8 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                     *reinterpret_cast<unsigned long long *>(row + s * wplane) = packed[s];
             }
         }
-        __syncthreads();  // buf is rewritten by the next term
+        if (W)
+            __syncthreads();  // buf is rewritten by the next term
     }
 }
 
