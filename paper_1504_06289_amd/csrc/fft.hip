@@ -9,19 +9,21 @@
 // Real transforms of length N use one complex transform of length M = N/2
 // (even samples as real part, odd as imaginary part) plus the standard
 // split/merge step with the twiddles e^(-2 pi i f / N).  The complex
-// transform runs in LDS with 256 threads as a Stockham autosort FFT
-// (radix 16, last pass radix 8/4/2); after each pass the sub-transform size
-// Ns grows by the radix R, butterfly j reads entries j + r M/R, multiplies
-// entry r by e^(sign 2 pi i (j mod Ns) r / (Ns R)), does an R-point DFT and
-// writes entries (j/Ns) Ns R + (j mod Ns) + r Ns.  LDS entry i is stored at
+// transform runs in LDS with 512 threads as a Stockham autosort FFT whose
+// pass structure is fixed at compile time (radix 8, last pass radix 8/4/2);
+// after each pass the sub-transform size Ns grows by the radix R, butterfly j
+// reads entries j + r M/R, multiplies entry r by
+// e^(sign 2 pi i (j mod Ns) r / (Ns R)), does an R-point DFT and writes
+// entries (j/Ns) Ns R + (j mod Ns) + r Ns.  Each thread keeps the twiddle
+// bases of its butterflies in registers.  LDS entry i is stored at
 // i ^ ((i >> 4) & 15) (a permutation inside each aligned group of 16), which
 // makes the strided reads and writes of every pass hit distinct banks and
 // keeps the buffer at exactly M entries (64 KB for M = 4096).
 //
 // Kernels:
 //   fft_twiddles       e^(-2 pi i t / N), t < N, for one N (sincospi)
-//   rfft_rows          half spectra of the zero-padded rows of U
-//   rfft_kernel_embed  half spectra of the circulant embeddings of the p_k
+//   rfft_batch         half spectra of the zero-padded rows of U, or of the
+//                      circulant embeddings of the p_k
 //   fft_conv           for one function j and every term k: product of the
 //                      spectra, inverse transform, first n samples written
 //                      either as binary64 W or directly as the int8 slices
@@ -35,9 +37,7 @@ namespace {
 typedef double2 cplx;
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
-constexpr int kMaxM = 4096;                  // complex length: N <= 8192, n <= 4096
-constexpr int kPairs = (kMaxM / 2 + 1 + kThreads - 1) / kThreads;  // 9
+constexpr int kMaxM = 4096;  // complex length: N <= 8192, n <= 4096
 
 __device__ inline cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -124,88 +124,6 @@ template <int R, int SIGN> __device__ inline void dft_small(cplx *v)
         dft4<SIGN>(v);
     else if constexpr (R == 2)
         dft2<SIGN>(v);
-}
-
-// One Stockham pass of radix R on buf (M complex, padded addressing), in
-// place: every thread loads its butterfly, the block synchronises, then
-// stores.  M/R <= 256 (one butterfly per thread at most).
-// twN: e^(-2 pi i t / N) with N = 2M, so e^(-2 pi i s / M) = twN[2s].
-template <int R, int SIGN>
-__device__ void stockham_pass(cplx *buf, int M, int Ns, const cplx *__restrict__ twN)
-{
-    const int nb = M / R;
-    const int j = threadIdx.x;
-    cplx v[R];
-    const bool active = j < nb;
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[r] = buf[pad(j + r * nb)];
-        const int jm = j % Ns;
-        if (Ns > 1) {
-            // twiddle of entry r: e^(SIGN 2 pi i jm r / (Ns R)) = w1^r
-            const int step = jm * (M / (Ns * R));  // index into the M-point table
-            cplx w[R];
-            w[0] = make_double2(1.0, 0.0);
-            auto tw = [&](int s) {
-                const cplx x = twN[2 * s];
-                return SIGN > 0 ? cconj(x) : x;
-            };
-            w[1] = tw(step);
-            if constexpr (R >= 4) {
-                w[2] = tw(2 * step);
-                w[3] = cmul(w[2], w[1]);
-            }
-            if constexpr (R >= 8) {
-                w[4] = tw(4 * step);
-                w[5] = cmul(w[4], w[1]);
-                w[6] = cmul(w[4], w[2]);
-                w[7] = cmul(w[4], w[3]);
-            }
-            if constexpr (R >= 16) {
-                w[8] = tw(8 * step);
-#pragma unroll
-                for (int r = 9; r < 16; ++r)
-                    w[r] = cmul(w[8], w[r - 8]);
-            }
-#pragma unroll
-            for (int r = 1; r < R; ++r)
-                v[r] = cmul(v[r], w[r]);
-        }
-        dft_small<R, SIGN>(v);
-    }
-    __syncthreads();
-    if (active) {
-        const int jm = j % Ns;
-        const int base = (j / Ns) * Ns * R + jm;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            buf[pad(base + r * Ns)] = v[r];
-    }
-    __syncthreads();
-}
-
-// Complex FFT of length M (power of two, 1..kMaxM) on buf, SIGN = -1
-// forward, +1 inverse (unnormalised).  Caller synchronises before the call.
-template <int SIGN> __device__ void fft_lds(cplx *buf, int M, const cplx *__restrict__ twN)
-{
-    int Ns = 1;
-    while (Ns < M) {
-        const int rem = M / Ns;
-        if (rem >= 16) {
-            stockham_pass<16, SIGN>(buf, M, Ns, twN);
-            Ns *= 16;
-        } else if (rem == 8) {
-            stockham_pass<8, SIGN>(buf, M, Ns, twN);
-            Ns *= 8;
-        } else if (rem == 4) {
-            stockham_pass<4, SIGN>(buf, M, Ns, twN);
-            Ns *= 4;
-        } else {
-            stockham_pass<2, SIGN>(buf, M, Ns, twN);
-            Ns *= 2;
-        }
-    }
 }
 
 // ---- FFT with the pass structure fixed at compile time ----------------------
@@ -320,62 +238,6 @@ __global__ __launch_bounds__(256) void fft_twiddles_kernel(cplx *twN, int N)
         sincospi(2.0 * (double)t / (double)N, &s, &c);
         twN[t] = make_double2(c, -s);
     }
-}
-
-// Half spectrum X[0..M] of a real length-N sequence given as z (M complex:
-// even samples real, odd imaginary) after its forward M-point FFT in buf.
-__device__ void rfft_finish(const cplx *buf, int M, const cplx *__restrict__ twN,
-                            cplx *__restrict__ out)
-{
-    for (int f = threadIdx.x; f <= M; f += blockDim.x) {
-        const cplx a = buf[pad(f % M)];
-        const cplx b = cconj(buf[pad((M - f) % M)]);
-        const cplx E = cscale(cadd(a, b), 0.5);
-        const cplx d = csub(a, b);
-        const cplx O = make_double2(0.5 * d.y, -0.5 * d.x);  // (a - b) / (2i)
-        const cplx w = f < 2 * M ? twN[f] : make_double2(1.0, 0.0);
-        out[f] = cadd(E, cmul(w, O));
-    }
-}
-
-// rows of X [rows][len] (zero-padded to N) -> half spectra [rows][M+1]
-__global__ __launch_bounds__(256) void rfft_rows_kernel(const double *__restrict__ X, int len,
-                                                        int M, const cplx *__restrict__ twN,
-                                                        cplx *__restrict__ spec)
-{
-    extern __shared__ cplx buf[];
-    const long row = blockIdx.x;
-    const double *x = X + row * len;
-    for (int m = threadIdx.x; m < M; m += blockDim.x) {
-        const int t0 = 2 * m, t1 = 2 * m + 1;
-        buf[pad(m)] = make_double2(t0 < len ? x[t0] : 0.0, t1 < len ? x[t1] : 0.0);
-    }
-    __syncthreads();
-    fft_lds<-1>(buf, M, twN);
-    rfft_finish(buf, M, twN, spec + row * (M + 1));
-}
-
-// circulant embeddings of p [R_N][2n-1] (length N = 2M) -> half spectra [R_N][M+1]
-__global__ __launch_bounds__(256) void rfft_kernel_embed(const double *__restrict__ p, int n,
-                                                         int M, const cplx *__restrict__ twN,
-                                                         cplx *__restrict__ spec)
-{
-    extern __shared__ cplx buf[];
-    const int k = blockIdx.x;
-    const int N = 2 * M;
-    const double *pk = p + (long)k * (2L * n - 1) + (n - 1);  // pk[lag]
-    auto emb = [&](int t) -> double {
-        if (t < n)
-            return pk[t];
-        if (t > N - n)
-            return pk[t - N];
-        return 0.0;
-    };
-    for (int m = threadIdx.x; m < M; m += blockDim.x)
-        buf[pad(m)] = make_double2(emb(2 * m), emb(2 * m + 1));
-    __syncthreads();
-    fft_lds<-1>(buf, M, twN);
-    rfft_finish(buf, M, twN, spec + (long)k * (M + 1));
 }
 
 __device__ inline int row_exp(double amax)
@@ -575,7 +437,79 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     }
 }
 
-size_t lds_bytes(int M) { return sizeof(cplx) * (size_t)(M < 4 ? 4 : M); }
+// Forward real FFTs (half spectra [rows][M+1]) of either the rows of X
+// [rows][len] zero-padded to N = 2M (X != nullptr) or the circulant
+// embeddings of the kernel vectors p [rows][2n-1] (X == nullptr).  Each
+// workgroup takes rows blockIdx.x, blockIdx.x + gridDim.x, ...: the twiddles
+// stay in registers across its rows and the next row's samples are loaded
+// while the current one is transformed.
+template <int M>
+__global__ __launch_bounds__(kConvThreads) void rfft_batch_kernel(
+    const double *__restrict__ X, int len, const double *__restrict__ p, int n, int rows,
+    const cplx *__restrict__ twN, cplx *__restrict__ spec)
+{
+    constexpr int TT = kConvThreads;
+    constexpr int PER = (M + TT - 1) / TT;      // packed inputs per thread
+    constexpr int FIN = (M + 1 + TT - 1) / TT;  // outputs per thread
+    __shared__ cplx buf[M];
+    const int tid = threadIdx.x;
+
+    FftTwiddles<M, kConvRadix> Tw;
+    load_twiddles_pass<M, kConvRadix, TT, -1, 0>(Tw, twN);
+
+    auto sample = [&](int r, int t) -> double {
+        if (X)
+            return t < len ? X[(long)r * len + t] : 0.0;
+        const double *pk = p + (long)r * (2L * n - 1) + (n - 1);  // pk[lag]
+        if (t < n)
+            return pk[t];
+        if (t > 2 * M - n)
+            return pk[t - 2 * M];
+        return 0.0;
+    };
+    cplx nxt[PER];
+    auto load_row = [&](int r) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int m = tid + TT * q;
+            if (m < M)
+                nxt[q] = make_double2(sample(r, 2 * m), sample(r, 2 * m + 1));
+        }
+    };
+
+    int r = blockIdx.x;
+    if (r < rows)
+        load_row(r);
+    for (; r < rows; r += gridDim.x) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int m = tid + TT * q;
+            if (m < M)
+                buf[pad(m)] = nxt[q];
+        }
+        if (r + (int)gridDim.x < rows)
+            load_row(r + gridDim.x);  // in flight during the transform
+        __syncthreads();
+        fft_fixed<M, kConvRadix, TT, -1, 0>(buf, Tw, M);
+        // X[f] = E + w^f O from the packed transform Z: E = (Z[f] + conj Z[M-f]) / 2,
+        // O = (Z[f] - conj Z[M-f]) / (2i)
+        cplx *out = spec + (long)r * (M + 1);
+#pragma unroll
+        for (int q = 0; q < FIN; ++q) {
+            const int f = tid + TT * q;
+            if (f <= M) {
+                const cplx a = buf[pad(f % M)];
+                const cplx b = cconj(buf[pad((M - f) % M)]);
+                const cplx E = cscale(cadd(a, b), 0.5);
+                const cplx d = csub(a, b);
+                const cplx O = make_double2(0.5 * d.y, -0.5 * d.x);
+                out[f] = cadd(E, cmul(twN[f], O));
+            }
+        }
+        __syncthreads();  // buf is rewritten by the next row
+    }
+}
+
 
 }  // namespace
 
@@ -595,22 +529,47 @@ hipError_t launch_fft_twiddles(cplx *twN, int N, hipStream_t stream)
     return hipGetLastError();
 }
 
+static hipError_t launch_rfft_batch(const double *X, int len, const double *p, int n, int rows,
+                                    int N, const cplx *twN, cplx *spec, hipStream_t stream)
+{
+    const int M = N / 2;
+    const int blocks = rows < 512 ? rows : 512;  // two 64 KB workgroups per CU
+#define TC_RFFT_CASE(MM)                                                                        \
+    case MM:                                                                                    \
+        hipLaunchKernelGGL(rfft_batch_kernel<MM>, dim3(blocks), dim3(kConvThreads), 0, stream,  \
+                           X, len, p, n, rows, twN, spec);                                      \
+        break;
+    switch (M) {
+        TC_RFFT_CASE(1)
+        TC_RFFT_CASE(2)
+        TC_RFFT_CASE(4)
+        TC_RFFT_CASE(8)
+        TC_RFFT_CASE(16)
+        TC_RFFT_CASE(32)
+        TC_RFFT_CASE(64)
+        TC_RFFT_CASE(128)
+        TC_RFFT_CASE(256)
+        TC_RFFT_CASE(512)
+        TC_RFFT_CASE(1024)
+        TC_RFFT_CASE(2048)
+        TC_RFFT_CASE(4096)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef TC_RFFT_CASE
+    return hipGetLastError();
+}
+
 hipError_t launch_rfft_rows(const double *X, int rows, int len, int N, const cplx *twN,
                             cplx *spec, hipStream_t stream)
 {
-    const int M = N / 2;
-    hipLaunchKernelGGL(rfft_rows_kernel, dim3(rows), dim3(256), lds_bytes(M), stream, X, len, M,
-                       twN, spec);
-    return hipGetLastError();
+    return launch_rfft_batch(X, len, nullptr, 0, rows, N, twN, spec, stream);
 }
 
 hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, const cplx *twN,
                                     cplx *spec, hipStream_t stream)
 {
-    const int M = N / 2;
-    hipLaunchKernelGGL(rfft_kernel_embed, dim3(R_N), dim3(256), lds_bytes(M), stream, p, n, M,
-                       twN, spec);
-    return hipGetLastError();
+    return launch_rfft_batch(nullptr, 0, p, n, R_N, N, twN, spec, stream);
 }
 
 hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, int R_f, int R_N,
