@@ -116,9 +116,11 @@ def kernel_roofline(name, per_launch_ms, w, prec):
     peak = PEAK["int8" if name.endswith("_i8") else "fp32" if name.endswith("_f32")
                 else "bf16" if name.endswith("_bf16") else "fp64"]
     if name in ("gram_i8", "gram_f64", "gram_f32", "gram_bf16"):
-        flops = 2.0 * n * R_f * R_f * R_N            # U^T W_k for every k
+        # U^T W_k for every k; G_k is symmetric, so the algorithm needs its
+        # upper triangle only: R_f (R_f + 1) / 2 entries of 2n flops each
+        flops = 1.0 * n * R_f * (R_f + 1) * R_N
         out = {"bound": "mfma", "achieved": flops / s / 1e12, "unit": "TFLOP/s", "peak": peak,
-               "work": f"2 n R_f^2 R_N = {flops:.4g} flops per launch"}
+               "work": f"n R_f (R_f+1) R_N = {flops:.4g} flops per launch (upper triangles)"}
         if name == "gram_i8":
             # executed matrix-core work: 10 slice products over the padded
             # upper-triangle tiles (the counter SQ_INSTS_VALU_MFMA_MOPS_I8 x 512)
