@@ -335,6 +335,8 @@ def extra_rows(tc, wl, torch, dev, args):
         batch.append((c, [p, p, p], [torch.from_numpy(u).to(dev) for u in wi.U]))
     Fb = sum(wi.flops() for wi in insts)
     for prec in ("fp64", "ozaki8"):
+        # direct/FFT choice per distinct mode shape from the autotuner
+        tc.autotune_batched(batch, prec=prec)
         msb = timed(lambda: tc.tei_gram_batched(batch, prec=prec), 2, 1, torch)
         rows[f"batched_c4_{prec}_ms"] = round(msb, 3)
         rows[f"batched_c4_{prec}_GFLOPs"] = round(Fb / (msb * 1e-3) / 1e9, 1)

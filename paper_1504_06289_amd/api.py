@@ -229,6 +229,28 @@ def autotune(c: torch.Tensor, p3, U3, prec="fp64"):
     return {l: (float(ms[2 * l]), float(ms[2 * l + 1])) for l in range(3)}
 
 
+def autotune_batched(instances, prec="fp64"):
+    """tc_autotune over a batch (sequence of (c, p3, U3)): every distinct mode
+    shape is timed once with both algorithms and the faster is recorded.
+    Returns an array [count][3][2] of (ms_direct, ms_fft) per instance and mode."""
+    dev = instances[0][2][0].device
+    arr = (TcInstance * len(instances))()
+    Js = []
+    for i, (c, p3, U3) in enumerate(instances):
+        R_f = U3[0].shape[0]
+        J = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+        arr[i] = make_instance(c, p3, U3, J, None)
+        Js.append(J)
+    L = _lib.lib()
+    ws_bytes = max(L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, (TcInstance * 1)(arr[i]), 1,
+                                        _prec(prec)) for i in range(len(instances)))
+    ws = _workspace(ws_bytes, dev)
+    ms = np.zeros(6 * len(instances))
+    check(L.tc_autotune(arr, len(instances), _prec(prec), _ptr(ws), ws_bytes, _stream(dev),
+                        ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tc_autotune")
+    return ms.reshape(len(instances), 3, 2)
+
+
 def profile_enable(on: bool = True) -> None:
     """Bracket every kernel launch of the library with HIP events."""
     check(_lib.lib().tc_profile_enable(1 if on else 0), "tc_profile_enable")

@@ -255,6 +255,35 @@ def test_autotune_records_a_choice(tc, orc):
     tc.tune_set(512, 64, 8, "fp64", "auto")
 
 
+def test_autotune_batched_then_batch_matches_oracle(tc, orc):
+    """The batched autotuner records one choice per distinct mode shape; the
+    batch run afterwards (with those choices) still matches the oracle."""
+    say("autotune batched")
+    ws = [wl.small_products((300, 300, 300), 40, R_N=6, b=6.0, seed=1),
+          wl.small_products((130, 64, 200), 20, R_N=6, b=6.0, seed=2),
+          wl.small_products((300, 300, 300), 40, R_N=6, b=6.0, seed=3)]
+    batch, refs = [], []
+    for w in ws:
+        c, ps = oracle_setup(orc, w)
+        batch.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
+        refs.append(orc.tei_gram(c, ps, w.U))
+    shapes = sorted({(nl, w.R_f, w.R_N) for w in ws for nl in w.n})
+    try:
+        ms = tc.autotune_batched(batch, prec="ozaki8")
+        assert ms.shape == (3, 3, 2) and np.all(ms > 0)
+        np.testing.assert_array_equal(ms[0], ms[2])  # the same shapes, timed once
+        for i, w in enumerate(ws):
+            for l in range(3):
+                d, f = ms[i, l]
+                assert tc.tune_get(w.n[l], w.R_f, w.R_N, "ozaki8") == ("fft" if f < d else "direct")
+        Js = tc.tei_gram_batched(batch, prec="ozaki8")
+        for J, Jr in zip(Js, refs):
+            assert e_J(host(J), Jr) <= 1e-7
+    finally:
+        for sh in shapes:
+            tc.tune_set(*sh, "ozaki8", "auto")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "ozaki8"])
 def test_graph_replays_match_eager(tc, orc, prec):
     """A batch captured in a HIP graph: every replay (with eager work and
