@@ -274,19 +274,29 @@ __device__ inline void split4_i8(double x, int E, int8_t s[4])
 // [R_N][R_f][n]) or int8 slices (WS != nullptr, layout [4][R_N][R_f_pad][n_pad]
 // with exponents EW [R_N][R_f_pad]); blocks with j >= R_f write zero slices.
 //
-// Each thread owns the frequency pairs (f, M - f), f = tid + 256 q <= M/2.
+// Each thread owns the frequency pairs (f, M - f), f = tid + 512 q <= M/2.
 // The spectrum of u_j and the split twiddles e^(-2 pi i f/N), f <= M/4, stay
 // in LDS for all terms (with the transform buffer: 144 KB at M = 4096),
-// and the kernel spectrum of term k+1 is loaded into registers while term k
-// is transformed, so the inner loop waits on no global load.
+// and the kernel spectrum of the next transformed term is loaded into
+// registers while the current one is transformed, so the inner loop waits on
+// no global load.
+//
+// Narrow terms (band != nullptr, int8 output only): a term whose kernel
+// vector has band[k] = B >= 0 (all of |p_k[m]|, |m| > B, together below
+// 2^-60 of sum_m |p_k[m]|) is convolved directly as
+// sum_{|m| <= B} p_k[m] u_j[t - m] in binary64 from u_j staged in LDS, after
+// the transformed terms; the dropped tail is far below the 28-bit split.
 constexpr int kConvThreads = 512;  // 8 waves: two per SIMD with one workgroup per CU
 constexpr int kConvRadix = 8;      // M/8 <= 512 butterflies per pass
+constexpr int kBandMax = 16;       // widest band taken directly (cheaper than a transform)
+constexpr int kBandPad = 32;       // zeros around u_j in LDS: >= kBandMax + 15
 
 template <int M>
 __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx *__restrict__ Uspec, const cplx *__restrict__ Cspec, int n, int R_f, int R_N,
     const cplx *__restrict__ twN, double *__restrict__ W, int8_t *__restrict__ WS,
-    int *__restrict__ EW, int R_f_pad, int n_pad, long wplane)
+    int *__restrict__ EW, int R_f_pad, int n_pad, long wplane, const double *__restrict__ U,
+    const double *__restrict__ p, const int *__restrict__ band)
 {
     constexpr int TT = kConvThreads;
     constexpr int PAIRS = (M / 2 + 1 + TT - 1) / TT;
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     __shared__ cplx buf[M];
     __shared__ cplx Ush[M];
     __shared__ cplx twsh[QUART];
-    __shared__ double red[TT / 64];  // per-wave maxima
+    __shared__ double red[2][TT / 64];  // per-wave maxima, alternating between terms
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
 
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx uM = Uj[M];  // only the pair (0, M) uses it
     constexpr double invM = 1.0 / (double)M;
 
-    // kernel spectrum of the current term at this thread's pairs
+    // kernel spectrum of a term at this thread's pairs
     cplx cf[PAIRS], cg[PAIRS];
     auto load_c = [&](int k) {
         const cplx *Ck = Cspec + (long)k * (M + 1);
@@ -334,10 +344,61 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
             }
         }
     };
-    load_c(0);
+    // the next transformed term at or after k
+    auto next_fft = [&](int k) {
+        while (k < R_N && band && band[k] >= 0)
+            ++k;
+        return k;
+    };
+
+    // int8 slices of W_k[j] from the samples t = 8 tid .. 8 tid + 7 (zero at
+    // t >= n): block maximum, row exponent, split, one 8-byte store per slice.
+    // The maxima alternate between two arrays, so the next term's writes
+    // cannot meet this term's reads.  n_pad <= 8 TT on this route.
+    int nemit = 0;
+    auto emit = [&](int k, const double (&zs)[8]) {
+        const bool own = 8 * tid < n_pad;
+        double amax = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            amax = fmax(amax, fabs(zs[q]));
+        for (int o = 32; o > 0; o >>= 1)
+            amax = fmax(amax, __shfl_xor(amax, o));
+        double *rd = red[nemit & 1];
+        ++nemit;
+        if ((tid & 63) == 0)
+            rd[tid >> 6] = amax;
+        __syncthreads();
+        amax = rd[0];
+#pragma unroll
+        for (int wv = 1; wv < TT / 64; ++wv)
+            amax = fmax(amax, rd[wv]);
+        const int E = row_exp(amax);
+        if (tid == 0)
+            EW[(long)k * R_f_pad + j] = E;
+        if (own) {
+            unsigned long long packed[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int8_t d[4];
+                split4_i8(zs[q], E, d);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    packed[s] |= (unsigned long long)(unsigned char)d[s] << (8 * q);
+            }
+            int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad + 8 * tid;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                *reinterpret_cast<unsigned long long *>(row + s * wplane) = packed[s];
+        }
+    };
+
+    int k = next_fft(0);
+    if (k < R_N)
+        load_c(k);
     __syncthreads();
 
-    for (int k = 0; k < R_N; ++k) {
+    while (k < R_N) {
 #pragma unroll
         for (int q = 0; q < PAIRS; ++q) {
             const int f = tid + TT * q;
@@ -368,8 +429,9 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                 }
             }
         }
-        if (k + 1 < R_N)
-            load_c(k + 1);  // in flight during the transform
+        const int kn = next_fft(k + 1);
+        if (kn < R_N)
+            load_c(kn);  // in flight during the transform
         __syncthreads();
         // outputs m hold the samples 2m, 2m + 1: only m < ceil(n/2) are used
         fft_fixed<M, kConvRadix, TT, +1, 0>(buf, Tw, (n + 1) / 2);
@@ -384,56 +446,123 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                 if (t + 1 < n)
                     Wrow[t + 1] = z.y * invM;
             }
+            __syncthreads();  // buf is rewritten by the next term
         } else {
             // thread tid owns the eight samples t = 8 tid .. 8 tid + 7 (the
-            // complex outputs m = 4 tid .. 4 tid + 3), so each slice row gets one
-            // 8-byte store per thread; n_pad <= 8 TT on this route
-            const bool own = 8 * tid < n_pad;
+            // complex outputs m = 4 tid .. 4 tid + 3); all reads of buf for this
+            // term happen before the barrier inside emit, so the next term may
+            // overwrite buf without another barrier
             double zs[8];
-            double amax = 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int m = 4 * tid + q;
                 const int t = 2 * m;
                 cplx z = make_double2(0.0, 0.0);
-                if (own && m < M)
+                if (8 * tid < n_pad && m < M)
                     z = buf[pad(m)];
                 zs[2 * q] = t < n ? z.x * invM : 0.0;
                 zs[2 * q + 1] = t + 1 < n ? z.y * invM : 0.0;
-                amax = fmax(amax, fmax(fabs(zs[2 * q]), fabs(zs[2 * q + 1])));
             }
-            // block maximum; after this barrier every read of buf for this term is
-            // done, so the next term may overwrite buf without another barrier
-            for (int o = 32; o > 0; o >>= 1)
-                amax = fmax(amax, __shfl_xor(amax, o));
-            if ((tid & 63) == 0)
-                red[tid >> 6] = amax;
-            __syncthreads();
-            amax = red[0];
+            emit(k, zs);
+        }
+        k = kn;
+    }
+
+    if (band && !W) {
+        // narrow terms: u_j in LDS with kBandPad zeros on both sides (buf is
+        // free: the last transform's reads ended before the barrier in its
+        // emit; 2M >= 9/8 (n + 2 kBandPad) is checked at launch).  Entry x of
+        // the padded row sits at x + x/8, so the lanes' windows (eight entries
+        // apart) fall on different banks.
+        double *ush = reinterpret_cast<double *>(buf);
+        const double *urow = U + (long)j * n;
+        for (int t = tid; t < n + 2 * kBandPad; t += TT) {
+            const int x = t - kBandPad;
+            ush[t + (t >> 3)] = (x >= 0 && x < n) ? urow[x] : 0.0;
+        }
+        __syncthreads();
+        const int t0 = 8 * tid;
+        const double *uw = ush + 9 * tid;  // entry 8 tid + c of the padded row at uw[c + c/8]
+        for (int kb = 0; kb < R_N; ++kb) {
+            const int b = band[kb];
+            if (b < 0)
+                continue;
+            const double *pk = p + (long)kb * (2L * n - 1) + (n - 1);  // pk[lag]
+            double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (t0 < n) {
+                // chunks of eight lags m0 .. m0 + 7 over the window
+                // u[t0 - m0 - 7 .. t0 - m0 + 7]
+                for (int m0 = -b; m0 <= b; m0 += 8) {
+                    double pm[8], win[15];
 #pragma unroll
-            for (int wv = 1; wv < TT / 64; ++wv)
-                amax = fmax(amax, red[wv]);
-            const int E = row_exp(amax);
-            if (tid == 0)
-                EW[(long)k * R_f_pad + j] = E;
-            if (own) {
-                unsigned long long packed[4] = {0, 0, 0, 0};
+                    for (int r = 0; r < 8; ++r)
+                        pm[r] = m0 + r <= b ? pk[m0 + r] : 0.0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    int8_t d[4];
-                    split4_i8(zs[q], E, d);
+                    for (int q = 0; q < 15; ++q) {
+                        // u[t0 - m0 + q - 7] = padded entry 8 tid + c, c >= 0
+                        const int c = kBandPad - 7 + q - m0;
+                        win[q] = uw[c + (c >> 3)];
+                    }
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        packed[s] |= (unsigned long long)(unsigned char)d[s] << (8 * q);
+                    for (int i = 0; i < 8; ++i)
+#pragma unroll
+                        for (int r = 0; r < 8; ++r)
+                            acc[i] = fma(pm[r], win[i - r + 7], acc[i]);
                 }
-                int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad + 8 * tid;
+            }
+            double zs[8];
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    *reinterpret_cast<unsigned long long *>(row + s * wplane) = packed[s];
+            for (int i = 0; i < 8; ++i)
+                zs[i] = t0 + i < n ? acc[i] : 0.0;
+            emit(kb, zs);
+        }
+    }
+}
+
+// band[k] = the smallest B <= min(kBandMax, n - 1) with
+// sum_{|m| > B} |p_k[m]| <= 2^-60 sum_m |p_k[m]|, or -1 if there is none
+// (one workgroup per term; fixed summation order)
+__global__ __launch_bounds__(256) void term_band_kernel(const double *__restrict__ p, int n,
+                                                        int *__restrict__ band)
+{
+    __shared__ double part[2][4];
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double *pk = p + (long)k * (2L * n - 1) + (n - 1);
+    const int cap = n - 1 < kBandMax ? n - 1 : kBandMax;
+    double tot = 0.0, out = 0.0;
+    for (int m = tid; m < n; m += 256) {
+        const double a = fabs(pk[m]) + (m > 0 ? fabs(pk[-m]) : 0.0);
+        tot += a;
+        if (m > cap)
+            out += a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o);
+        out += __shfl_xor(out, o);
+    }
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = tot;
+        part[1][tid >> 6] = out;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        tot = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
+        out = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+        const double thr = ldexp(tot, -60);
+        int B = -1;
+        if (out <= thr) {
+            B = cap;
+            double tail = out;
+            while (B > 0) {
+                const double add = fabs(pk[B]) + fabs(pk[-B]);
+                if (tail + add > thr)
+                    break;
+                tail += add;
+                --B;
             }
         }
-        if (W)
-            __syncthreads();  // buf is rewritten by the next term
+        band[k] = B;
     }
 }
 
@@ -572,19 +701,28 @@ hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, cons
     return launch_rfft_batch(nullptr, 0, p, n, R_N, N, twN, spec, stream);
 }
 
+hipError_t launch_term_band(const double *p, int n, int R_N, int *band, hipStream_t stream)
+{
+    hipLaunchKernelGGL(term_band_kernel, dim3(R_N), dim3(256), 0, stream, p, n, band);
+    return hipGetLastError();
+}
+
 hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, int R_f, int R_N,
                            const cplx *twN, double *W, int8_t *WS, int *EW, int R_f_pad,
-                           int n_pad, long wplane, hipStream_t stream)
+                           int n_pad, long wplane, const double *U, const double *p,
+                           const int *band, hipStream_t stream)
 {
     const int M = N / 2;
     const int blocks = W ? R_f : R_f_pad;
+    if (W || 2 * M < (n + 2 * kBandPad) * 9 / 8 + 1)
+        band = nullptr;  // the direct path is for int8 output with room for the padded row
     if (!W && (n_pad > 8 * kConvThreads || n_pad % 8 != 0))
         return hipErrorInvalidValue;  // one 8-byte slice chunk per thread
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
         hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(kConvThreads), 0, stream,    \
-                           Uspec, Cspec,                                                        \
-                           n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane);               \
+                           Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane,  \
+                           U, p, band);                                                         \
         break;
     switch (M) {
         TC_FFT_CONV_CASE(1)

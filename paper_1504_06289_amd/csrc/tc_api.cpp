@@ -110,6 +110,7 @@ struct ModeScratch {
     double2 *twN = nullptr;    // FFT twiddles
     double2 *Uspec = nullptr;  // half spectra of U rows
     double2 *Cspec = nullptr;  // half spectra of the kernel embeddings
+    int *band = nullptr;       // lag band of each kernel term (int8 FFT route)
 };
 
 ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram)
@@ -137,6 +138,8 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
         s.twN = c.take<double2>(N);
         s.Uspec = c.take<double2>((size_t)R_f * (N / 2 + 1));
         s.Cspec = c.take<double2>((size_t)R_N * (N / 2 + 1));
+        if (prec == TC_OZAKI_I8)
+            s.band = c.take<int>(R_N);
     }
     return s;
 }
@@ -229,7 +232,8 @@ tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, 
         if (r != TC_OK)
             return r;
         TRYK("fft_conv", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN, W,
-                                         nullptr, nullptr, 0, 0, 0, st));
+                                         nullptr, nullptr, 0, 0, 0, nullptr, nullptr, nullptr,
+                                         st));
         return TC_OK;
     }
     if (prec == TC_FP64) {
@@ -284,8 +288,10 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         if (r != TC_OK)
             return r;
         TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
+        TRYK("term_band", launch_term_band(p, n, R_N, s.band, st));
         TRYK("fft_conv_split", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN,
-                                               nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, st));
+                                               nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane,
+                                               U, p, s.band, st));
     } else {
         const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
         if (r != TC_OK)

@@ -109,11 +109,18 @@ hipError_t launch_rfft_rows(const double *X, int rows, int len, int N, const dou
 // half spectra [R_N][N/2+1] of the circulant embeddings of p [R_N][2n-1]
 hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, const double2 *twN,
                                     double2 *spec, hipStream_t stream);
+// band[k] for the int8 route: the smallest B <= min(16, n-1) such that the
+// kernel entries |p_k[m]|, |m| > B, sum to at most 2^-60 of sum_m |p_k[m]|,
+// or -1 (then term k is transformed)
+hipError_t launch_term_band(const double *p, int n, int R_N, int *band, hipStream_t stream);
 // W_k[j][t] (t < n) for all j, k from the spectra; output binary64 W
 // [R_N][R_f][n] (W != nullptr) or int8 slices WS [4][R_N][R_f_pad][n_pad] with
-// exponents EW [R_N][R_f_pad] (W == nullptr; padding rows zeroed)
+// exponents EW [R_N][R_f_pad] (W == nullptr; padding rows zeroed).  With
+// band != nullptr (int8 output only), terms with band[k] >= 0 are convolved
+// directly from U [R_f][n] and p [R_N][2n-1] over lags |m| <= band[k].
 hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, int N, int R_f,
                            int R_N, const double2 *twN, double *W, int8_t *WS, int *EW,
-                           int R_f_pad, int n_pad, long wplane, hipStream_t stream);
+                           int R_f_pad, int n_pad, long wplane, const double *U,
+                           const double *p, const int *band, hipStream_t stream);
 
 }  // namespace tc
