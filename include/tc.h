@@ -89,7 +89,9 @@ typedef enum {
  * implicit-Toeplitz matrix-core product in the arithmetic selected by
  * tc_precision.  TC_ALGO_FFT: aperiodic convolution through a circulant
  * embedding of length N >= 2n-1 with binary64 FFTs (n <= 4096); the Grams then
- * use the tc_precision arithmetic.  TC_ALGO_AUTO: the entry of the tuning
+ * use the tc_precision arithmetic.  With TC_OZAKI_I8 a kernel term whose
+ * vector carries at most 2^-60 of its absolute sum beyond lag 16 is convolved
+ * directly in binary64 over those lags instead.  TC_ALGO_AUTO: the entry of the tuning
  * table for the mode's (n, R_f, R_N, precision), else a built-in rule. */
 typedef enum {
     TC_ALGO_AUTO = 0,
