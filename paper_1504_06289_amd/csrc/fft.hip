@@ -281,14 +281,14 @@ __device__ inline void split4_i8(double x, int E, int8_t s[4])
 // registers while the current one is transformed, so the inner loop waits on
 // no global load.
 //
-// Narrow terms (band != nullptr, int8 output only): a term whose kernel
-// vector has band[k] = B >= 0 (all of |p_k[m]|, |m| > B, together below
-// 2^-60 of sum_m |p_k[m]|) is convolved directly as
+// Term classes (band != nullptr, int8 output only; see launch_term_class): a
+// narrow term, band[k] = B >= 0 (all of |p_k[m]|, |m| > B, together below
+// 2^-60 of sum_m |p_k[m]|), is convolved directly as
 // sum_{|m| <= B} p_k[m] u_j[t - m] in binary64 from u_j staged in LDS, after
-// the transformed terms; the dropped tail is far below the 28-bit split.
+// the transformed terms (the dropped tail is far below the 28-bit split); a
+// smooth term, band[k] = -2, is skipped (its Gram is formed at low rank).
 constexpr int kConvThreads = 512;  // 8 waves: two per SIMD with one workgroup per CU
 constexpr int kConvRadix = 8;      // M/8 <= 512 butterflies per pass
-constexpr int kBandMax = 16;       // widest band taken directly (cheaper than a transform)
 constexpr int kBandPad = 32;       // zeros around u_j in LDS: >= kBandMax + 15
 
 template <int M>
@@ -308,8 +308,13 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
 
+    // the terms of this workgroup: [kb, ke) (a split over blockIdx.y when there
+    // are few rows)
+    const int kb = (int)((long)blockIdx.y * R_N / gridDim.y);
+    const int ke = (int)((long)(blockIdx.y + 1) * R_N / gridDim.y);
+
     if (j >= R_f) {  // zero padding rows of the slices
-        for (int k = 0; k < R_N; ++k) {
+        for (int k = kb; k < ke; ++k) {
             int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
             for (int t = tid; t < n_pad; t += blockDim.x)
                 for (int s = 0; s < 4; ++s)
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     };
     // the next transformed term at or after k
     auto next_fft = [&](int k) {
-        while (k < R_N && band && band[k] >= 0)
+        while (k < ke && band && band[k] != -1)
             ++k;
         return k;
     };
@@ -393,12 +398,12 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         }
     };
 
-    int k = next_fft(0);
-    if (k < R_N)
+    int k = next_fft(kb);
+    if (k < ke)
         load_c(k);
     __syncthreads();
 
-    while (k < R_N) {
+    while (k < ke) {
 #pragma unroll
         for (int q = 0; q < PAIRS; ++q) {
             const int f = tid + TT * q;
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
             }
         }
         const int kn = next_fft(k + 1);
-        if (kn < R_N)
+        if (kn < ke)
             load_c(kn);  // in flight during the transform
         __syncthreads();
         // outputs m hold the samples 2m, 2m + 1: only m < ceil(n/2) are used
@@ -483,11 +488,11 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         __syncthreads();
         const int t0 = 8 * tid;
         const double *uw = ush + 9 * tid;  // entry 8 tid + c of the padded row at uw[c + c/8]
-        for (int kb = 0; kb < R_N; ++kb) {
-            const int b = band[kb];
+        for (int kt = kb; kt < ke; ++kt) {
+            const int b = band[kt];
             if (b < 0)
                 continue;
-            const double *pk = p + (long)kb * (2L * n - 1) + (n - 1);  // pk[lag]
+            const double *pk = p + (long)kt * (2L * n - 1) + (n - 1);  // pk[lag]
             double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (t0 < n) {
                 // chunks of eight lags m0 .. m0 + 7 over the window
@@ -514,55 +519,8 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 zs[i] = t0 + i < n ? acc[i] : 0.0;
-            emit(kb, zs);
+            emit(kt, zs);
         }
-    }
-}
-
-// band[k] = the smallest B <= min(kBandMax, n - 1) with
-// sum_{|m| > B} |p_k[m]| <= 2^-60 sum_m |p_k[m]|, or -1 if there is none
-// (one workgroup per term; fixed summation order)
-__global__ __launch_bounds__(256) void term_band_kernel(const double *__restrict__ p, int n,
-                                                        int *__restrict__ band)
-{
-    __shared__ double part[2][4];
-    const int k = blockIdx.x;
-    const int tid = threadIdx.x;
-    const double *pk = p + (long)k * (2L * n - 1) + (n - 1);
-    const int cap = n - 1 < kBandMax ? n - 1 : kBandMax;
-    double tot = 0.0, out = 0.0;
-    for (int m = tid; m < n; m += 256) {
-        const double a = fabs(pk[m]) + (m > 0 ? fabs(pk[-m]) : 0.0);
-        tot += a;
-        if (m > cap)
-            out += a;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        tot += __shfl_xor(tot, o);
-        out += __shfl_xor(out, o);
-    }
-    if ((tid & 63) == 0) {
-        part[0][tid >> 6] = tot;
-        part[1][tid >> 6] = out;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        tot = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
-        out = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
-        const double thr = ldexp(tot, -60);
-        int B = -1;
-        if (out <= thr) {
-            B = cap;
-            double tail = out;
-            while (B > 0) {
-                const double add = fabs(pk[B]) + fabs(pk[-B]);
-                if (tail + add > thr)
-                    break;
-                tail += add;
-                --B;
-            }
-        }
-        band[k] = B;
     }
 }
 
@@ -701,12 +659,6 @@ hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, cons
     return launch_rfft_batch(nullptr, 0, p, n, R_N, N, twN, spec, stream);
 }
 
-hipError_t launch_term_band(const double *p, int n, int R_N, int *band, hipStream_t stream)
-{
-    hipLaunchKernelGGL(term_band_kernel, dim3(R_N), dim3(256), 0, stream, p, n, band);
-    return hipGetLastError();
-}
-
 hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, int R_f, int R_N,
                            const cplx *twN, double *W, int8_t *WS, int *EW, int R_f_pad,
                            int n_pad, long wplane, const double *U, const double *p,
@@ -714,13 +666,17 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
 {
     const int M = N / 2;
     const int blocks = W ? R_f : R_f_pad;
+    // few rows: split the terms over blockIdx.y so that ~512 workgroups run
+    int ysplit = (512 + blocks - 1) / blocks;
+    ysplit = ysplit < 1 ? 1 : (ysplit > R_N ? R_N : ysplit);
     if (W || 2 * M < (n + 2 * kBandPad) * 9 / 8 + 1)
         band = nullptr;  // the direct path is for int8 output with room for the padded row
     if (!W && (n_pad > 8 * kConvThreads || n_pad % 8 != 0))
         return hipErrorInvalidValue;  // one 8-byte slice chunk per thread
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
-        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks), dim3(kConvThreads), 0, stream,    \
+        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks, ysplit), dim3(kConvThreads), 0,    \
+                           stream,                                                              \
                            Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane,  \
                            U, p, band);                                                         \
         break;

@@ -1,0 +1,505 @@
+// Term classes of the int8 FFT route and the low-rank Grams of smooth terms.
+//
+// A kernel term is
+//   narrow  (class B >= 0) when |p_k[m]|, |m| > B <= 16, carry at most 2^-60
+//           of sum_m |p_k[m]| (convolved directly inside the FFT kernel);
+//   smooth  (class -2) when p_k is a polynomial of degree < kPolyRank in the
+//           lag to within 2^-44 max|p_k| (least squares on the 2n-1 lags);
+//   general (class -1) otherwise (FFT convolution and int8 Gram).
+// For a smooth term the Toeplitz matrix is T_k = T_poly + E with T_poly[a][b]
+// = P(a-b), P of degree < kPolyRank, |E| <= delta.  The rows and columns of
+// T_poly lie in the span of the polynomials of degree < kPolyRank on the cell
+// grid, with orthonormal basis Q (rows Q[r][a]), so T_poly = Q^T Q T_poly Q^T Q
+// and
+//   G_k = U T_k U^T ~ X S_k X^T,   X = U Q^T [R_f][R],   S_k = Q T_k Q^T [R][R],
+// with |dG_ij| <= 2 (2n-1) delta |u_i|_2 |u_j|_2.  S_k comes from the half
+// spectra of Q's rows and of the kernel embedding (Parseval); the Gram costs
+// 2 R_f^2 R flops instead of an FFT convolution plus an int8 Gram over n.
+//
+// The basis is the orthonormal discrete Chebyshev (Gram) polynomials on the
+// points x = 0..N-1, from the three-term recurrence
+//   phi_0 = N^-1/2,  phi_1 = (3 / (N (N^2-1)))^1/2 z,  z = 2x - N + 1,
+//   phi_{r+1} = A_r z phi_r - B_r phi_{r-1},
+//   A_r = ((2r+1)(2r+3) / (N^2-(r+1)^2))^1/2 / (r+1),
+//   B_r = r/(r+1) ((2r+3)(N^2-r^2) / ((2r-1)(N^2-(r+1)^2)))^1/2,
+// evaluated point by point (coefficients from the host).
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int RQ = kPolyRank;
+
+__device__ inline void poly_eval(const PolyCoef &pc, int x, double (&ph)[RQ])
+{
+    const double z = 2.0 * x - pc.N + 1.0;
+    ph[0] = pc.c0;
+    ph[1] = pc.c1 * z;
+#pragma unroll
+    for (int r = 1; r < RQ - 1; ++r)
+        ph[r + 1] = pc.A[r] * z * ph[r] - pc.B[r] * ph[r - 1];
+}
+
+// sum over the 256 threads of a block, for RQ values at once (result in every thread)
+__device__ inline void block_sum(double (&v)[RQ], double (*red)[RQ])
+{
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        for (int o = 32; o > 0; o >>= 1)
+            v[r] += __shfl_xor(v[r], o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < RQ) {
+        double w = 0.0;
+#pragma unroll
+        for (int r = 0; r < RQ; ++r)
+            w = lane == r ? v[r] : w;
+        red[wave][lane] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        v[r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    __syncthreads();
+}
+
+__device__ inline double block_max(double v, double *red4)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0)
+        red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = fmax(fmax(red4[0], red4[1]), fmax(red4[2], red4[3]));
+    __syncthreads();
+    return v;
+}
+
+// one workgroup (256 threads) per term
+__global__ __launch_bounds__(256) void term_class_kernel(const double *__restrict__ p, int n,
+                                                         PolyCoef lag, int smooth_ok,
+                                                         int *__restrict__ cls)
+{
+    __shared__ double red[4][RQ];
+    __shared__ double red4[4];
+    __shared__ double part[2][4];
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double *pk = p + (long)k * (2L * n - 1) + (n - 1);  // pk[lag]
+    const int L = 2 * n - 1;
+
+    // narrow: smallest B <= min(16, n-1) with the tail beyond B below 2^-60 of the sum
+    const int cap = n - 1 < kBandMax ? n - 1 : kBandMax;
+    double tot = 0.0, out = 0.0;
+    for (int m = tid; m < n; m += 256) {
+        const double a = fabs(pk[m]) + (m > 0 ? fabs(pk[-m]) : 0.0);
+        tot += a;
+        if (m > cap)
+            out += a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o);
+        out += __shfl_xor(out, o);
+    }
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = tot;
+        part[1][tid >> 6] = out;
+    }
+    __syncthreads();
+    tot = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
+    out = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+    const double thr = ldexp(tot, -60);
+    if (out <= thr) {
+        if (tid == 0) {
+            int B = cap;
+            double tail = out;
+            while (B > 0) {
+                const double add = fabs(pk[B]) + fabs(pk[-B]);
+                if (tail + add > thr)
+                    break;
+                tail += add;
+                --B;
+            }
+            cls[k] = B;
+        }
+        return;  // uniform: every thread saw the same out and thr
+    }
+    if (!smooth_ok) {
+        if (tid == 0)
+            cls[k] = -1;
+        return;
+    }
+
+    // smooth: least-squares polynomial fit on the lags x = m + n - 1 = 0..L-1
+    double c[RQ], ph[RQ];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        c[r] = 0.0;
+    double pmax = 0.0;
+    for (int x = tid; x < L; x += 256) {
+        const double v = pk[x - (n - 1)];
+        pmax = fmax(pmax, fabs(v));
+        poly_eval(lag, x, ph);
+#pragma unroll
+        for (int r = 0; r < RQ; ++r)
+            c[r] = fma(ph[r], v, c[r]);
+    }
+    block_sum(c, red);
+    pmax = block_max(pmax, red4);
+    double res = 0.0;
+    for (int x = tid; x < L; x += 256) {
+        poly_eval(lag, x, ph);
+        double fit = 0.0;
+#pragma unroll
+        for (int r = 0; r < RQ; ++r)
+            fit = fma(c[r], ph[r], fit);
+        res = fmax(res, fabs(pk[x - (n - 1)] - fit));
+    }
+    res = block_max(res, red4);
+    if (tid == 0)
+        cls[k] = (pmax > 0.0 && res <= ldexp(pmax, -44)) ? -2 : -1;
+}
+
+// klist = the terms that are not smooth, in increasing order; nk = their count
+__global__ void term_list_kernel(const int *__restrict__ cls, int R_N, int *__restrict__ klist,
+                                 int *__restrict__ nk)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int c = 0;
+        for (int k = 0; k < R_N; ++k)
+            if (cls[k] != -2)
+                klist[c++] = k;
+        *nk = c;
+    }
+}
+
+// Q[r][a] = phi_r(a) on the cell grid
+__global__ __launch_bounds__(256) void poly_rows_kernel(int n, PolyCoef cell,
+                                                        double *__restrict__ Q)
+{
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= n)
+        return;
+    double ph[RQ];
+    poly_eval(cell, a, ph);
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        Q[(long)r * n + a] = ph[r];
+}
+
+// X[i][r] = sum_a U[i][a] Q[r][a]: workgroup (row block, cell split) takes 64
+// rows of U and one of PKS ranges of cells, in chunks of 64 cells staged in LDS
+// with the matching columns of Q; each thread accumulates 8 outputs.  The
+// splits are added in a fixed order by poly_project_reduce.
+constexpr int PRT = 64, PKC = 64, PKS = kProjectSplit;
+__global__ __launch_bounds__(256) void poly_project_kernel(const double *__restrict__ U, int n,
+                                                           int R_f, const double *__restrict__ Q,
+                                                           double *__restrict__ part)
+{
+    __shared__ double Us[PRT][PKC + 1];
+    __shared__ double Qs[RQ][PKC + 1];
+    const int i0 = blockIdx.x * PRT;
+    const int ks = blockIdx.y;
+    const int c0 = (int)((long)ks * n / PKS), c1 = (int)((long)(ks + 1) * n / PKS);
+    const int tid = threadIdx.x;
+    const int row = tid >> 2, r0 = (tid & 3) * 8;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int a0 = c0; a0 < c1; a0 += PKC) {
+        for (int e = tid; e < PRT * PKC; e += 256) {
+            const int rr = e / PKC, aa = e % PKC;
+            Us[rr][aa] = (i0 + rr < R_f && a0 + aa < c1) ? U[(long)(i0 + rr) * n + a0 + aa] : 0.0;
+        }
+        for (int e = tid; e < RQ * PKC; e += 256) {
+            const int rr = e / PKC, aa = e % PKC;
+            Qs[rr][aa] = a0 + aa < c1 ? Q[(long)rr * n + a0 + aa] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int aa = 0; aa < PKC; ++aa) {
+            const double u = Us[row][aa];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                acc[q] = fma(u, Qs[r0 + q][aa], acc[q]);
+        }
+        __syncthreads();
+    }
+    if (i0 + row < R_f) {
+        double *out = part + ((long)ks * R_f + i0 + row) * RQ + r0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            out[q] = acc[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void poly_project_reduce(const double *__restrict__ part,
+                                                           int R_f, double *__restrict__ X)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)R_f * RQ)
+        return;
+    double v = 0.0;
+    for (int ks = 0; ks < PKS; ++ks)
+        v += part[(long)ks * R_f * RQ + e];
+    X[e] = v;
+}
+
+// S_k = Q T_k Q^T for the smooth terms from the half spectra (real signals of
+// length N = 2M, zero-padded, so the circular product is the aperiodic one on
+// the cells):  S_k[r][s] = (1/N) sum_{w=0}^{M} m_w Re(conj(Qh_r(w)) Ch_k(w) Qh_s(w)),
+// m_0 = m_M = 1, else 2.  Workgroup (k, split) sums one range of frequencies in
+// chunks staged in LDS; its four waves take every fourth frequency and each
+// thread a 4 x 4 block of (r, s), and the waves' sums are added in LDS.
+// spectral_reduce adds the splits in a fixed order.
+constexpr int SW = 64;  // frequencies per LDS chunk
+__global__ __launch_bounds__(256) void spectral_gram_kernel(const double2 *__restrict__ Qspec,
+                                                            const double2 *__restrict__ Cspec,
+                                                            int M, const int *__restrict__ cls,
+                                                            double *__restrict__ partial)
+{
+    __shared__ double2 Qs[RQ][SW + 1];
+    __shared__ double2 Cs[SW];
+    __shared__ double red[4][RQ * RQ / 2];
+    const int k = blockIdx.x, sp = blockIdx.y;
+    if (cls[k] != -2)
+        return;
+    const int tot = M + 1;
+    const int w0 = (int)((long)sp * tot / gridDim.y);
+    const int w1 = (int)((long)(sp + 1) * tot / gridDim.y);
+    const int tid = threadIdx.x;
+    const int grp = tid >> 6, t64 = tid & 63;
+    const int rb = (t64 >> 3) * 4, sb = (t64 & 7) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = 0.0;
+    const double2 *Ck = Cspec + (long)k * (M + 1);
+    for (int wb = w0; wb < w1; wb += SW) {
+        const int cnt = w1 - wb < SW ? w1 - wb : SW;
+        for (int e = tid; e < RQ * SW; e += 256) {
+            const int rr = e / SW, ww = e % SW;
+            Qs[rr][ww] = ww < cnt ? Qspec[(long)rr * (M + 1) + wb + ww] : make_double2(0.0, 0.0);
+        }
+        if (tid < SW)
+            Cs[tid] = tid < cnt ? Ck[wb + tid] : make_double2(0.0, 0.0);
+        __syncthreads();
+        for (int ww = grp; ww < cnt; ww += 4) {
+            const int w = wb + ww;
+            const double m = (w == 0 || w == M) ? 1.0 : 2.0;
+            const double2 c = Cs[ww];
+            double2 ar[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const double2 q = Qs[rb + a][ww];
+                // m conj(q) c
+                ar[a] = make_double2(m * (q.x * c.x + q.y * c.y), m * (q.x * c.y - q.y * c.x));
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double2 qs = Qs[sb + b][ww];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    acc[a][b] = fma(ar[a].x, qs.x, fma(-ar[a].y, qs.y, acc[a][b]));
+            }
+        }
+        __syncthreads();
+    }
+    // add the four waves' sums: two halves of the 32 x 32 block through LDS
+    double *out = partial + ((long)k * gridDim.y + sp) * RQ * RQ;
+    for (int half = 0; half < 2; ++half) {
+        const bool mine = (rb >= 16 * half) && (rb < 16 * half + 16);
+        if (mine) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    red[grp][(rb - 16 * half + a) * RQ + sb + b] = acc[a][b];
+        }
+        __syncthreads();
+        for (int e = tid; e < RQ * RQ / 2; e += 256)
+            out[16 * half * RQ + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void spectral_reduce_kernel(const double *__restrict__ partial,
+                                                              const int *__restrict__ cls,
+                                                              int nsplit, double inv_n,
+                                                              double *__restrict__ S)
+{
+    const int k = blockIdx.x;
+    if (cls[k] != -2)
+        return;
+    for (int e = threadIdx.x; e < RQ * RQ; e += 256) {
+        double v = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp)
+            v += partial[((long)k * nsplit + sp) * RQ * RQ + e];
+        S[(long)k * RQ * RQ + e] = v * inv_n;
+    }
+}
+
+// G_k = X S_k X^T for the smooth terms: upper-triangle 64 x 64 tiles, mirrored
+constexpr int LT = 64;
+__global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restrict__ X,
+                                                           const double *__restrict__ S,
+                                                           const int *__restrict__ cls,
+                                                           double *__restrict__ G, int R_f,
+                                                           int ntiles)
+{
+    __shared__ double Xi[LT][RQ + 1];
+    __shared__ double Xj[LT][RQ + 1];
+    __shared__ double Ss[RQ][RQ + 1];
+    __shared__ double Y[LT][RQ + 1];
+    const int k = blockIdx.y;
+    if (cls[k] != -2)
+        return;
+    int t = blockIdx.x;
+    int ti = 0;
+    while (t >= ntiles - ti) {
+        t -= ntiles - ti;
+        ++ti;
+    }
+    const int tj = ti + t;
+    const int i0 = ti * LT, j0 = tj * LT;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < LT * RQ; e += 256) {
+        const int row = e / RQ, r = e % RQ;
+        Xi[row][r] = i0 + row < R_f ? X[(long)(i0 + row) * RQ + r] : 0.0;
+        Xj[row][r] = j0 + row < R_f ? X[(long)(j0 + row) * RQ + r] : 0.0;
+    }
+    const double *Sk = S + (long)k * RQ * RQ;
+    for (int e = tid; e < RQ * RQ; e += 256)
+        Ss[e / RQ][e % RQ] = Sk[e];
+    __syncthreads();
+    // Y = Xi S_k: thread -> row tid/4, columns (tid%4) + 4q
+    {
+        const int row = tid >> 2, c0 = tid & 3;
+#pragma unroll
+        for (int q = 0; q < RQ / 4; ++q) {
+            const int col = c0 + 4 * q;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < RQ; ++r)
+                s = fma(Xi[row][r], Ss[r][col], s);
+            Y[row][col] = s;
+        }
+    }
+    __syncthreads();
+    // G tile = Y Xj^T: thread -> rows 4 (tid/16) + a, columns (tid%16) + 16 b
+    const int ra = (tid >> 4) * 4, cb = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            acc[a][b] = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < RQ; ++r) {
+        double ya[4], xb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            ya[a] = Y[ra + a][r];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            xb[b] = Xj[cb + 16 * b][r];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = fma(ya[a], xb[b], acc[a][b]);
+    }
+    double *Gk = G + (long)k * R_f * R_f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + ra + a;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = j0 + cb + 16 * b;
+            if (i < R_f && j < R_f && i <= j) {
+                Gk[(long)i * R_f + j] = acc[a][b];
+                Gk[(long)j * R_f + i] = acc[a][b];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+PolyCoef poly_coef(int N)
+{
+    PolyCoef pc{};
+    const double Nd = N;
+    pc.N = Nd;
+    pc.c0 = 1.0 / std::sqrt(Nd);
+    pc.c1 = std::sqrt(3.0 / (Nd * (Nd * Nd - 1.0)));
+    for (int r = 1; r < kPolyRank - 1; ++r) {
+        const double rr = r;
+        const double den = Nd * Nd - (rr + 1.0) * (rr + 1.0);
+        pc.A[r] = std::sqrt((2.0 * rr + 1.0) * (2.0 * rr + 3.0) / den) / (rr + 1.0);
+        pc.B[r] = rr / (rr + 1.0) *
+                  std::sqrt((2.0 * rr + 3.0) * (Nd * Nd - rr * rr) / ((2.0 * rr - 1.0) * den));
+    }
+    return pc;
+}
+
+bool smooth_terms_supported(int n) { return n >= kPolyMinN; }
+
+hipError_t launch_term_class(const double *p, int n, int R_N, int *cls, hipStream_t stream)
+{
+    const int smooth = smooth_terms_supported(n) ? 1 : 0;
+    const PolyCoef lag = smooth ? poly_coef(2 * n - 1) : PolyCoef{};
+    hipLaunchKernelGGL(term_class_kernel, dim3(R_N), dim3(256), 0, stream, p, n, lag, smooth, cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_term_list(const int *cls, int R_N, int *klist, int *nk, hipStream_t stream)
+{
+    hipLaunchKernelGGL(term_list_kernel, dim3(1), dim3(64), 0, stream, cls, R_N, klist, nk);
+    return hipGetLastError();
+}
+
+hipError_t launch_poly_rows(int n, double *Q, hipStream_t stream)
+{
+    hipLaunchKernelGGL(poly_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n,
+                       poly_coef(n), Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q, double *part,
+                               double *X, hipStream_t stream)
+{
+    hipLaunchKernelGGL(poly_project_kernel, dim3((R_f + PRT - 1) / PRT, PKS), dim3(256), 0,
+                       stream, U, n, R_f, Q, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(poly_project_reduce, dim3((unsigned)(((long)R_f * RQ + 255) / 256)),
+                       dim3(256), 0, stream, part, R_f, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int N, int R_N,
+                                const int *cls, double *partial, double *S, hipStream_t stream)
+{
+    const int M = N / 2;
+    hipLaunchKernelGGL(spectral_gram_kernel, dim3(R_N, kSpectralSplit), dim3(256), 0, stream,
+                       Qspec, Cspec, M, cls, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(spectral_reduce_kernel, dim3(R_N), dim3(256), 0, stream, partial, cls,
+                       kSpectralSplit, 1.0 / (double)N, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
+                               int R_f, int R_N, hipStream_t stream)
+{
+    const int nt = (R_f + LT - 1) / LT;
+    dim3 grid(nt * (nt + 1) / 2, R_N);
+    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, S, cls, G, R_f, nt);
+    return hipGetLastError();
+}
+
+}  // namespace tc

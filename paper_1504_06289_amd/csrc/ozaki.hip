@@ -307,11 +307,14 @@ constexpr int G_BYTES = 4 * GT * AROW;  // 20480 per operand
 __global__ __launch_bounds__(256) void gram_i8_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
-    int R_f_pad, double *__restrict__ G, int R_f, int ntiles)
+    int R_f_pad, double *__restrict__ G, int R_f, int ntiles, const int *__restrict__ klist,
+    const int *__restrict__ nk)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[G_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[G_BYTES];
 
+    if (klist && (int)blockIdx.y >= *nk)
+        return;
     int t = blockIdx.x;
     int ti = 0;
     while (t >= ntiles - ti) {
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
         ++ti;
     }
     const int tj = ti + t;
-    const int k = blockIdx.y;
+    const int k = klist ? klist[blockIdx.y] : (int)blockIdx.y;
     const int i0 = ti * GT, j0 = tj * GT;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -439,17 +442,29 @@ __device__ inline int gw_offset(int sl, int row, int c16)
 __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
-    int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri)
+    int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri,
+    const int *__restrict__ klist, const int *__restrict__ nk)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[2][GW_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][GW_BYTES];
 
     const int w = blockIdx.x;
-    const int xcd = w & 7, local = w >> 3;
-    const int k = xcd + 8 * (local / ntri);
-    const int t = local % ntri;
-    if (k >= R_N)
-        return;
+    int k, t;
+    if (klist) {
+        // a subset of the terms: items in term order (balanced over the XCDs
+        // by the dispatcher's round robin)
+        const int kk = w / ntri;
+        t = w % ntri;
+        if (kk >= *nk)
+            return;
+        k = klist[kk];
+    } else {
+        const int xcd = w & 7, local = w >> 3;
+        k = xcd + 8 * (local / ntri);
+        t = local % ntri;
+        if (k >= R_N)
+            return;
+    }
     int tj = 0;
     while ((tj + 1) * (tj + 2) / 2 <= t)
         ++tj;
@@ -600,22 +615,24 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 }
 
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
-                          const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream)
+                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *klist,
+                          const int *nk, hipStream_t stream)
 {
     if (R_f >= 256 && L.R_f_pad % GT2 == 0) {
         const int nt = L.R_f_pad / GT2;
         const int ntri = nt * (nt + 1) / 2;
-        // items: for every XCD x, the terms k = x, x + 8, ... each with ntri tiles
-        const int kgroups = (R_N + 7) / 8;
-        const int items = 8 * kgroups * ntri;
+        // all terms: for every XCD x, the terms k = x, x + 8, ... each with ntri
+        // tiles; a term list: R_N * ntri items in term order (the excess exits)
+        const int items = klist ? R_N * ntri : 8 * ((R_N + 7) / 8) * ntri;
         hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
-                           L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri);
+                           L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
+                           klist, nk);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
     hipLaunchKernelGGL(gram_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, WS, EW,
-                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt);
+                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt, klist, nk);
     return hipGetLastError();
 }
 

@@ -110,7 +110,16 @@ struct ModeScratch {
     double2 *twN = nullptr;    // FFT twiddles
     double2 *Uspec = nullptr;  // half spectra of U rows
     double2 *Cspec = nullptr;  // half spectra of the kernel embeddings
-    int *band = nullptr;       // lag band of each kernel term (int8 FFT route)
+    // int8 FFT route: term classes and the low-rank Grams of smooth terms
+    int *cls = nullptr;        // class of each kernel term (launch_term_class)
+    int *klist = nullptr;      // terms that are not smooth, and their count
+    int *nk = nullptr;
+    double *Q = nullptr;       // [kPolyRank][n] orthonormal polynomials
+    double *X = nullptr;       // [R_f][kPolyRank] projections of U's rows
+    double *Xp = nullptr;      // partial sums of X over cell ranges
+    double2 *Qspec = nullptr;  // half spectra of Q's rows
+    double *Sp = nullptr;      // partial sums of S over frequency ranges
+    double *S = nullptr;       // [R_N][kPolyRank][kPolyRank] = Q T_k Q^T
 };
 
 ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram)
@@ -138,8 +147,19 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
         s.twN = c.take<double2>(N);
         s.Uspec = c.take<double2>((size_t)R_f * (N / 2 + 1));
         s.Cspec = c.take<double2>((size_t)R_N * (N / 2 + 1));
-        if (prec == TC_OZAKI_I8)
-            s.band = c.take<int>(R_N);
+        if (prec == TC_OZAKI_I8 && gram) {
+            s.cls = c.take<int>(R_N);
+            s.klist = c.take<int>(R_N);
+            s.nk = c.take<int>(1);
+            if (smooth_terms_supported(n)) {
+                s.Q = c.take<double>((size_t)kPolyRank * n);
+                s.X = c.take<double>((size_t)R_f * kPolyRank);
+                s.Xp = c.take<double>((size_t)kProjectSplit * R_f * kPolyRank);
+                s.Qspec = c.take<double2>((size_t)kPolyRank * (N / 2 + 1));
+                s.Sp = c.take<double>((size_t)R_N * kSpectralSplit * kPolyRank * kPolyRank);
+                s.S = c.take<double>((size_t)R_N * kPolyRank * kPolyRank);
+            }
+        }
     }
     return s;
 }
@@ -288,17 +308,29 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         if (r != TC_OK)
             return r;
         TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
-        TRYK("term_band", launch_term_band(p, n, R_N, s.band, st));
+        TRYK("term_class", launch_term_class(p, n, R_N, s.cls, st));
+        TRYK("term_list", launch_term_list(s.cls, R_N, s.klist, s.nk, st));
         TRYK("fft_conv_split", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN,
                                                nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane,
-                                               U, p, s.band, st));
-    } else {
-        const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
-        if (r != TC_OK)
-            return r;
-        TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
+                                               U, p, s.cls, st));
+        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, s.klist, s.nk, st));
+        if (smooth_terms_supported(n)) {
+            // smooth terms: G_k = X S_k X^T with S_k = Q T_k Q^T from the spectra
+            // of Q's rows and of the kernel
+            const int N = fft_length(n);
+            TRYK("poly_rows", launch_poly_rows(n, s.Q, st));
+            TRYK("poly_project", launch_poly_project(U, n, R_f, s.Q, s.Xp, s.X, st));
+            TRYK("rfft_rows", launch_rfft_rows(s.Q, kPolyRank, n, N, s.twN, s.Qspec, st));
+            TRYK("spectral_gram", launch_spectral_gram(s.Qspec, s.Cspec, N, R_N, s.cls, s.Sp, s.S, st));
+            TRYK("lowrank_gram", launch_lowrank_gram(s.X, s.S, s.cls, G, R_f, R_N, st));
+        }
+        return TC_OK;
     }
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, st));
+    const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
+    if (r != TC_OK)
+        return r;
+    TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, nullptr, st));
     return TC_OK;
 }
 

@@ -94,9 +94,11 @@ hipError_t launch_split_kernel_vectors(const double *p, int n, int R_N, const Oz
 hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS, const int *EP,
                               const OzakiLayout &L, double *W, int n, int R_f, int R_N,
                               hipStream_t stream);
-// G[k][i][j] = sum_a U[i][a] W[k][j][a] from the slices (binary64, symmetric)
+// G[k][i][j] = sum_a U[i][a] W[k][j][a] from the slices (binary64, symmetric),
+// for every k, or (klist != nullptr) for k = klist[0 .. *nk - 1] only
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
-                          const OzakiLayout &L, double *G, int R_f, int R_N, hipStream_t stream);
+                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *klist,
+                          const int *nk, hipStream_t stream);
 
 // ---- FFT route (fft.hip) ---------------------------------------------------
 // N = smallest power of two >= 2n-1; the route needs N/2 <= 4096 (n <= 4096).
@@ -109,18 +111,47 @@ hipError_t launch_rfft_rows(const double *X, int rows, int len, int N, const dou
 // half spectra [R_N][N/2+1] of the circulant embeddings of p [R_N][2n-1]
 hipError_t launch_rfft_kernel_embed(const double *p, int n, int R_N, int N, const double2 *twN,
                                     double2 *spec, hipStream_t stream);
-// band[k] for the int8 route: the smallest B <= min(16, n-1) such that the
-// kernel entries |p_k[m]|, |m| > B, sum to at most 2^-60 of sum_m |p_k[m]|,
-// or -1 (then term k is transformed)
-hipError_t launch_term_band(const double *p, int n, int R_N, int *band, hipStream_t stream);
 // W_k[j][t] (t < n) for all j, k from the spectra; output binary64 W
 // [R_N][R_f][n] (W != nullptr) or int8 slices WS [4][R_N][R_f_pad][n_pad] with
 // exponents EW [R_N][R_f_pad] (W == nullptr; padding rows zeroed).  With
-// band != nullptr (int8 output only), terms with band[k] >= 0 are convolved
-// directly from U [R_f][n] and p [R_N][2n-1] over lags |m| <= band[k].
+// band != nullptr (int8 output only; the term classes of launch_term_class),
+// terms of class B >= 0 are convolved directly from U [R_f][n] and p
+// [R_N][2n-1] over lags |m| <= B, and terms of class -2 are skipped.
 hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, int N, int R_f,
                            int R_N, const double2 *twN, double *W, int8_t *WS, int *EW,
                            int R_f_pad, int n_pad, long wplane, const double *U,
                            const double *p, const int *band, hipStream_t stream);
+
+// ---- term classes and smooth terms (lowrank.hip) ---------------------------
+constexpr int kBandMax = 16;   // widest band of a narrow term
+constexpr int kPolyRank = 32;  // polynomial degree < kPolyRank for a smooth term
+constexpr int kPolyMinN = 128; // smooth terms only for n >= kPolyMinN
+// coefficients of the orthonormal discrete Chebyshev polynomials on N points
+struct PolyCoef {
+    double N, c0, c1;
+    double A[kPolyRank], B[kPolyRank];
+};
+PolyCoef poly_coef(int N);
+bool smooth_terms_supported(int n);
+// cls[k]: B >= 0 narrow (band B), -2 smooth (polynomial to 2^-44 relative),
+// -1 general
+hipError_t launch_term_class(const double *p, int n, int R_N, int *cls, hipStream_t stream);
+// klist[0..nk-1]: the terms with cls != -2, increasing
+hipError_t launch_term_list(const int *cls, int R_N, int *klist, int *nk, hipStream_t stream);
+// Q[r][a], r < kPolyRank, a < n: orthonormal polynomials on the cell grid
+hipError_t launch_poly_rows(int n, double *Q, hipStream_t stream);
+// X[i][r] = sum_a U[i][a] Q[r][a]; part: scratch [kProjectSplit][R_f][kPolyRank]
+constexpr int kProjectSplit = 16;
+hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q, double *part,
+                               double *X, hipStream_t stream);
+// S[k] = Q T_k Q^T (kPolyRank x kPolyRank) for the terms of class -2, from the
+// half spectra of Q's rows [kPolyRank][N/2+1] and of the kernel embeddings
+// [R_N][N/2+1]; partial: scratch [R_N][kSpectralSplit][kPolyRank][kPolyRank]
+constexpr int kSpectralSplit = 16;
+hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int N, int R_N,
+                                const int *cls, double *partial, double *S, hipStream_t stream);
+// G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank])
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
+                               int R_f, int R_N, hipStream_t stream);
 
 }  // namespace tc
