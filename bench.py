@@ -108,10 +108,13 @@ def cpu_baseline(w, cols_req):
             "plain_fp64_s": dt_plain}
 
 
-def kernel_roofline(name, per_launch_ms, w, prec):
+def kernel_roofline(name, per_launch_ms, w, prec, gram_terms=None):
     """Algorithmic work of one launch of `name` on workload w (one mode, all
-    terms) and the matching roofline."""
+    terms, or the gram_terms terms the int8 Gram of the FFT route processes)
+    and the matching roofline."""
     n, R_f, R_N = w.n[0], w.R_f, w.R_N
+    if gram_terms is not None and name == "gram_i8":
+        R_N = gram_terms
     s = per_launch_ms * 1e-3
     peak = PEAK["int8" if name.endswith("_i8") else "fp32" if name.endswith("_f32")
                 else "bf16" if name.endswith("_bf16") else "fp64"]
@@ -197,14 +200,14 @@ def measured_traffic(name, w):
     return None
 
 
-def mfma_pct(prof, w, prec):
+def mfma_pct(prof, w, prec, gram_terms=None):
     """% of the dtype's MFMA peak executed by the matrix-core kernels of one
     step (Gram and direct Toeplitz products), from their measured times."""
     out = {}
     for name in ("gram_i8", "toeplitz_i8", "gram_f64", "toeplitz_f64", "gram_f32",
                  "toeplitz_f32", "gram_bf16", "toeplitz_bf16"):
         if name in prof:
-            r = kernel_roofline(name, prof[name][0] / prof[name][1], w, prec)
+            r = kernel_roofline(name, prof[name][0] / prof[name][1], w, prec, gram_terms)
             ex = r.get("executed", {"frac": r["frac"]})["frac"]
             out[name] = round(100.0 * ex, 2)
     return out
@@ -255,7 +258,13 @@ def main():
     tc.profile_enable(False)
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1]} for k, v in prof.items()}
     dom = max(prof.items(), key=lambda kv: kv[1][0])
-    roof = kernel_roofline(dom[0], dom[1][0] / dom[1][1], w, args.prec)
+    # terms the int8 Gram processes on the FFT route (smooth terms take the
+    # low-rank path); every term otherwise
+    cls = tc.term_classes(p)
+    gram_terms = None
+    if args.prec == "ozaki8" and tc.tune_get(w.n[0], w.R_f, w.R_N, args.prec) == "fft":
+        gram_terms = int((cls != -2).sum())
+    roof = kernel_roofline(dom[0], dom[1][0] / dom[1][1], w, args.prec, gram_terms)
 
     out = {
         "metric": "TEI Gram assembly GFLOP/s + % MFMA peak, mixed vs FP64, at rel err \u22641e-7",
@@ -275,7 +284,9 @@ def main():
                    "algorithm": tc.tune_get(w.n[0], w.R_f, w.R_N, args.prec),
                    "flops_per_step": F},
         "roofline": roof,
-        "mfma_peak_pct": mfma_pct(prof, w, args.prec),
+        "mfma_peak_pct": mfma_pct(prof, w, args.prec, gram_terms),
+        "term_classes": {"narrow": int((cls >= 0).sum()), "smooth": int((cls == -2).sum()),
+                         "general": int((cls == -1).sum())},
         "kernels_one_step": kernels,
         "autotune_ms_per_mode": {"direct": round(tuned[0][0], 4), "fft": round(tuned[0][1], 4)},
     }

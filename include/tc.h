@@ -89,9 +89,9 @@ typedef enum {
  * implicit-Toeplitz matrix-core product in the arithmetic selected by
  * tc_precision.  TC_ALGO_FFT: aperiodic convolution through a circulant
  * embedding of length N >= 2n-1 with binary64 FFTs (n <= 4096); the Grams then
- * use the tc_precision arithmetic.  With TC_OZAKI_I8 a kernel term whose
- * vector carries at most 2^-60 of its absolute sum beyond lag 16 is convolved
- * directly in binary64 over those lags instead.  TC_ALGO_AUTO: the entry of the tuning
+ * use the tc_precision arithmetic.  With TC_OZAKI_I8 the route treats narrow
+ * and smooth kernel terms separately (tc_term_classes).  TC_ALGO_AUTO: the
+ * entry of the tuning
  * table for the mode's (n, R_f, R_N, precision), else a built-in rule. */
 typedef enum {
     TC_ALGO_AUTO = 0,
@@ -152,6 +152,23 @@ tc_status tc_newton_kernel(int n, double h, int R_N, double u0, double hu,
 tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev,
                       const double *U_dev, double *W_dev, tc_precision prec,
                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tc_term_classes -- how the int8 FFT route (TC_OZAKI_I8 with TC_ALGO_FFT)
+ * treats each kernel term of a mode (diagnostics; the route computes the
+ * same classes internally).  cls_dev [R_N] device output:
+ *   B >= 0  narrow: sum_{|m| > B} |p_k[m]| <= 2^-60 sum_m |p_k[m]| with
+ *           B <= min(16, n-1) smallest; W_k by direct convolution over
+ *           |m| <= B;
+ *   -2      smooth (n >= 128 only): the least-squares polynomial of degree
+ *           < 32 in the lag reproduces p_k to within 2^-44 max|p_k| at every
+ *           lag; G_k = X S_k X^T at rank 32 from an orthonormal polynomial
+ *           basis Q of the cells (X = U Q^T, S_k = Q T_k Q^T), binary64,
+ *           |error of G_k[i][j]| <= 2 (2n-1) 2^-44 max|p_k| |u_i|_2 |u_j|_2;
+ *   -1      general: FFT convolution and the int8 Gram.
+ *   p_dev [R_N][2n-1] device.
+ */
+tc_status tc_term_classes(int n, int R_N, const double *p_dev, int *cls_dev, void *stream);
 
 /*
  * tc_tei_gram -- the TEI/Coulomb matrix of every instance (Section 3.2):

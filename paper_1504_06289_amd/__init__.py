@@ -4,4 +4,4 @@ two-electron-integral Gram assembly of Khoromskaia & Khoromskij
 Python binding (see api.py) plus the seeded synthetic workloads."""
 from .api import (TeiGram, TeiGramGraph, autotune, autotune_batched, convolve,  # noqa: F401
                   newton_kernel, profile_enable, profile_read, tei_gram, tei_gram_backward,
-                  tei_gram_batched, tune_get, tune_set)
+                  tei_gram_batched, term_classes, tune_get, tune_set)

@@ -32,7 +32,8 @@ TC_OP_TEI_GRAM_BACKWARD = 2
 # the ABI symbols declared in include/tc.h
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
            "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
-           "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read")
+           "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
+           "tc_term_classes")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.tc_profile_read.argtypes = [ctypes.c_int, ctypes.c_void_p, pd,
                                       ctypes.POINTER(ctypes.c_long)]
         L.tc_profile_read.restype = ctypes.c_int
+        L.tc_term_classes.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.tc_term_classes.restype = ctypes.c_int
         _lib = L
     return _lib
 

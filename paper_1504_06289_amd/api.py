@@ -83,6 +83,18 @@ def convolve(p: torch.Tensor, U: torch.Tensor, prec="fp64",
     return W
 
 
+def term_classes(p: torch.Tensor) -> np.ndarray:
+    """tc_term_classes: per kernel term, B >= 0 (narrow, band B), -2 (smooth,
+    low-rank Gram) or -1 (general), as the int8 FFT route treats it."""
+    _dev_f64(p, "p")
+    R_N, L = p.shape
+    n = (L + 1) // 2
+    cls = torch.empty(R_N, dtype=torch.int32, device=p.device)
+    check(_lib.lib().tc_term_classes(n, R_N, _ptr(p), _ptr(cls), _stream(p.device)),
+          "tc_term_classes")
+    return cls.cpu().numpy()
+
+
 def make_instance(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],
                   J: torch.Tensor, G: Optional[torch.Tensor] = None) -> TcInstance:
     _dev_f64(c, "c")

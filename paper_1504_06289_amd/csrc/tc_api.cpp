@@ -602,6 +602,15 @@ tc_status tc_newton_kernel(int n, double h, int R_N, double u0, double hu, doubl
     return TC_OK;
 }
 
+tc_status tc_term_classes(int n, int R_N, const double *p_dev, int *cls_dev, void *stream)
+{
+    if (!size_ok(n, 1, R_N) || !p_dev || !cls_dev)
+        return TC_ERR_INVALID_ARG;
+    if (launch_term_class(p_dev, n, R_N, cls_dev, (hipStream_t)stream) != hipSuccess)
+        return TC_ERR_HIP;
+    return TC_OK;
+}
+
 tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double *U_dev,
                       double *W_dev, tc_precision prec, void *ws, size_t ws_bytes, void *stream)
 {

@@ -198,3 +198,12 @@ def test_batch_workspace_is_per_branch(L):
     assert six == 4 * up(one)
     two = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 2, _lib.TC_FP64)
     assert two == 2 * up(one)
+
+
+def test_term_classes_rejects_bad_arguments(L):
+    v = ctypes.c_void_p(0x1000)
+    assert L.tc_term_classes(0, 4, v, v, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_term_classes(64, 0, v, v, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_term_classes(64, 4, None, v, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_term_classes(64, 4, v, None, None) == _lib.TC_ERR_INVALID_ARG
+

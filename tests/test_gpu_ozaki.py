@@ -158,3 +158,67 @@ def test_autograd_ozaki(tc, orc):
     dUr = orc.tei_gram_backward(c, ps, w.U, np.outer(wv, wv))
     for l in range(3):
         assert rel_fro(host(Us[l].grad), dUr[l]) <= TOL_J
+
+
+def test_term_classes_c3(tc, orc):
+    """The term classes of the 4096-cell kernel (R_N = 32) against the
+    criteria recomputed on the host: minimal band for narrow terms, and the
+    polynomial-fit residual for smooth and general ones (decisions within a
+    small margin of a threshold are not checked)."""
+    say("term classes c3")
+    w = wl.config("c3")
+    t, c, p = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu)
+    cls = tc.term_classes(p)
+    P = host(p)
+    n = w.n[0]
+    say(f"   classes: {cls.tolist()}")
+    lag = np.arange(-(n - 1), n) / (n - 1.0)
+    Qv, _ = np.linalg.qr(np.polynomial.chebyshev.chebvander(lag, 31))
+    for k in range(w.R_N):
+        a = np.abs(P[k])
+        tot = a.sum()
+        thr = 2.0 ** -60 * tot
+        # the outer entries summed directly (tot minus the centre would cancel)
+        tail = lambda B: a[:n - 1 - B].sum() + a[n + B:].sum()
+        if cls[k] >= 0:
+            B = int(cls[k])
+            assert B <= 16
+            assert tail(B) <= thr * (1 + 1e-9) + 1e-300
+            if B > 0:
+                assert tail(B - 1) > thr * (1 - 1e-9)
+            continue
+        assert tail(16) > thr * (1 - 1e-9)       # not narrow
+        res = np.abs(P[k] - Qv @ (Qv.T @ P[k])).max() / a.max()
+        if cls[k] == -2:
+            assert res <= 4 * 2.0 ** -44, (k, res)
+        else:
+            assert res > 2.0 ** -44 / 4, (k, res)
+    # this kernel: 7 narrow (t_k >= 85), 15 smooth (t_k <= 0.08), 10 general
+    assert (cls >= 0).sum() == 7 and (cls == -2).sum() == 15
+
+
+def test_smooth_term_grams_binary64_accuracy(tc, orc):
+    """The Grams of smooth terms come from the rank-32 polynomial projection
+    in binary64: within 2 (2n-1) 2^-44 max|p_k| |u_i| |u_j| of the oracle
+    (much tighter than the int8 bound the other terms meet)."""
+    say("smooth-term Grams")
+    w = wl.small_products((512, 512, 512), 48, R_N=12, b=8.0, seed=11)
+    c, ps = oracle_setup(orc, w)
+    with algorithm(tc, "fft", shapes_of(w), PREC):
+        J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC,
+                           save_G=True)
+    Jr, Gr = orc.tei_gram(c, ps, w.U, return_G=True)
+    G = host(G)
+    assert e_J(host(J), Jr) <= TOL_J
+    nsmooth = 0
+    for l in range(3):
+        cls = tc.term_classes(dev(ps[l]))
+        un = np.linalg.norm(w.U[l], axis=1)
+        n = w.n[l]
+        for k in np.nonzero(cls == -2)[0]:
+            nsmooth += 1
+            bound = 2 * (2 * n - 1) * 2.0 ** -44 * np.abs(ps[l][k]).max() * np.outer(un, un)
+            assert np.all(np.abs(G[l][k] - Gr[l][k]) <= bound + 1e-300), (l, k)
+            np.testing.assert_array_equal(G[l][k], G[l][k].T)
+    say(f"   smooth terms checked: {nsmooth}")
+    assert nsmooth > 0
