@@ -37,7 +37,9 @@
  *   - The caller owns every buffer.  The library never allocates, frees or
  *     synchronises: scratch memory comes from the caller's workspace (size
  *     from tc_workspace_bytes), and all work is enqueued on the caller's
- *     stream (a hipStream_t passed as void*; NULL = the default stream).
+ *     stream (a hipStream_t passed as void*; NULL = the default stream) or,
+ *     for tc_tei_gram, on internal streams forked from it and joined back
+ *     into it, so that it completes in the caller's stream order.
  *   - Arguments are validated before anything is enqueued; on any error no
  *     output is written.  Launch failures return TC_ERR_HIP.  Faults during
  *     execution surface at the caller's next synchronisation.
@@ -178,12 +180,14 @@ tc_status tc_term_classes(int n, int R_N, const double *p_dev, int *cls_dev, voi
  * backward pass can then skip recomputing them).
  *   inst  host array of count descriptors (pointers inside are device).
  *   count >= 1.   ws: tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec).
- * With count > 1 the instances run concurrently on four internal streams of
- * default priority (created at the first such call and kept for the life of
- * the process) that fork from and join back into `stream` through events,
- * so the call still completes in stream order and can be captured as one
- * graph with parallel branches.  Calls with count > 1 from several host
- * threads are serialised while they enqueue.
+ * The work runs on four internal streams of default priority (created at
+ * the first call and kept for the life of the process) that fork from and
+ * join back into `stream` through events, so the call still completes in
+ * stream order and can be captured as one graph with parallel branches.
+ * With count == 1 the Grams of the three modes run concurrently, each in its
+ * own workspace region, and the Hadamard sum follows on `stream`; with
+ * count > 1 the instances run concurrently and the modes of each in turn.
+ * Calls from several host threads are serialised while they enqueue.
  */
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec,
                       void *ws, size_t ws_bytes, void *stream);
@@ -238,7 +242,10 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
 /*
  * Kernel timing (diagnostics).  tc_profile_enable(1) makes every kernel
  * launch of the library record a pair of HIP events on its stream (events
- * are created on demand, so do not enable it during graph capture).
+ * are created on demand, so do not enable it during graph capture).  While
+ * it is on, tc_tei_gram runs the three modes of a lone instance in turn on
+ * the caller's stream, so that every recorded duration is that of the kernel
+ * alone on the device.
  * tc_profile_read synchronises the recorded events, writes up to
  * max_kernels entries (kernel name, total milliseconds, number of launches)
  * accumulated since the previous read, clears them, and returns the number

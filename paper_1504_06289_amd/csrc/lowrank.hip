@@ -41,7 +41,11 @@ __device__ inline void poly_eval(const PolyCoef &pc, int x, double (&ph)[RQ])
         ph[r + 1] = pc.A[r] * z * ph[r] - pc.B[r] * ph[r - 1];
 }
 
-// sum over the 256 threads of a block, for RQ values at once (result in every thread)
+constexpr int TCT = 256;        // threads of the term-class workgroup
+constexpr int TCW = TCT / 64;   // its waves
+
+// sum over the TCT threads of a block, for RQ values at once (result in every
+// thread; fixed order)
 __device__ inline void block_sum(double (&v)[RQ], double (*red)[RQ])
 {
 #pragma unroll
@@ -58,31 +62,38 @@ __device__ inline void block_sum(double (&v)[RQ], double (*red)[RQ])
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RQ; ++r)
-        v[r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    for (int r = 0; r < RQ; ++r) {
+        double t = 0.0;
+        for (int wv = 0; wv < TCW; ++wv)
+            t += red[wv][r];
+        v[r] = t;
+    }
     __syncthreads();
 }
 
-__device__ inline double block_max(double v, double *red4)
+__device__ inline double block_max(double v, double *redw)
 {
     for (int o = 32; o > 0; o >>= 1)
         v = fmax(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0)
-        red4[threadIdx.x >> 6] = v;
+        redw[threadIdx.x >> 6] = v;
     __syncthreads();
-    v = fmax(fmax(red4[0], red4[1]), fmax(red4[2], red4[3]));
+    v = redw[0];
+    for (int wv = 1; wv < TCW; ++wv)
+        v = fmax(v, redw[wv]);
     __syncthreads();
     return v;
 }
 
-// one workgroup (256 threads) per term
-__global__ __launch_bounds__(256) void term_class_kernel(const double *__restrict__ p, int n,
+// one workgroup (TCT threads) per term
+__global__ __launch_bounds__(TCT) void term_class_kernel(const double *__restrict__ p, int n,
                                                          PolyCoef lag, int smooth_ok,
                                                          int *__restrict__ cls)
 {
-    __shared__ double red[4][RQ];
-    __shared__ double red4[4];
-    __shared__ double part[2][4];
+    __shared__ double red[TCW][RQ];
+    __shared__ double redw[TCW];
+    __shared__ double part[2][TCW];
+    __shared__ double cA[RQ], cB[RQ];
     const int k = blockIdx.x;
     const int tid = threadIdx.x;
     const double *pk = p + (long)k * (2L * n - 1) + (n - 1);  // pk[lag]
@@ -91,7 +102,7 @@ __global__ __launch_bounds__(256) void term_class_kernel(const double *__restric
     // narrow: smallest B <= min(16, n-1) with the tail beyond B below 2^-60 of the sum
     const int cap = n - 1 < kBandMax ? n - 1 : kBandMax;
     double tot = 0.0, out = 0.0;
-    for (int m = tid; m < n; m += 256) {
+    for (int m = tid; m < n; m += TCT) {
         const double a = fabs(pk[m]) + (m > 0 ? fabs(pk[-m]) : 0.0);
         tot += a;
         if (m > cap)
@@ -106,8 +117,12 @@ __global__ __launch_bounds__(256) void term_class_kernel(const double *__restric
         part[1][tid >> 6] = out;
     }
     __syncthreads();
-    tot = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
-    out = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+    tot = 0.0;
+    out = 0.0;
+    for (int wv = 0; wv < TCW; ++wv) {
+        tot += part[0][wv];
+        out += part[1][wv];
+    }
     const double thr = ldexp(tot, -60);
     if (out <= thr) {
         if (tid == 0) {
@@ -130,47 +145,53 @@ __global__ __launch_bounds__(256) void term_class_kernel(const double *__restric
         return;
     }
 
-    // smooth: least-squares polynomial fit on the lags x = m + n - 1 = 0..L-1
-    double c[RQ], ph[RQ];
+    // smooth: least-squares polynomial fit on the lags x = m + n - 1 = 0..L-1.
+    // The basis values are produced by the recurrence as they are consumed
+    // (two live values), with its coefficients in LDS.
+    if (tid < RQ) {
+        cA[tid] = lag.A[tid];
+        cB[tid] = lag.B[tid];
+    }
+    __syncthreads();
+    double c[RQ];
 #pragma unroll
     for (int r = 0; r < RQ; ++r)
         c[r] = 0.0;
     double pmax = 0.0;
-    for (int x = tid; x < L; x += 256) {
+    for (int x = tid; x < L; x += TCT) {
         const double v = pk[x - (n - 1)];
         pmax = fmax(pmax, fabs(v));
-        poly_eval(lag, x, ph);
+        const double z = 2.0 * x - lag.N + 1.0;
+        double f0 = lag.c0, f1 = lag.c1 * z;
+        c[0] = fma(f0, v, c[0]);
+        c[1] = fma(f1, v, c[1]);
 #pragma unroll
-        for (int r = 0; r < RQ; ++r)
-            c[r] = fma(ph[r], v, c[r]);
+        for (int r = 1; r < RQ - 1; ++r) {
+            const double f2 = cA[r] * z * f1 - cB[r] * f0;
+            c[r + 1] = fma(f2, v, c[r + 1]);
+            f0 = f1;
+            f1 = f2;
+        }
     }
     block_sum(c, red);
-    pmax = block_max(pmax, red4);
+    pmax = block_max(pmax, redw);
     double res = 0.0;
-    for (int x = tid; x < L; x += 256) {
-        poly_eval(lag, x, ph);
-        double fit = 0.0;
+    for (int x = tid; x < L; x += TCT) {
+        const double z = 2.0 * x - lag.N + 1.0;
+        double f0 = lag.c0, f1 = lag.c1 * z;
+        double fit = fma(c[1], f1, c[0] * f0);
 #pragma unroll
-        for (int r = 0; r < RQ; ++r)
-            fit = fma(c[r], ph[r], fit);
+        for (int r = 1; r < RQ - 1; ++r) {
+            const double f2 = cA[r] * z * f1 - cB[r] * f0;
+            fit = fma(c[r + 1], f2, fit);
+            f0 = f1;
+            f1 = f2;
+        }
         res = fmax(res, fabs(pk[x - (n - 1)] - fit));
     }
-    res = block_max(res, red4);
+    res = block_max(res, redw);
     if (tid == 0)
         cls[k] = (pmax > 0.0 && res <= ldexp(pmax, -44)) ? -2 : -1;
-}
-
-// klist = the terms that are not smooth, in increasing order; nk = their count
-__global__ void term_list_kernel(const int *__restrict__ cls, int R_N, int *__restrict__ klist,
-                                 int *__restrict__ nk)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int c = 0;
-        for (int k = 0; k < R_N; ++k)
-            if (cls[k] != -2)
-                klist[c++] = k;
-        *nk = c;
-    }
 }
 
 // Q[r][a] = phi_r(a) on the cell grid
@@ -187,11 +208,11 @@ __global__ __launch_bounds__(256) void poly_rows_kernel(int n, PolyCoef cell,
         Q[(long)r * n + a] = ph[r];
 }
 
-// X[i][r] = sum_a U[i][a] Q[r][a]: workgroup (row block, cell split) takes 64
+// X[i][r] = sum_a U[i][a] Q[r][a]: workgroup (row block, cell split) takes 32
 // rows of U and one of PKS ranges of cells, in chunks of 64 cells staged in LDS
-// with the matching columns of Q; each thread accumulates 8 outputs.  The
+// with the matching columns of Q; each thread accumulates 4 outputs.  The
 // splits are added in a fixed order by poly_project_reduce.
-constexpr int PRT = 64, PKC = 64, PKS = kProjectSplit;
+constexpr int PRT = 32, PKC = 64, PKS = kProjectSplit;
 __global__ __launch_bounds__(256) void poly_project_kernel(const double *__restrict__ U, int n,
                                                            int R_f, const double *__restrict__ Q,
                                                            double *__restrict__ part)
@@ -202,8 +223,8 @@ __global__ __launch_bounds__(256) void poly_project_kernel(const double *__restr
     const int ks = blockIdx.y;
     const int c0 = (int)((long)ks * n / PKS), c1 = (int)((long)(ks + 1) * n / PKS);
     const int tid = threadIdx.x;
-    const int row = tid >> 2, r0 = (tid & 3) * 8;
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int row = tid >> 3, r0 = (tid & 7) * 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int a0 = c0; a0 < c1; a0 += PKC) {
         for (int e = tid; e < PRT * PKC; e += 256) {
             const int rr = e / PKC, aa = e % PKC;
@@ -214,11 +235,11 @@ __global__ __launch_bounds__(256) void poly_project_kernel(const double *__restr
             Qs[rr][aa] = a0 + aa < c1 ? Q[(long)rr * n + a0 + aa] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll 8
         for (int aa = 0; aa < PKC; ++aa) {
             const double u = Us[row][aa];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int q = 0; q < 4; ++q)
                 acc[q] = fma(u, Qs[r0 + q][aa], acc[q]);
         }
         __syncthreads();
@@ -226,7 +247,7 @@ __global__ __launch_bounds__(256) void poly_project_kernel(const double *__restr
     if (i0 + row < R_f) {
         double *out = part + ((long)ks * R_f + i0 + row) * RQ + r0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 4; ++q)
             out[q] = acc[q];
     }
 }
@@ -339,18 +360,39 @@ __global__ __launch_bounds__(256) void spectral_reduce_kernel(const double *__re
     }
 }
 
-// G_k = X S_k X^T for the smooth terms: upper-triangle 64 x 64 tiles, mirrored
+// Y[k] = X S_k ([R_f][kPolyRank]) for the smooth terms: one thread per entry
+__global__ __launch_bounds__(256) void lowrank_y_kernel(const double *__restrict__ X,
+                                                        const double *__restrict__ S,
+                                                        const int *__restrict__ cls, int R_f,
+                                                        double *__restrict__ Y)
+{
+    const int k = blockIdx.y;
+    if (cls[k] != -2)
+        return;
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)R_f * RQ)
+        return;
+    const long i = e / RQ;
+    const int s = (int)(e % RQ);
+    const double *x = X + i * RQ;
+    const double *Sk = S + (long)k * RQ * RQ;
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < RQ; ++r)
+        v = fma(x[r], Sk[r * RQ + s], v);
+    Y[(long)k * R_f * RQ + e] = v;
+}
+
+// G_k = Y_k X^T for the smooth terms: upper-triangle 64 x 64 tiles, mirrored
 constexpr int LT = 64;
 __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restrict__ X,
-                                                           const double *__restrict__ S,
+                                                           const double *__restrict__ Y,
                                                            const int *__restrict__ cls,
                                                            double *__restrict__ G, int R_f,
                                                            int ntiles)
 {
-    __shared__ double Xi[LT][RQ + 1];
-    __shared__ double Xj[LT][RQ + 1];
-    __shared__ double Ss[RQ][RQ + 1];
-    __shared__ double Y[LT][RQ + 1];
+    __shared__ double Ys[LT][RQ + 1];
+    __shared__ double Xs[LT][RQ + 1];
     const int k = blockIdx.y;
     if (cls[k] != -2)
         return;
@@ -363,30 +405,14 @@ __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restr
     const int tj = ti + t;
     const int i0 = ti * LT, j0 = tj * LT;
     const int tid = threadIdx.x;
+    const double *Yk = Y + (long)k * R_f * RQ;
     for (int e = tid; e < LT * RQ; e += 256) {
         const int row = e / RQ, r = e % RQ;
-        Xi[row][r] = i0 + row < R_f ? X[(long)(i0 + row) * RQ + r] : 0.0;
-        Xj[row][r] = j0 + row < R_f ? X[(long)(j0 + row) * RQ + r] : 0.0;
-    }
-    const double *Sk = S + (long)k * RQ * RQ;
-    for (int e = tid; e < RQ * RQ; e += 256)
-        Ss[e / RQ][e % RQ] = Sk[e];
-    __syncthreads();
-    // Y = Xi S_k: thread -> row tid/4, columns (tid%4) + 4q
-    {
-        const int row = tid >> 2, c0 = tid & 3;
-#pragma unroll
-        for (int q = 0; q < RQ / 4; ++q) {
-            const int col = c0 + 4 * q;
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < RQ; ++r)
-                s = fma(Xi[row][r], Ss[r][col], s);
-            Y[row][col] = s;
-        }
+        Ys[row][r] = i0 + row < R_f ? Yk[(long)(i0 + row) * RQ + r] : 0.0;
+        Xs[row][r] = j0 + row < R_f ? X[(long)(j0 + row) * RQ + r] : 0.0;
     }
     __syncthreads();
-    // G tile = Y Xj^T: thread -> rows 4 (tid/16) + a, columns (tid%16) + 16 b
+    // thread -> rows 4 (tid/16) + a, columns (tid%16) + 16 b
     const int ra = (tid >> 4) * 4, cb = tid & 15;
     double acc[4][4];
 #pragma unroll
@@ -394,15 +420,15 @@ __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restr
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             acc[a][b] = 0.0;
-#pragma unroll 8
+#pragma unroll 4
     for (int r = 0; r < RQ; ++r) {
         double ya[4], xb[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-            ya[a] = Y[ra + a][r];
+            ya[a] = Ys[ra + a][r];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-            xb[b] = Xj[cb + 16 * b][r];
+            xb[b] = Xs[cb + 16 * b][r];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -449,15 +475,10 @@ hipError_t launch_term_class(const double *p, int n, int R_N, int *cls, hipStrea
 {
     const int smooth = smooth_terms_supported(n) ? 1 : 0;
     const PolyCoef lag = smooth ? poly_coef(2 * n - 1) : PolyCoef{};
-    hipLaunchKernelGGL(term_class_kernel, dim3(R_N), dim3(256), 0, stream, p, n, lag, smooth, cls);
+    hipLaunchKernelGGL(term_class_kernel, dim3(R_N), dim3(TCT), 0, stream, p, n, lag, smooth, cls);
     return hipGetLastError();
 }
 
-hipError_t launch_term_list(const int *cls, int R_N, int *klist, int *nk, hipStream_t stream)
-{
-    hipLaunchKernelGGL(term_list_kernel, dim3(1), dim3(64), 0, stream, cls, R_N, klist, nk);
-    return hipGetLastError();
-}
 
 hipError_t launch_poly_rows(int n, double *Q, hipStream_t stream)
 {
@@ -493,12 +514,17 @@ hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int 
     return hipGetLastError();
 }
 
-hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
-                               int R_f, int R_N, hipStream_t stream)
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
+                               double *G, int R_f, int R_N, hipStream_t stream)
 {
+    hipLaunchKernelGGL(lowrank_y_kernel, dim3((unsigned)(((long)R_f * RQ + 255) / 256), R_N),
+                       dim3(256), 0, stream, X, S, cls, R_f, Y);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
     const int nt = (R_f + LT - 1) / LT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, S, cls, G, R_f, nt);
+    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, Y, cls, G, R_f, nt);
     return hipGetLastError();
 }
 

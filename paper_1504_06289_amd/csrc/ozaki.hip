@@ -304,16 +304,27 @@ __global__ __launch_bounds__(256) void toeplitz_i8_kernel(
 constexpr int GT = 64;
 constexpr int G_BYTES = 4 * GT * AROW;  // 20480 per operand
 
+// the kk-th term (in increasing k) whose class is not -2, or -1 if there are
+// fewer; uniform over the workgroup
+__device__ inline int nth_listed_term(const int *__restrict__ cls, int R_N, int kk)
+{
+    for (int k = 0; k < R_N; ++k)
+        if (cls[k] != -2 && kk-- == 0)
+            return k;
+    return -1;
+}
+
 __global__ __launch_bounds__(256) void gram_i8_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
-    int R_f_pad, double *__restrict__ G, int R_f, int ntiles, const int *__restrict__ klist,
-    const int *__restrict__ nk)
+    int R_f_pad, double *__restrict__ G, int R_f, int ntiles, int R_N,
+    const int *__restrict__ cls)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[G_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[G_BYTES];
 
-    if (klist && (int)blockIdx.y >= *nk)
+    const int k = cls ? nth_listed_term(cls, R_N, blockIdx.y) : (int)blockIdx.y;
+    if (k < 0)
         return;
     int t = blockIdx.x;
     int ti = 0;
@@ -322,7 +333,6 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
         ++ti;
     }
     const int tj = ti + t;
-    const int k = klist ? klist[blockIdx.y] : (int)blockIdx.y;
     const int i0 = ti * GT, j0 = tj * GT;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -443,21 +453,20 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
     int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri,
-    const int *__restrict__ klist, const int *__restrict__ nk)
+    const int *__restrict__ cls)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[2][GW_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][GW_BYTES];
 
     const int w = blockIdx.x;
     int k, t;
-    if (klist) {
-        // a subset of the terms: items in term order (balanced over the XCDs
-        // by the dispatcher's round robin)
-        const int kk = w / ntri;
+    if (cls) {
+        // the terms of class other than -2: items in term order (balanced
+        // over the XCDs by the dispatcher's round robin)
         t = w % ntri;
-        if (kk >= *nk)
+        k = nth_listed_term(cls, R_N, w / ntri);
+        if (k < 0)
             return;
-        k = klist[kk];
     } else {
         const int xcd = w & 7, local = w >> 3;
         k = xcd + 8 * (local / ntri);
@@ -615,24 +624,24 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 }
 
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
-                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *klist,
-                          const int *nk, hipStream_t stream)
+                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
+                          hipStream_t stream)
 {
     if (R_f >= 256 && L.R_f_pad % GT2 == 0) {
         const int nt = L.R_f_pad / GT2;
         const int ntri = nt * (nt + 1) / 2;
         // all terms: for every XCD x, the terms k = x, x + 8, ... each with ntri
-        // tiles; a term list: R_N * ntri items in term order (the excess exits)
-        const int items = klist ? R_N * ntri : 8 * ((R_N + 7) / 8) * ntri;
+        // tiles; classes given: R_N * ntri items in term order (the excess exits)
+        const int items = cls ? R_N * ntri : 8 * ((R_N + 7) / 8) * ntri;
         hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
                            L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
-                           klist, nk);
+                           cls);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
     hipLaunchKernelGGL(gram_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, WS, EW,
-                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt, klist, nk);
+                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt, R_N, cls);
     return hipGetLastError();
 }
 

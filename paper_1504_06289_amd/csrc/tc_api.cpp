@@ -112,14 +112,13 @@ struct ModeScratch {
     double2 *Cspec = nullptr;  // half spectra of the kernel embeddings
     // int8 FFT route: term classes and the low-rank Grams of smooth terms
     int *cls = nullptr;        // class of each kernel term (launch_term_class)
-    int *klist = nullptr;      // terms that are not smooth, and their count
-    int *nk = nullptr;
     double *Q = nullptr;       // [kPolyRank][n] orthonormal polynomials
     double *X = nullptr;       // [R_f][kPolyRank] projections of U's rows
     double *Xp = nullptr;      // partial sums of X over cell ranges
     double2 *Qspec = nullptr;  // half spectra of Q's rows
     double *Sp = nullptr;      // partial sums of S over frequency ranges
     double *S = nullptr;       // [R_N][kPolyRank][kPolyRank] = Q T_k Q^T
+    double *Y = nullptr;       // [R_N][R_f][kPolyRank] = X S_k
 };
 
 ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram)
@@ -149,8 +148,6 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
         s.Cspec = c.take<double2>((size_t)R_N * (N / 2 + 1));
         if (prec == TC_OZAKI_I8 && gram) {
             s.cls = c.take<int>(R_N);
-            s.klist = c.take<int>(R_N);
-            s.nk = c.take<int>(1);
             if (smooth_terms_supported(n)) {
                 s.Q = c.take<double>((size_t)kPolyRank * n);
                 s.X = c.take<double>((size_t)R_f * kPolyRank);
@@ -158,6 +155,7 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
                 s.Qspec = c.take<double2>((size_t)kPolyRank * (N / 2 + 1));
                 s.Sp = c.take<double>((size_t)R_N * kSpectralSplit * kPolyRank * kPolyRank);
                 s.S = c.take<double>((size_t)R_N * kPolyRank * kPolyRank);
+                s.Y = c.take<double>((size_t)R_N * R_f * kPolyRank);
             }
         }
     }
@@ -309,11 +307,10 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
             return r;
         TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
         TRYK("term_class", launch_term_class(p, n, R_N, s.cls, st));
-        TRYK("term_list", launch_term_list(s.cls, R_N, s.klist, s.nk, st));
         TRYK("fft_conv_split", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN,
                                                nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane,
                                                U, p, s.cls, st));
-        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, s.klist, s.nk, st));
+        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, s.cls, st));
         if (smooth_terms_supported(n)) {
             // smooth terms: G_k = X S_k X^T with S_k = Q T_k Q^T from the spectra
             // of Q's rows and of the kernel
@@ -322,7 +319,7 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
             TRYK("poly_project", launch_poly_project(U, n, R_f, s.Q, s.Xp, s.X, st));
             TRYK("rfft_rows", launch_rfft_rows(s.Q, kPolyRank, n, N, s.twN, s.Qspec, st));
             TRYK("spectral_gram", launch_spectral_gram(s.Qspec, s.Cspec, N, R_N, s.cls, s.Sp, s.S, st));
-            TRYK("lowrank_gram", launch_lowrank_gram(s.X, s.S, s.cls, G, R_f, R_N, st));
+            TRYK("lowrank_gram", launch_lowrank_gram(s.X, s.S, s.cls, s.Y, G, R_f, R_N, st));
         }
         return TC_OK;
     }
@@ -330,7 +327,7 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
     if (r != TC_OK)
         return r;
     TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, nullptr, st));
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, st));
     return TC_OK;
 }
 
@@ -343,22 +340,34 @@ int max_n(const tc_instance &I)
     return m;
 }
 
-// Workspace plan of one instance.  Layout: [W][G?][D?][per-mode scratch];
-// the per-mode scratch is sized for the largest mode and reused.
+// Workspace plan of one instance.  Layout: [G?][D?] and then either one
+// [W][per-mode scratch] region sized for the largest mode and reused by the
+// three modes in turn, or (split) one such region per mode, so that the modes
+// can run concurrently.
 struct InstancePlan {
-    double *W, *G, *D;
+    double *G, *D;
+    double *W[3];
     ModeScratch ms[3];
     size_t bytes;
 };
 
-InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bool backward)
+InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bool backward,
+                           bool split = false)
 {
     InstancePlan P{};
     Carver c(ws);
     const size_t F2 = (size_t)I.R_f * I.R_f;
-    P.W = c.take<double>((size_t)I.R_N * I.R_f * max_n(I));
     P.G = I.G_saved ? I.G_saved : c.take<double>(3 * (size_t)I.R_N * F2);
     P.D = backward ? c.take<double>((size_t)I.R_N * F2) : nullptr;
+    if (split) {
+        for (int l = 0; l < 3; ++l) {
+            P.W[l] = c.take<double>((size_t)I.R_N * I.R_f * I.n[l]);
+            P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true);
+        }
+        P.bytes = c.used;
+        return P;
+    }
+    P.W[0] = P.W[1] = P.W[2] = c.take<double>((size_t)I.R_N * I.R_f * max_n(I));
     const size_t scratch0 = c.used;
     size_t scratch_max = 0;
     for (int l = 0; l < 3; ++l) {
@@ -459,17 +468,45 @@ bool pool_init()
     return true;
 }
 
-tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st)
+bool profiling()
 {
-    const InstancePlan P = plan_instance(ws, I, prec, false);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
+// One instance: the Grams of the three modes, then the Hadamard sum.  With
+// `split` the workspace plan has one region per mode and the modes run
+// concurrently on three pool branches (forked from and joined back into st;
+// the caller holds g_pool_mu and the pool is initialised), except while
+// kernel timing is on, when they run in turn on st.
+tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st,
+                           bool split_plan = false)
+{
+    const InstancePlan P = plan_instance(ws, I, prec, false, split_plan);
     const size_t F2 = (size_t)I.R_f * I.R_f;
-    for (int l = 0; l < 3; ++l) {
+    const bool split = split_plan && !profiling();
+    if (split && hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    tc_status status = TC_OK;
+    for (int l = 0; l < 3 && status == TC_OK; ++l) {
+        hipStream_t sl = split ? g_pool.st[l] : st;
+        if (split && hipStreamWaitEvent(sl, g_pool.fork, 0) != hipSuccess) {
+            status = TC_ERR_HIP;
+            break;
+        }
         const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
-        const tc_status r = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W,
-                                       P.G + (size_t)l * I.R_N * F2, P.ms[l], st);
-        if (r != TC_OK)
-            return r;
+        status = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l],
+                            P.G + (size_t)l * I.R_N * F2, P.ms[l], sl);
     }
+    if (split) {
+        // join every branch, also after a failed launch
+        for (int l = 0; l < 3; ++l)
+            if (hipEventRecord(g_pool.join[l], g_pool.st[l]) != hipSuccess ||
+                hipStreamWaitEvent(st, g_pool.join[l], 0) != hipSuccess)
+                status = TC_ERR_HIP;
+    }
+    if (status != TC_OK)
+        return status;
     TRYK("hadamard_sum", launch_hadamard_sum(I.c, P.G, P.G + (size_t)I.R_N * F2,
                                              P.G + 2 * (size_t)I.R_N * F2, I.J, I.R_f, I.R_N, st));
     return TC_OK;
@@ -483,8 +520,8 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
     if (!I.G_saved) {
         for (int l = 0; l < 3; ++l) {
             const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
-            const tc_status r = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W,
-                                           P.G + (size_t)l * I.R_N * F2, P.ms[l], st);
+            const tc_status r = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l],
+                                           P.W[l], P.G + (size_t)l * I.R_N * F2, P.ms[l], st);
             if (r != TC_OK)
                 return r;
         }
@@ -494,10 +531,12 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
         const double *Gb = P.G + (size_t)((l + 2) % 3) * I.R_N * F2;
         TRYK("adjoint_d", launch_adjoint_d(I.c, Jbar, Ga, Gb, P.D, I.R_f, I.R_N, st));
         const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
-        const tc_status r = mode_W(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W, P.ms[l], st);
+        const tc_status r =
+            mode_W(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l], P.ms[l], st);
         if (r != TC_OK)
             return r;
-        TRYK("adjoint_gemm_f64", launch_adjoint_gemm_f64(P.D, P.W, dU[l], I.n[l], I.R_f, I.R_N, 2.0, st));
+        TRYK("adjoint_gemm_f64",
+             launch_adjoint_gemm_f64(P.D, P.W[l], dU[l], I.n[l], I.R_f, I.R_N, 2.0, st));
     }
     return TC_OK;
 }
@@ -540,8 +579,9 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
         for (int l = 0; l < 3; ++l)
             if (!size_ok(inst[i].n[l], inst[i].R_f, inst[i].R_N))
                 return (size_t)-1;
-    if (op == TC_OP_TEI_GRAM && count > 1)
-        return plan_batch(inst, count, prec).bytes;
+    if (op == TC_OP_TEI_GRAM)
+        return count > 1 ? plan_batch(inst, count, prec).bytes
+                         : plan_instance(nullptr, inst[0], prec, false, true).bytes;
     size_t w = 0;
     for (int i = 0; i < count; ++i) {
         const size_t wi =
@@ -641,13 +681,13 @@ tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec, voi
     if (need > 0 && (!ws || ws_bytes < need))
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    if (count == 1)
-        return forward_instance(inst[0], prec, ws, st);
-
-    const BatchPlan B = plan_batch(inst, count, prec);
     std::lock_guard<std::mutex> lk(g_pool_mu);
     if (!pool_init())
         return TC_ERR_HIP;
+    if (count == 1)  // one instance: its three modes on three branches
+        return forward_instance(inst[0], prec, ws, st, true);
+
+    const BatchPlan B = plan_batch(inst, count, prec);
     // fork: every branch waits for the work already queued on the caller's stream
     if (hipEventRecord(g_pool.fork, st) != hipSuccess)
         return TC_ERR_HIP;
@@ -747,7 +787,7 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
                             status = TC_ERR_HIP;
                         if (status == TC_OK)
                             status = mode_grams(prec, cand[a], I.n[l], I.R_f, I.R_N, I.p[l],
-                                                I.U[l], P.W, P.G, P.ms[l], st);
+                                                I.U[l], P.W[l], P.G, P.ms[l], st);
                     }
                     float t = 0.0f;
                     if (status == TC_OK &&

@@ -95,10 +95,10 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
                               const OzakiLayout &L, double *W, int n, int R_f, int R_N,
                               hipStream_t stream);
 // G[k][i][j] = sum_a U[i][a] W[k][j][a] from the slices (binary64, symmetric),
-// for every k, or (klist != nullptr) for k = klist[0 .. *nk - 1] only
+// for every k, or (cls != nullptr, device [R_N]) for the k with cls[k] != -2 only
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
-                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *klist,
-                          const int *nk, hipStream_t stream);
+                          const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
+                          hipStream_t stream);
 
 // ---- FFT route (fft.hip) ---------------------------------------------------
 // N = smallest power of two >= 2n-1; the route needs N/2 <= 4096 (n <= 4096).
@@ -136,12 +136,10 @@ bool smooth_terms_supported(int n);
 // cls[k]: B >= 0 narrow (band B), -2 smooth (polynomial to 2^-44 relative),
 // -1 general
 hipError_t launch_term_class(const double *p, int n, int R_N, int *cls, hipStream_t stream);
-// klist[0..nk-1]: the terms with cls != -2, increasing
-hipError_t launch_term_list(const int *cls, int R_N, int *klist, int *nk, hipStream_t stream);
 // Q[r][a], r < kPolyRank, a < n: orthonormal polynomials on the cell grid
 hipError_t launch_poly_rows(int n, double *Q, hipStream_t stream);
 // X[i][r] = sum_a U[i][a] Q[r][a]; part: scratch [kProjectSplit][R_f][kPolyRank]
-constexpr int kProjectSplit = 16;
+constexpr int kProjectSplit = 32;
 hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q, double *part,
                                double *X, hipStream_t stream);
 // S[k] = Q T_k Q^T (kPolyRank x kPolyRank) for the terms of class -2, from the
@@ -150,8 +148,9 @@ hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q,
 constexpr int kSpectralSplit = 16;
 hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int N, int R_N,
                                 const int *cls, double *partial, double *S, hipStream_t stream);
-// G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank])
-hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
-                               int R_f, int R_N, hipStream_t stream);
+// G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank];
+// Y: scratch [R_N][R_f][kPolyRank])
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
+                               double *G, int R_f, int R_N, hipStream_t stream);
 
 }  // namespace tc

@@ -58,27 +58,30 @@ def test_workspace_bytes(L):
     I = _inst(n=100, R_f=10, R_N=3)
     arr = (_lib.TcInstance * 1)(I)
     w = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
-    # W of one mode + the three modes' Grams + the FFT scratch of one mode
-    # (twiddles [N], spectra of U [R_f][N/2+1] and of the kernel [R_N][N/2+1],
-    # N = 256 for n = 100), each rounded up to 256 bytes
+    # one instance runs its three modes concurrently: the three modes' Grams,
+    # then per mode its W and its FFT scratch (twiddles [N], spectra of U
+    # [R_f][N/2+1] and of the kernel [R_N][N/2+1], N = 256 for n = 100), each
+    # rounded up to 256 bytes
     up = lambda x: (x + 255) // 256 * 256
     fft = up(16 * 256) + up(16 * 10 * 129) + up(16 * 3 * 129)
-    assert w == up(8 * 3 * 10 * 100) + up(8 * 3 * 3 * 100) + fft
-    # row-scaled precisions add the row exponents of U [R_f], p [R_N] and W [R_N][R_f]
+    mode = up(8 * 3 * 10 * 100) + fft
+    assert w == up(8 * 3 * 3 * 100) + 3 * mode
+    # row-scaled precisions add, per mode, the row exponents of U [R_f], p [R_N]
+    # and W [R_N][R_f]
     for prec in (_lib.TC_FP32, _lib.TC_BF16X3, _lib.TC_BF16X6):
         assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, prec) == \
-            w + up(4 * 10) + up(4 * 3) + up(4 * 3 * 10)
+            w + 3 * (up(4 * 10) + up(4 * 3) + up(4 * 3 * 10))
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
-    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
-        up(8 * 3 * 10 * 100) + fft
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == 3 * mode
+    # the adjoint runs the modes in turn: one W and one mode's scratch, and D
     wb = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_FP64)
     assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100) + fft
     # no FFT scratch beyond the FFT route's size limit (n > 4096)
     I = _inst(n=5000, R_f=2, R_N=1)
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
-    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == up(8 * 2 * 5000)
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == 3 * up(8 * 2 * 5000)
     bad = (_lib.TcInstance * 1)(_inst(n=0))
     assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, bad, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
     assert L.tc_workspace_bytes(7, arr, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
@@ -189,12 +192,15 @@ def test_autotune_rejects(L):
 
 def test_batch_workspace_is_per_branch(L):
     """A batch is spread over 4 branches, each with its own workspace region
-    sized for its largest instance."""
+    sized for its largest instance, whose modes run in turn (one mode region)."""
     insts = [_inst(n=64, R_f=8, R_N=4) for _ in range(6)]
     arr = (_lib.TcInstance * 6)(*insts)
-    one = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
+    single = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64)
     six = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 6, _lib.TC_FP64)
     up = lambda x: (x + 255) // 256 * 256
+    grams = up(8 * 3 * 4 * 8 * 8)
+    assert (single - grams) % 3 == 0   # a lone instance has three mode regions
+    one = grams + (single - grams) // 3
     assert six == 4 * up(one)
     two = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 2, _lib.TC_FP64)
     assert two == 2 * up(one)

@@ -284,14 +284,17 @@ def test_autotune_batched_then_batch_matches_oracle(tc, orc):
             tc.tune_set(*sh, "ozaki8", "auto")
 
 
+@pytest.mark.parametrize("count", [1, 3])
 @pytest.mark.parametrize("prec", ["fp64", "ozaki8"])
-def test_graph_replays_match_eager(tc, orc, prec):
-    """A batch captured in a HIP graph: every replay (with eager work and
-    synchronisations in between) reproduces the eager result bitwise, and
-    the eager result matches the oracle."""
-    say(f"graph replay {prec}")
+def test_graph_replays_match_eager(tc, orc, prec, count):
+    """A batch captured in a HIP graph (one instance: its modes on parallel
+    branches; three: the instances on parallel branches): every replay (with
+    eager work and synchronisations in between) reproduces the eager result
+    bitwise, and the eager result matches the oracle."""
+    say(f"graph replay {prec} count={count}")
     insts, refs = [], []
-    for i, (n, R_f, R_N) in enumerate([(300, 40, 6), (130, 70, 5), (64, 9, 4)]):
+    shapes = [((300, 257, 130), 40, 6), (130, 70, 5), (64, 9, 4)][:count]
+    for i, (n, R_f, R_N) in enumerate(shapes):
         w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=40 + i)
         c, ps = oracle_setup(orc, w)
         insts.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
