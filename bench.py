@@ -111,13 +111,15 @@ def cpu_baseline(w, cols_req):
             "plain_fp64_s": dt_plain}
 
 
-def kernel_roofline(name, per_launch_ms, w, prec, gram_terms=None):
-    """Algorithmic work of one launch of `name` on workload w (one mode, all
-    terms, or the gram_terms terms the int8 Gram of the FFT route processes)
-    and the matching roofline."""
+def kernel_roofline(name, per_launch_ms, w, prec, cls=None):
+    """Algorithmic work of one launch of `name` on workload w (one mode) and
+    the matching roofline.  cls: the term classes when the int8 FFT route
+    runs (the int8 Gram then processes the terms of class != -2, and the FFT
+    convolution transforms those of class -1 and convolves those of class
+    B >= 0 directly over 2B + 1 lags); otherwise every kernel takes all terms."""
     n, R_f, R_N = w.n[0], w.R_f, w.R_N
-    if gram_terms is not None and name == "gram_i8":
-        R_N = gram_terms
+    if cls is not None and name == "gram_i8":
+        R_N = int((cls != -2).sum())
     s = per_launch_ms * 1e-3
     peak = PEAK["int8" if name.endswith("_i8") else "fp32" if name.endswith("_f32")
                 else "bf16" if name.endswith("_bf16") else "fp64"]
@@ -153,14 +155,25 @@ def kernel_roofline(name, per_launch_ms, w, prec, gram_terms=None):
         while 2 * M < 2 * n - 1:
             M *= 2
         lg = max(1, M.bit_length() - 1)
-        flops = R_N * R_f * (5.0 * M * lg + 14.0 * (M + 1))
+        n_fft, n_out, direct = R_N, R_N, 0.0
+        if cls is not None and name == "fft_conv_split":
+            n_fft = int((cls == -1).sum())
+            n_out = int((cls != -2).sum())
+            direct = float(sum(2 * (2 * int(b) + 1) for b in cls if b >= 0))
+        flops = R_f * (n_fft * (5.0 * M * lg + 14.0 * (M + 1)) + direct * n)
         out = {"bound": "alu", "achieved": flops / s / 1e12, "unit": "TFLOP/s",
                "peak": PEAK["fp64"],
-               "work": f"R_N R_f (5 M log2 M + 14 (M+1)) = {flops:.4g} FP64 flops per launch"}
-        out_bytes = (4 if name == "fft_conv_split" else 8) * R_N * R_f * n
+               "work": f"R_f (T_fft (5 M log2 M + 14 (M+1)) + sum_narrow 2 (2B+1) n) = {flops:.4g} "
+                       f"FP64 flops per launch (T_fft = {n_fft} transformed terms)"}
+        out_bytes = (4 if name == "fft_conv_split" else 8) * n_out * R_f * n
         in_bytes = 16 * (M + 1) * (R_f + R_N)
         out["hbm_bytes"] = out_bytes + in_bytes
         out["hbm_GBs"] = (out_bytes + in_bytes) / s / 1e9
+    elif name == "hadamard_sum":
+        # reads the upper triangles of the 3 R_N Grams, writes all of J
+        byts = 8.0 * (3 * R_N * R_f * (R_f + 1) / 2 + R_f * R_f)
+        out = {"bound": "hbm", "achieved": byts / s / 1e9, "unit": "GB/s", "peak": HBM_GBS,
+               "work": f"8 B (3 R_N R_f (R_f+1)/2 + R_f^2) = {byts:.4g} bytes per launch"}
     else:
         return None
     out["frac"] = out["achieved"] / out["peak"]
@@ -203,14 +216,14 @@ def measured_traffic(name, w):
     return None
 
 
-def mfma_pct(prof, w, prec, gram_terms=None):
+def mfma_pct(prof, w, prec, cls=None):
     """% of the dtype's MFMA peak executed by the matrix-core kernels of one
     step (Gram and direct Toeplitz products), from their measured times."""
     out = {}
     for name in ("gram_i8", "toeplitz_i8", "gram_f64", "toeplitz_f64", "gram_f32",
                  "toeplitz_f32", "gram_bf16", "toeplitz_bf16"):
         if name in prof:
-            r = kernel_roofline(name, prof[name][0] / prof[name][1], w, prec, gram_terms)
+            r = kernel_roofline(name, prof[name][0] / prof[name][1], w, prec, cls)
             ex = r.get("executed", {"frac": r["frac"]})["frac"]
             out[name] = round(100.0 * ex, 2)
     return out
@@ -253,6 +266,17 @@ def main():
     tuned = tc.autotune(torch.from_numpy(c).to(dev), [p, p, p], U, prec=args.prec)
     ms = timed(lambda: step(args.prec), args.steps, args.warmup, torch)
     value = F / (ms * 1e-3) / 1e9
+    # host time of one tc_tei_gram call (enqueue only; the GPU runs behind)
+    t_, c_, p_ = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu, device=dev)
+    cd_ = torch.from_numpy(c_).to(dev)
+    host = []
+    for _ in range(max(3, args.steps)):
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        tc.tei_gram(cd_, [p_, p_, p_], U, prec=args.prec)
+        host.append((time.perf_counter() - h0) * 1e3)
+    torch.cuda.synchronize()
+    host_ms = float(np.median(host))
 
     # per-kernel times: a second timed region of the same K steps with the
     # library's HIP-event timing on (the three modes then run in turn, so each
@@ -268,10 +292,10 @@ def main():
     # terms the int8 Gram processes on the FFT route (smooth terms take the
     # low-rank path); every term otherwise
     cls = tc.term_classes(p)
-    gram_terms = None
+    route_cls = None
     if args.prec == "ozaki8" and tc.tune_get(w.n[0], w.R_f, w.R_N, args.prec) == "fft":
-        gram_terms = int((cls != -2).sum())
-    roof = kernel_roofline(dom[0], dom[1][0] / dom[1][1], w, args.prec, gram_terms)
+        route_cls = cls
+    roof = kernel_roofline(dom[0], dom[1][0] / dom[1][1], w, args.prec, route_cls)
 
     out = {
         "metric": "TEI Gram assembly GFLOP/s + % MFMA peak, mixed vs FP64, at rel err \u22641e-7",
@@ -291,11 +315,16 @@ def main():
                    "algorithm": tc.tune_get(w.n[0], w.R_f, w.R_N, args.prec),
                    "flops_per_step": F},
         "roofline": roof,
-        "mfma_peak_pct": mfma_pct(prof, w, args.prec, gram_terms),
+        "mfma_peak_pct": mfma_pct(prof, w, args.prec, route_cls),
+        "other_rooflines": {k: {"achieved": round(r["achieved"], 2), "unit": r["unit"],
+                                "frac": round(r["frac"], 4), "kernel_ms": round(r["kernel_ms"], 4)}
+                            for k, r in ((k, kernel_roofline(k, v[0] / v[1], w, args.prec, route_cls))
+                                         for k, v in prof.items() if k != dom[0]) if r},
         "term_classes": {"narrow": int((cls >= 0).sum()), "smooth": int((cls == -2).sum()),
                          "general": int((cls == -1).sum())},
         "kernels_one_step": kernels,
         "profiled_ms_per_step": round(ms_prof, 4),
+        "host_enqueue_ms_tei_gram": round(host_ms, 4),
         "autotune_ms_per_mode": {"direct": round(tuned[0][0], 4), "fft": round(tuned[0][1], 4)},
     }
     for s in shapes:
