@@ -275,6 +275,51 @@ tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, 
     return TC_OK;
 }
 
+// int8 FFT route, the part of a mode that depends only on the kernel vectors
+// (and n): twiddles, kernel spectra, term classes and, for smooth terms, the
+// polynomial basis Q, its spectra and S_k = Q T_k Q^T.
+tc_status int8fft_kernel_part(int n, int R_N, const double *p, const ModeScratch &s,
+                              hipStream_t st)
+{
+    const int N = fft_length(n);
+    TRYK("fft_twiddles", launch_fft_twiddles(s.twN, N, st));
+    TRYK("rfft_kernel_embed", launch_rfft_kernel_embed(p, n, R_N, N, s.twN, s.Cspec, st));
+    TRYK("term_class", launch_term_class(p, n, R_N, s.cls, st));
+    if (smooth_terms_supported(n)) {
+        TRYK("poly_rows", launch_poly_rows(n, s.Q, st));
+        TRYK("rfft_rows", launch_rfft_rows(s.Q, kPolyRank, n, N, s.twN, s.Qspec, st));
+        TRYK("spectral_gram",
+             launch_spectral_gram(s.Qspec, s.Cspec, N, R_N, s.cls, s.Sp, s.S, st));
+    }
+    return TC_OK;
+}
+
+// The part that depends on U, in the mode's scratch s, reading the kernel
+// part's results from kp: s itself, or the scratch of an earlier mode with the
+// same kernel vectors and n whose kernel part ran earlier on the same stream.
+// (Running the small smooth-term kernels before the convolution instead of
+// after the int8 Gram measured 0.1 ms slower per step with concurrent modes.)
+tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double *U, double *G,
+                         const ModeScratch &s, const ModeScratch &kp, hipStream_t st)
+{
+    const int N = fft_length(n);
+    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
+    if (&kp != &s)
+        TRYK("fft_twiddles", launch_fft_twiddles(s.twN, N, st));
+    TRYK("rfft_rows", launch_rfft_rows(U, R_f, n, N, s.twN, s.Uspec, st));
+    TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
+    TRYK("fft_conv_split", launch_fft_conv(s.Uspec, kp.Cspec, n, N, R_f, R_N, s.twN, nullptr,
+                                           s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, U, p,
+                                           kp.cls, st));
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, st));
+    if (smooth_terms_supported(n)) {
+        // smooth terms: G_k = X S_k X^T with X = U Q^T
+        TRYK("poly_project", launch_poly_project(U, n, R_f, kp.Q, s.Xp, s.X, st));
+        TRYK("lowrank_gram", launch_lowrank_gram(s.X, kp.S, kp.cls, s.Y, G, R_f, R_N, st));
+    }
+    return TC_OK;
+}
+
 // G_k = U^T T_k U for all k of one mode (W is scratch).
 tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N,
                      const double *p, const double *U, double *W, double *G,
@@ -300,29 +345,13 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
                                                bf16_pieces(prec), st));
         return TC_OK;
     }
-    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
     if (algo == TC_ALGO_FFT) {
-        const tc_status r = fft_spectra(n, R_f, R_N, p, U, s, st);
+        const tc_status r = int8fft_kernel_part(n, R_N, p, s, st);
         if (r != TC_OK)
             return r;
-        TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
-        TRYK("term_class", launch_term_class(p, n, R_N, s.cls, st));
-        TRYK("fft_conv_split", launch_fft_conv(s.Uspec, s.Cspec, n, fft_length(n), R_f, R_N, s.twN,
-                                               nullptr, s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane,
-                                               U, p, s.cls, st));
-        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, s.cls, st));
-        if (smooth_terms_supported(n)) {
-            // smooth terms: G_k = X S_k X^T with S_k = Q T_k Q^T from the spectra
-            // of Q's rows and of the kernel
-            const int N = fft_length(n);
-            TRYK("poly_rows", launch_poly_rows(n, s.Q, st));
-            TRYK("poly_project", launch_poly_project(U, n, R_f, s.Q, s.Xp, s.X, st));
-            TRYK("rfft_rows", launch_rfft_rows(s.Q, kPolyRank, n, N, s.twN, s.Qspec, st));
-            TRYK("spectral_gram", launch_spectral_gram(s.Qspec, s.Cspec, N, R_N, s.cls, s.Sp, s.S, st));
-            TRYK("lowrank_gram", launch_lowrank_gram(s.X, s.S, s.cls, s.Y, G, R_f, R_N, st));
-        }
-        return TC_OK;
+        return int8fft_u_part(n, R_f, R_N, p, U, G, s, s, st);
     }
+    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
     const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
     if (r != TC_OK)
         return r;
@@ -479,12 +508,32 @@ bool profiling()
 // concurrently on three pool branches (forked from and joined back into st;
 // the caller holds g_pool_mu and the pool is initialised), except while
 // kernel timing is on, when they run in turn on st.
+//
+// On the int8 FFT route, when the modes run in turn, a mode whose kernel
+// vectors and n equal those of an earlier mode (the same pointer: the common
+// case of one grid spacing in all three directions) reuses that mode's kernel
+// part (spectra, term classes, S_k) instead of recomputing it.  Concurrent
+// modes each compute their own: waiting for another branch's kernel part
+// makes the three chains reach their large kernels together, which measured
+// slower than the duplicated small kernels.
 tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st,
                            bool split_plan = false)
 {
     const InstancePlan P = plan_instance(ws, I, prec, false, split_plan);
     const size_t F2 = (size_t)I.R_f * I.R_f;
     const bool split = split_plan && !profiling();
+    tc_algorithm algo[3];
+    int owner[3];
+    for (int l = 0; l < 3; ++l) {
+        algo[l] = resolve(I.n[l], I.R_f, I.R_N, prec);
+        owner[l] = l;
+        const bool i8fft = prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT;
+        for (int m = 0; m < l && i8fft && !split; ++m)
+            if (owner[m] == m && algo[m] == algo[l] && I.p[m] == I.p[l] && I.n[m] == I.n[l]) {
+                owner[l] = m;
+                break;
+            }
+    }
     if (split && hipEventRecord(g_pool.fork, st) != hipSuccess)
         return TC_ERR_HIP;
     tc_status status = TC_OK;
@@ -494,9 +543,19 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
             status = TC_ERR_HIP;
             break;
         }
-        const tc_algorithm algo = resolve(I.n[l], I.R_f, I.R_N, prec);
-        status = mode_grams(prec, algo, I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l],
-                            P.G + (size_t)l * I.R_N * F2, P.ms[l], sl);
+        double *Gl = P.G + (size_t)l * I.R_N * F2;
+        const bool i8fft = prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT;
+        if (!i8fft) {
+            status = mode_grams(prec, algo[l], I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l], Gl,
+                                P.ms[l], sl);
+            continue;
+        }
+        const int o = owner[l];
+        if (o == l)
+            status = int8fft_kernel_part(I.n[l], I.R_N, I.p[l], P.ms[l], sl);
+        if (status == TC_OK)
+            status = int8fft_u_part(I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], Gl, P.ms[l], P.ms[o],
+                                    sl);
     }
     if (split) {
         // join every branch, also after a failed launch

@@ -102,8 +102,12 @@ def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols, algo):
     say(f"ozaki tei_gram sampled {name} {algo}")
     w = wl.config(name)
     c, ps = oracle_setup(orc, w)
+    # one grid spacing in all directions: one kernel tensor for the three
+    # modes, as a caller passes it (the modes then share its spectra)
+    assert all(np.array_equal(ps[0], q) for q in ps)
+    pd = dev(ps[0])
     with algorithm(tc, algo, shapes_of(w), PREC):
-        J = host(tc.tei_gram(dev(c), [dev(p) for p in ps], [dev(u) for u in w.U], prec=PREC))
+        J = host(tc.tei_gram(dev(c), [pd, pd, pd], [dev(u) for u in w.U], prec=PREC))
     rng = np.random.default_rng(321)
     S = np.sort(rng.choice(w.R_f, size=min(ncols, w.R_f), replace=False))
     Jc = orc.tei_gram_columns(c, ps, w.U, S)
@@ -115,6 +119,34 @@ def test_tei_gram_ozaki_sampled_full_size(tc, orc, name, ncols, algo):
     say(f"   e_J(block) = {err:.2e}, columns = {err_cols:.2e}")
     assert err <= TOL_J and err_cols <= TOL_J
     np.testing.assert_array_equal(J, J.T)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_tei_gram_ozaki_shared_kernel_tensor(tc, orc, algo):
+    """The three modes given one kernel tensor (whose spectra, term classes
+    and S_k the modes then share) give bitwise the J of three separate copies,
+    with the modes concurrent and with kernel timing on (modes in turn)."""
+    say(f"ozaki shared kernel tensor {algo}")
+    w = wl.small_products(300, 100, R_N=24, b=8.0, seed=11)
+    c, ps = oracle_setup(orc, w)
+    Us = [dev(u) for u in w.U]
+    pd = dev(ps[0])
+    with algorithm(tc, algo, shapes_of(w), PREC):
+        J_sep = host(tc.tei_gram(dev(c), [dev(p) for p in ps], Us, prec=PREC))
+        J_one = host(tc.tei_gram(dev(c), [pd, pd, pd], Us, prec=PREC))
+        tc.profile_enable(True)
+        try:
+            J_ser = host(tc.tei_gram(dev(c), [pd, pd, pd], Us, prec=PREC))
+        finally:
+            tc.profile_enable(False)
+            tc.profile_read()
+    np.testing.assert_array_equal(J_one, J_sep)
+    np.testing.assert_array_equal(J_ser, J_sep)
+    assert e_J(J_one, orc.tei_gram(c, ps, w.U)) <= TOL_J
+    if algo == "fft":
+        cls = tc.term_classes(pd)
+        say(f"   classes: {cls.tolist()}")
+        assert (cls == -2).any() and (cls != -2).any()
 
 
 def test_tei_gram_ozaki_deterministic(tc, orc):
