@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const double *__restrict
                                                         const double *__restrict__ W,
                                                         const int *__restrict__ EW,
                                                         double *__restrict__ G, int n, int R_f,
-                                                        int ntiles)
+                                                        int ntiles, int mirror)
 {
     __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][BT * ROWB];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BT * ROWB];
@@ -344,7 +344,8 @@ __global__ __launch_bounds__(256) void gram_bf16_kernel(const double *__restrict
                 if (i < R_f && j < R_f && i <= j) {
                     const double v = ldexp(sum[x][y][r], EU[i] + EWk[j]);
                     Gk[(long)i * R_f + j] = v;
-                    Gk[(long)j * R_f + i] = v;
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = v;
                 }
             }
         }
@@ -368,16 +369,17 @@ hipError_t launch_toeplitz_bf16(const double *p, const int *EP, const double *U,
 }
 
 hipError_t launch_gram_bf16(const double *U, const int *EU, const double *W, const int *EW,
-                            double *G, int n, int R_f, int R_N, int pieces, hipStream_t stream)
+                            double *G, int n, int R_f, int R_N, int pieces, bool mirror,
+                            hipStream_t stream)
 {
     const int nt = (R_f + BT - 1) / BT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
     if (pieces == 2)
         hipLaunchKernelGGL(gram_bf16_kernel<2>, grid, dim3(256), 0, stream, U, EU, W, EW, G, n,
-                           R_f, nt);
+                           R_f, nt, (int)mirror);
     else if (pieces == 3)
         hipLaunchKernelGGL(gram_bf16_kernel<3>, grid, dim3(256), 0, stream, U, EU, W, EW, G, n,
-                           R_f, nt);
+                           R_f, nt, (int)mirror);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const double *__restrict_
                                                        const double *__restrict__ W,
                                                        const int *__restrict__ EW,
                                                        double *__restrict__ G, int n, int R_f,
-                                                       int ntiles)
+                                                       int ntiles, int mirror)
 {
     __shared__ float As[2][BT][BK + 1];
     __shared__ float Bs[2][BT][BK + 1];
@@ -270,7 +270,8 @@ __global__ __launch_bounds__(256) void gram_f32_kernel(const double *__restrict_
                 if (i < R_f && j < R_f && i <= j) {
                     const double g = ldexp(sum[x][y][r], EU[i] + EWk[j]);
                     Gk[(long)i * R_f + j] = g;
-                    Gk[(long)j * R_f + i] = g;
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = g;
                 }
             }
         }
@@ -294,11 +295,13 @@ hipError_t launch_toeplitz_f32(const double *p, const int *EP, const double *U, 
 }
 
 hipError_t launch_gram_f32(const double *U, const int *EU, const double *W, const int *EW,
-                           double *G, int n, int R_f, int R_N, hipStream_t stream)
+                           double *G, int n, int R_f, int R_N, bool mirror,
+                           hipStream_t stream)
 {
     const int nt = (R_f + BT - 1) / BT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(gram_f32_kernel, grid, dim3(256), 0, stream, U, EU, W, EW, G, n, R_f, nt);
+    hipLaunchKernelGGL(gram_f32_kernel, grid, dim3(256), 0, stream, U, EU, W, EW, G, n, R_f, nt,
+                       (int)mirror);
     return hipGetLastError();
 }
 

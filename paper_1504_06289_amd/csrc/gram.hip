@@ -25,7 +25,7 @@ constexpr int PAD = 1;
 __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict__ U,
                                                        const double *__restrict__ W,
                                                        double *__restrict__ G, int n, int R_f,
-                                                       int ntiles)
+                                                       int ntiles, int mirror)
 {
     __shared__ double As[2][BT][BK + PAD];
     __shared__ double Bs[2][BT][BK + PAD];
@@ -118,7 +118,8 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
                 const int i = i0 + wi + x * 16 + lk + 4 * r;
                 if (i < R_f && j < R_f && i <= j) {
                     Gk[(long)i * R_f + j] = acc[x][y][r];
-                    Gk[(long)j * R_f + i] = acc[x][y][r];
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = acc[x][y][r];
                 }
             }
         }
@@ -127,11 +128,12 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
 }  // namespace
 
 hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n, int R_f,
-                           int R_N, hipStream_t stream)
+                           int R_N, bool mirror, hipStream_t stream)
 {
     const int nt = (R_f + BT - 1) / BT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(gram_f64_kernel, grid, dim3(256), 0, stream, U, W, G, n, R_f, nt);
+    hipLaunchKernelGGL(gram_f64_kernel, grid, dim3(256), 0, stream, U, W, G, n, R_f, nt,
+                       (int)mirror);
     return hipGetLastError();
 }
 

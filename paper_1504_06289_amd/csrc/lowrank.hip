@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restr
                                                            const double *__restrict__ Y,
                                                            const int *__restrict__ cls,
                                                            double *__restrict__ G, int R_f,
-                                                           int ntiles)
+                                                           int ntiles, int mirror)
 {
     __shared__ double Ys[LT][RQ + 1];
     __shared__ double Xs[LT][RQ + 1];
@@ -444,7 +444,8 @@ __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restr
             const int j = j0 + cb + 16 * b;
             if (i < R_f && j < R_f && i <= j) {
                 Gk[(long)i * R_f + j] = acc[a][b];
-                Gk[(long)j * R_f + i] = acc[a][b];
+                if (mirror)
+                    Gk[(long)j * R_f + i] = acc[a][b];
             }
         }
     }
@@ -515,7 +516,7 @@ hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int 
 }
 
 hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
-                               double *G, int R_f, int R_N, hipStream_t stream)
+                               double *G, int R_f, int R_N, bool mirror, hipStream_t stream)
 {
     hipLaunchKernelGGL(lowrank_y_kernel, dim3((unsigned)(((long)R_f * RQ + 255) / 256), R_N),
                        dim3(256), 0, stream, X, S, cls, R_f, Y);
@@ -524,7 +525,8 @@ hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls,
         return e;
     const int nt = (R_f + LT - 1) / LT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, Y, cls, G, R_f, nt);
+    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, Y, cls, G, R_f, nt,
+                       (int)mirror);
     return hipGetLastError();
 }
 

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
     int R_f_pad, double *__restrict__ G, int R_f, int ntiles, int R_N,
-    const int *__restrict__ cls)
+    const int *__restrict__ cls, int mirror)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[G_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[G_BYTES];
@@ -417,7 +417,8 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
                 if (j < R_f && i <= j) {
                     const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
                     Gk[(long)i * R_f + j] = v;
-                    Gk[(long)j * R_f + i] = v;
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = v;
                 }
             }
         }
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
     int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri,
-    const int *__restrict__ cls)
+    const int *__restrict__ cls, int mirror)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[2][GW_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][GW_BYTES];
@@ -576,7 +577,8 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
                 if (j < R_f && i <= j) {
                     const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
                     Gk[(long)i * R_f + j] = v;
-                    Gk[(long)j * R_f + i] = v;
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = v;
                 }
             }
         }
@@ -625,7 +627,7 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
-                          hipStream_t stream)
+                          bool mirror, hipStream_t stream)
 {
     if (R_f >= 256 && L.R_f_pad % GT2 == 0) {
         const int nt = L.R_f_pad / GT2;
@@ -635,13 +637,13 @@ hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, con
         const int items = cls ? R_N * ntri : 8 * ((R_N + 7) / 8) * ntri;
         hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
                            L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
-                           cls);
+                           cls, (int)mirror);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
     hipLaunchKernelGGL(gram_i8_kernel, grid, dim3(256), 0, stream, US, EU, L.uplane, WS, EW,
-                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt, R_N, cls);
+                       L.wplane, L.n_pad, L.R_f_pad, G, R_f, nt, R_N, cls, (int)mirror);
     return hipGetLastError();
 }
 

@@ -300,7 +300,8 @@ tc_status int8fft_kernel_part(int n, int R_N, const double *p, const ModeScratch
 // (Running the small smooth-term kernels before the convolution instead of
 // after the int8 Gram measured 0.1 ms slower per step with concurrent modes.)
 tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double *U, double *G,
-                         const ModeScratch &s, const ModeScratch &kp, hipStream_t st)
+                         const ModeScratch &s, const ModeScratch &kp, bool mirror,
+                         hipStream_t st)
 {
     const int N = fft_length(n);
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
@@ -311,11 +312,12 @@ tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double 
     TRYK("fft_conv_split", launch_fft_conv(s.Uspec, kp.Cspec, n, N, R_f, R_N, s.twN, nullptr,
                                            s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, U, p,
                                            kp.cls, st));
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, st));
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, mirror, st));
     if (smooth_terms_supported(n)) {
         // smooth terms: G_k = X S_k X^T with X = U Q^T
         TRYK("poly_project", launch_poly_project(U, n, R_f, kp.Q, s.Xp, s.X, st));
-        TRYK("lowrank_gram", launch_lowrank_gram(s.X, kp.S, kp.cls, s.Y, G, R_f, R_N, st));
+        TRYK("lowrank_gram",
+             launch_lowrank_gram(s.X, kp.S, kp.cls, s.Y, G, R_f, R_N, mirror, st));
     }
     return TC_OK;
 }
@@ -323,13 +325,13 @@ tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double 
 // G_k = U^T T_k U for all k of one mode (W is scratch).
 tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N,
                      const double *p, const double *U, double *W, double *G,
-                     const ModeScratch &s, hipStream_t st)
+                     const ModeScratch &s, hipStream_t st, bool mirror = true)
 {
     if (prec == TC_FP64) {
         const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
         if (r != TC_OK)
             return r;
-        TRYK("gram_f64", launch_gram_f64(U, W, G, n, R_f, R_N, st));
+        TRYK("gram_f64", launch_gram_f64(U, W, G, n, R_f, R_N, mirror, st));
         return TC_OK;
     }
     if (row_scaled(prec)) {
@@ -339,24 +341,24 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.EU, st));
         TRYK("row_exponents", launch_row_exponents(W, (long)R_N * R_f, n, s.EW, st));
         if (prec == TC_FP32)
-            TRYK("gram_f32", launch_gram_f32(U, s.EU, W, s.EW, G, n, R_f, R_N, st));
+            TRYK("gram_f32", launch_gram_f32(U, s.EU, W, s.EW, G, n, R_f, R_N, mirror, st));
         else
             TRYK("gram_bf16", launch_gram_bf16(U, s.EU, W, s.EW, G, n, R_f, R_N,
-                                               bf16_pieces(prec), st));
+                                               bf16_pieces(prec), mirror, st));
         return TC_OK;
     }
     if (algo == TC_ALGO_FFT) {
         const tc_status r = int8fft_kernel_part(n, R_N, p, s, st);
         if (r != TC_OK)
             return r;
-        return int8fft_u_part(n, R_f, R_N, p, U, G, s, s, st);
+        return int8fft_u_part(n, R_f, R_N, p, U, G, s, s, mirror, st);
     }
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
     const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
     if (r != TC_OK)
         return r;
     TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, st));
+    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, st));
     return TC_OK;
 }
 
@@ -522,6 +524,9 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
     const InstancePlan P = plan_instance(ws, I, prec, false, split_plan);
     const size_t F2 = (size_t)I.R_f * I.R_f;
     const bool split = split_plan && !profiling();
+    // the Hadamard sum reads only the upper triangles: the lower ones are
+    // written only into a caller's G_saved
+    const bool mirror = I.G_saved != nullptr;
     tc_algorithm algo[3];
     int owner[3];
     for (int l = 0; l < 3; ++l) {
@@ -547,7 +552,7 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
         const bool i8fft = prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT;
         if (!i8fft) {
             status = mode_grams(prec, algo[l], I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l], Gl,
-                                P.ms[l], sl);
+                                P.ms[l], sl, mirror);
             continue;
         }
         const int o = owner[l];
@@ -555,7 +560,7 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
             status = int8fft_kernel_part(I.n[l], I.R_N, I.p[l], P.ms[l], sl);
         if (status == TC_OK)
             status = int8fft_u_part(I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], Gl, P.ms[l], P.ms[o],
-                                    sl);
+                                    mirror, sl);
     }
     if (split) {
         // join every branch, also after a failed launch

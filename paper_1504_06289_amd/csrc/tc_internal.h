@@ -20,10 +20,12 @@ hipError_t launch_toeplitz_f64(const double *p, const double *U, double *W, int 
                                int R_f, int R_N, hipStream_t stream);
 
 // ---- Grams (gram.hip) -----------------------------------------------------
-// G[k][i][j] = sum_a U[i][a] W[k][j][a] for all k < R_N, exactly symmetric
-// (upper-triangle tiles computed, mirrored).
+// G[k][i][j] = sum_a U[i][a] W[k][j][a] for all k < R_N from upper-triangle
+// tiles: every Gram launcher writes the entries i <= j, and with `mirror` also
+// the entries i > j (exactly symmetric); without it those entries are left
+// untouched (the Hadamard sum reads only i <= j).
 hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n,
-                           int R_f, int R_N, hipStream_t stream);
+                           int R_f, int R_N, bool mirror, hipStream_t stream);
 
 // ---- binary32 matrix-core variants (fp32.hip) ------------------------------
 // E[r] = exponent of the largest |X[r][.]| (max < 2^E[r]; 0 for a zero row).
@@ -37,7 +39,7 @@ hipError_t launch_row_exponents(const double *X, long rows, int len, int *E,
 hipError_t launch_toeplitz_f32(const double *p, const int *EP, const double *U, const int *EU,
                                double *W, int n, int R_f, int R_N, hipStream_t stream);
 hipError_t launch_gram_f32(const double *U, const int *EU, const double *W, const int *EW,
-                           double *G, int n, int R_f, int R_N, hipStream_t stream);
+                           double *G, int n, int R_f, int R_N, bool mirror, hipStream_t stream);
 
 // ---- split-bfloat16 matrix-core variants (bf16.hip) ------------------------
 // As the binary32 variants, with each scaled binary64 entry split exactly into
@@ -48,7 +50,8 @@ hipError_t launch_toeplitz_bf16(const double *p, const int *EP, const double *U,
                                 double *W, int n, int R_f, int R_N, int pieces,
                                 hipStream_t stream);
 hipError_t launch_gram_bf16(const double *U, const int *EU, const double *W, const int *EW,
-                            double *G, int n, int R_f, int R_N, int pieces, hipStream_t stream);
+                            double *G, int n, int R_f, int R_N, int pieces, bool mirror,
+                            hipStream_t stream);
 
 // ---- Hadamard product across modes and sum over k (reduce.hip) -----------
 // J[e] = sum_k c[k] G0[k][e] G1[k][e] G2[k][e], e < R_f*R_f.
@@ -98,7 +101,7 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
 // for every k, or (cls != nullptr, device [R_N]) for the k with cls[k] != -2 only
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
-                          hipStream_t stream);
+                          bool mirror, hipStream_t stream);
 
 // ---- FFT route (fft.hip) ---------------------------------------------------
 // N = smallest power of two >= 2n-1; the route needs N/2 <= 4096 (n <= 4096).
@@ -151,6 +154,6 @@ hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int 
 // G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank];
 // Y: scratch [R_N][R_f][kPolyRank])
 hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
-                               double *G, int R_f, int R_N, hipStream_t stream);
+                               double *G, int R_f, int R_N, bool mirror, hipStream_t stream);
 
 }  // namespace tc
