@@ -377,6 +377,7 @@ int max_n(const tc_instance &I)
 // can run concurrently.
 struct InstancePlan {
     double *G, *D;
+    double *part;  // adjoint: partial sums of the split contraction (or null)
     double *W[3];
     ModeScratch ms[3];
     size_t bytes;
@@ -390,6 +391,17 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
     const size_t F2 = (size_t)I.R_f * I.R_f;
     P.G = I.G_saved ? I.G_saved : c.take<double>(3 * (size_t)I.R_N * F2);
     P.D = backward ? c.take<double>((size_t)I.R_N * F2) : nullptr;
+    P.part = nullptr;
+    if (backward) {
+        size_t np = 0;
+        for (int l = 0; l < 3; ++l) {
+            const size_t nl = (size_t)(adjoint_splits(I.n[l], I.R_f, I.R_N) - 1) * I.R_f * I.n[l];
+            if (nl > np)
+                np = nl;
+        }
+        if (np > 0)
+            P.part = c.take<double>(np);
+    }
     if (split) {
         for (int l = 0; l < 3; ++l) {
             P.W[l] = c.take<double>((size_t)I.R_N * I.R_f * I.n[l]);
@@ -600,7 +612,7 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
         if (r != TC_OK)
             return r;
         TRYK("adjoint_gemm_f64",
-             launch_adjoint_gemm_f64(P.D, P.W[l], dU[l], I.n[l], I.R_f, I.R_N, 2.0, st));
+             launch_adjoint_gemm_f64(P.D, P.W[l], dU[l], I.n[l], I.R_f, I.R_N, 2.0, P.part, st));
     }
     return TC_OK;
 }

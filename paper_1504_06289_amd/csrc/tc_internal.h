@@ -64,9 +64,14 @@ hipError_t launch_hadamard_sum(const double *c, const double *G0, const double *
 hipError_t launch_adjoint_d(const double *c, const double *Jbar, const double *Ga,
                             const double *Gb, double *D, int R_f, int R_N,
                             hipStream_t stream);
-// dU[i][a] = scale * sum_k sum_j D[k][j][i] W[k][j][a]
+// dU[i][a] = scale * sum_k sum_j D[k][j][i] W[k][j][a].  The contraction is
+// split into adjoint_splits(n, R_f, R_N) ranges; with more than one, part
+// holds the partial sums of all but the first ([S-1][R_f][n], device).
+constexpr int kAdjointMaxSplit = 8;
+int adjoint_splits(int n, int R_f, int R_N);
 hipError_t launch_adjoint_gemm_f64(const double *D, const double *W, double *dU, int n,
-                                   int R_f, int R_N, double scale, hipStream_t stream);
+                                   int R_f, int R_N, double scale, double *part,
+                                   hipStream_t stream);
 
 
 // ---- int8 error-free splitting path (ozaki.hip) ---------------------------

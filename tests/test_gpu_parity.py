@@ -206,7 +206,9 @@ def test_tei_gram_batched_matches_single(tc, orc):
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("n,R_f,R_N", [((24, 19, 28), 6, 6), ((100, 100, 100), 40, 5),
-                                       ((70, 130, 300), 67, 4)])
+                                       ((70, 130, 300), 67, 4),
+                                       # the adjoint contraction split into 3 K ranges
+                                       ((200, 150, 96), 130, 12)])
 def test_backward_parity(tc, orc, n, R_f, R_N, algo):
     say(f"backward n={n} R_f={R_f} R_N={R_N} {algo}")
     w = wl.small_products(n, R_f, R_N=R_N, b=6.0, seed=R_f)
