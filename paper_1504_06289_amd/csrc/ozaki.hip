@@ -462,10 +462,22 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int w = blockIdx.x;
     int k, t;
     if (cls) {
-        // the terms of class other than -2: items in term order (balanced
-        // over the XCDs by the dispatcher's round robin)
-        t = w % ntri;
-        k = nth_listed_term(cls, R_N, w / ntri);
+        // the nk terms of class other than -2: the nk * ntri items in term
+        // order, cut into eight contiguous chunks, chunk x on XCD x (work
+        // item w runs on XCD w mod 8), so the workgroups on one XCD share
+        // one term's U and W blocks in its L2
+        int nk = 0;
+        for (int kk = 0; kk < R_N; ++kk)
+            nk += cls[kk] != -2;
+        const int per = (nk * ntri + 7) / 8;
+        const int local = w >> 3;
+        if (local >= per)
+            return;
+        const int gi = (w & 7) * per + local;
+        if (gi >= nk * ntri)
+            return;
+        t = gi % ntri;
+        k = nth_listed_term(cls, R_N, gi / ntri);
         if (k < 0)
             return;
     } else {
@@ -633,8 +645,9 @@ hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, con
         const int nt = L.R_f_pad / GT2;
         const int ntri = nt * (nt + 1) / 2;
         // all terms: for every XCD x, the terms k = x, x + 8, ... each with ntri
-        // tiles; classes given: R_N * ntri items in term order (the excess exits)
-        const int items = cls ? R_N * ntri : 8 * ((R_N + 7) / 8) * ntri;
+        // tiles; classes given: the items of the listed terms in eight
+        // contiguous chunks, one per XCD (a multiple of 8 items, the excess exits)
+        const int items = cls ? 8 * ((R_N * ntri + 7) / 8) : 8 * ((R_N + 7) / 8) * ntri;
         hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
                            L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
                            cls, (int)mirror);
