@@ -249,7 +249,9 @@ def main():
 
     def step(prec):
         t, c, p = tc.newton_kernel(w.n[0], w.h[0], w.R_N, w.u0, w.hu, device=dev)
-        cd = torch.from_numpy(c).to(dev)
+        # the weights through pinned memory: an asynchronous copy, so the host
+        # does not wait for the previous step before enqueueing this one
+        cd = torch.from_numpy(c).pin_memory().to(dev, non_blocking=True)
         return tc.tei_gram(cd, [p, p, p], U, prec=prec)
 
     def with_algo(prec, algo, fn):

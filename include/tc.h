@@ -184,9 +184,10 @@ tc_status tc_term_classes(int n, int R_N, const double *p_dev, int *cls_dev, voi
  * the first call and kept for the life of the process) that fork from and
  * join back into `stream` through events, so the call still completes in
  * stream order and can be captured as one graph with parallel branches.
- * With count == 1 the Grams of the three modes run concurrently, each in its
- * own workspace region, and the Hadamard sum follows on `stream`; with
- * count > 1 the instances run concurrently and the modes of each in turn.
+ * With count == 1 the Grams of the three modes run concurrently (the first
+ * on `stream`, the other two on internal streams), each in its own workspace
+ * region, and the Hadamard sum follows on `stream`; with count > 1 the
+ * instances run concurrently and the modes of each in turn.
  * Calls from several host threads are serialised while they enqueue.
  */
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec,

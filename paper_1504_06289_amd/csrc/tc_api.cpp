@@ -519,9 +519,9 @@ bool profiling()
 
 // One instance: the Grams of the three modes, then the Hadamard sum.  With
 // `split` the workspace plan has one region per mode and the modes run
-// concurrently on three pool branches (forked from and joined back into st;
-// the caller holds g_pool_mu and the pool is initialised), except while
-// kernel timing is on, when they run in turn on st.
+// concurrently: the first on st, the other two on pool branches forked from
+// and joined back into st (the caller holds g_pool_mu and the pool is
+// initialised), except while kernel timing is on, when they run in turn on st.
 //
 // On the int8 FFT route, when the modes run in turn, a mode whose kernel
 // vectors and n equal those of an earlier mode (the same pointer: the common
@@ -555,8 +555,10 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
         return TC_ERR_HIP;
     tc_status status = TC_OK;
     for (int l = 0; l < 3 && status == TC_OK; ++l) {
-        hipStream_t sl = split ? g_pool.st[l] : st;
-        if (split && hipStreamWaitEvent(sl, g_pool.fork, 0) != hipSuccess) {
+        // the first mode stays on the caller's stream (no cross-queue wait
+        // before it starts); the other two fork onto branches
+        hipStream_t sl = (split && l > 0) ? g_pool.st[l] : st;
+        if (split && l > 0 && hipStreamWaitEvent(sl, g_pool.fork, 0) != hipSuccess) {
             status = TC_ERR_HIP;
             break;
         }
@@ -575,8 +577,8 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
                                     mirror, sl);
     }
     if (split) {
-        // join every branch, also after a failed launch
-        for (int l = 0; l < 3; ++l)
+        // join both branches, also after a failed launch
+        for (int l = 1; l < 3; ++l)
             if (hipEventRecord(g_pool.join[l], g_pool.st[l]) != hipSuccess ||
                 hipStreamWaitEvent(st, g_pool.join[l], 0) != hipSuccess)
                 status = TC_ERR_HIP;
