@@ -63,6 +63,8 @@ def lib():
                                               ctypes.c_int, pi, pd, ctypes.c_int]
         L.oracle_tei_gram_backward.argtypes = [pi, ctypes.c_int, ctypes.c_int, pd, ppd, ppd,
                                                pd, ppd]
+        L.oracle_coulomb.argtypes = [pi, ctypes.c_int, ctypes.c_int, ctypes.c_int, pd, ppd,
+                                     ppd, ppd, pd, pd, ctypes.c_int]
         L.oracle_bruteforce_J.argtypes = [ctypes.c_int, d, ctypes.c_int, ctypes.c_int, pd, pd,
                                           ppd, pd]
         L.oracle_gauss_legendre.argtypes = [ctypes.c_int, pd, pd]
@@ -151,6 +153,24 @@ def tei_gram_columns(c, p3, U3, cols, compensated: bool = True) -> np.ndarray:
                                   cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                   _p(out), int(compensated))
     return out
+
+
+def coulomb(c, p3, U3, V3, d, compensated: bool = True) -> np.ndarray:
+    """Jd[i] = sum_q c_q sum_m d_m prod_l <U^l[i], (T^l_q V^l)[m]>: the Coulomb
+    entries of the product functions (rows of U^l) against the density
+    sum_m d_m v^1_m x v^2_m x v^3_m (rows of V^l), Section 3.1."""
+    c, d = _f64(c), _f64(d)
+    p3 = [_f64(x) for x in p3]
+    U3 = [_f64(x) for x in U3]
+    V3 = [_f64(x) for x in V3]
+    R_f, R_rho, R_N = U3[0].shape[0], V3[0].shape[0], c.shape[0]
+    for l in range(3):
+        assert U3[l].shape[1] == V3[l].shape[1] and V3[l].shape[0] == R_rho
+    n = (ctypes.c_int * 3)(*[u.shape[1] for u in U3])
+    Jd = np.empty(R_f)
+    lib().oracle_coulomb(n, R_f, R_rho, R_N, _p(c), _pp(p3), _pp(U3), _pp(V3), _p(d),
+                         _p(Jd), int(compensated))
+    return Jd
 
 
 def tei_gram_backward(c, p3, U3, Jbar):

@@ -267,6 +267,45 @@ void oracle_tei_gram(const int *n, int R_f, int R_N, const double *c,
             free(G[l]);
 }
 
+void oracle_coulomb(const int *n, int R_f, int R_rho, int R_N, const double *c,
+                    const double *const *p, const double *const *U,
+                    const double *const *V, const double *d, double *Jd, int compensated)
+{
+    /* H[l][q][i][m] = <U^l[i], (T^l_q V^l)[m]> */
+    double *H[3];
+    for (int l = 0; l < 3; ++l) {
+        const int nl = n[l];
+        double *W = (double *)malloc(sizeof(double) * (size_t)R_N * R_rho * nl);
+        oracle_convolve(nl, R_rho, R_N, p[l], V[l], W, compensated);
+        H[l] = (double *)malloc(sizeof(double) * (size_t)R_N * R_f * R_rho);
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+        for (int q = 0; q < R_N; ++q)
+            for (int i = 0; i < R_f; ++i) {
+                const double *ui = U[l] + (long)i * nl;
+                for (int m = 0; m < R_rho; ++m) {
+                    const double *w = W + ((long)q * R_rho + m) * nl;
+                    acc2 A = {0.0, 0.0};
+                    for (long a = 0; a < nl; ++a)
+                        acc_dot(&A, ui[a], w[a], compensated);
+                    H[l][((long)q * R_f + i) * R_rho + m] = acc_val(&A);
+                }
+            }
+        free(W);
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < R_f; ++i) {
+        acc2 A = {0.0, 0.0};
+        for (int q = 0; q < R_N; ++q)
+            for (int m = 0; m < R_rho; ++m) {
+                const long e = ((long)q * R_f + i) * R_rho + m;
+                acc_add(&A, c[q] * d[m] * H[0][e] * H[1][e] * H[2][e], compensated);
+            }
+        Jd[i] = acc_val(&A);
+    }
+    for (int l = 0; l < 3; ++l)
+        free(H[l]);
+}
+
 void oracle_tei_gram_columns(const int *n, int R_f, int R_N, const double *c,
                              const double *const *p, const double *const *U,
                              int ncols, const int *cols, double *Jcols,

@@ -91,6 +91,21 @@ void oracle_tei_gram_columns(const int *n, int R_f, int R_N, const double *c,
                              int ncols, const int *cols, double *Jcols,
                              int compensated);
 
+/* Coulomb entries of the product functions against a density given in
+ * canonical format (Section 3.1: the Hartree potential of the density
+ * Theta' = sum_m d_m v^1_m x v^2_m x v^3_m is the sum of tensor products of
+ * the 1D convolutions v^l_m * p^l_q, and the Coulomb entries are its scalar
+ * products with the rank-1 products of basis functions):
+ *   Jd[i] = sum_q c_q sum_m d_m prod_l <U^l[i], (T^l_q V^l)[m]>,
+ * with T^l_q V^l the aperiodic convolution of oracle_convolve and <.,.> the
+ * plain sum over the cells (the cell volume is in c_q, as for J).
+ * U[l] [R_f][n_l], V[l] [R_rho][n_l], d [R_rho], Jd [R_f].
+ * Pins: with V = U the result is J d for the J of oracle_tei_gram; the Boys
+ * closed form for an s-Gaussian density against s-Gaussian functions. */
+void oracle_coulomb(const int *n, int R_f, int R_rho, int R_N, const double *c,
+                    const double *const *p, const double *const *U,
+                    const double *const *V, const double *d, double *Jd, int compensated);
+
 /* Adjoint of f = <Jbar, J> with respect to the side matrices:
  * dU^l = 2 sum_k W^l_k D^l_k with D^l_k = c_k S o G^{l+1}_k o G^{l+2}_k and
  * S = (Jbar + Jbar^T)/2 (T_k and G symmetric).  dU[l]: [R_f][n_l].

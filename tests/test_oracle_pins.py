@@ -275,6 +275,57 @@ def test_tei_gram_boys_closed_form_h2(orc):
     assert np.max(np.abs(rich - ref) / np.abs(ref)) < 2e-6, errs
 
 
+def test_coulomb_of_product_density_is_J_times_d(orc):
+    """A density expanded in the product functions themselves (V = U, weights
+    d) gives Jd = J d with the J of the TEI assembly: the Hartree-potential
+    route and the factorised TEI matrix compute the same integrals."""
+    w = wl.small_products((40, 33, 47), 21, R_N=9, b=7.0, seed=6)
+    ps, c = [], None
+    for l in range(3):
+        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
+        ps.append(p)
+    c = a * w.h[0] * w.h[1] * w.h[2]
+    d = np.random.default_rng(3).standard_normal(w.R_f)
+    Jd = orc.coulomb(c, ps, w.U, w.U, d)
+    J = orc.tei_gram(c, ps, w.U)
+    bound = 1e-13 * (np.abs(J) @ np.abs(d))
+    assert np.all(np.abs(Jd - J @ d) <= bound)
+    # a density of a subset of the products: the matching columns of J
+    sel = [2, 5, 11]
+    Jd2 = orc.coulomb(c, ps, w.U, [u[sel] for u in w.U], d[sel])
+    assert np.all(np.abs(Jd2 - J[:, sel] @ d[sel]) <= 1e-13 * (np.abs(J[:, sel]) @ np.abs(d[sel])))
+
+
+@pytest.mark.slow
+def test_coulomb_boys_closed_form_h2(orc):
+    """An s-Gaussian density against s-Gaussian functions: the Coulomb
+    entries converge to the Boys closed form at O(h^2)."""
+    b = 10.0
+    alphas = np.array([0.6, 1.3, 0.8])
+    centres = np.array([[0.3, -0.4, 0.1], [-1.1, 0.7, 0.5], [1.4, 1.0, -0.8]])
+    dal = np.array([0.9, 1.7])
+    dcen = np.array([[0.2, 0.1, -0.3], [-0.5, 0.8, 0.4]])
+    d = np.array([1.5, -0.7])
+    ref = np.array([sum(d[m] * float(_boys_ssss(alphas[i], centres[i], dal[m], dcen[m]))
+                        for m in range(2)) for i in range(3)])
+    errs, Js = [], {}
+    for n in (64, 128, 256, 512):
+        h = 2 * b / n
+        R_N, lo, hu = accurate_rule(h)
+        t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+        U, _ = wl.s_gaussians(n, b, 3, alphas=alphas, centres=centres)
+        V, _ = wl.s_gaussians(n, b, 2, alphas=dal, centres=dcen)
+        Jd = orc.coulomb(c, [p, p, p], U, V, d)
+        Js[n] = Jd
+        errs.append(np.max(np.abs(Jd - ref) / np.abs(ref)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert errs[-1] < 2e-4
+    for r in ratios[1:]:
+        assert 3.5 < r < 4.6, (errs, ratios)
+    rich = (4 * Js[512] - Js[256]) / 3
+    assert np.max(np.abs(rich - ref) / np.abs(ref)) < 2e-6, errs
+
+
 def test_J_symmetric_psd_products(orc):
     """J = J^T, J_ii > 0 and J is positive semi-definite up to rounding (each
     T_k is positive definite, Schur products of PSD matrices are PSD and
