@@ -118,6 +118,21 @@ typedef struct {
     double *G_saved;     /* [3][R_N][R_f][R_f] device output, or NULL        */
 } tc_instance;
 
+/* A density in canonical format against a set of product functions, for
+ * tc_coulomb (Section 3.1, the Hartree potential and the Coulomb matrix). */
+typedef struct {
+    int n[3];            /* cells per mode, 1 <= n_l <= TC_MAX_N             */
+    int R_f;             /* number of product functions (rows of U)          */
+    int R_rho;           /* number of density terms (rows of V), >= 1        */
+    int R_N;             /* number of kernel terms                           */
+    const double *c;     /* [R_N] device: weights c_k = a_k h_1 h_2 h_3 > 0  */
+    const double *p[3];  /* [R_N][2 n_l - 1] device; may alias across modes  */
+    const double *U[3];  /* [R_f][n_l] device: the product functions         */
+    const double *V[3];  /* [R_rho][n_l] device: the density factors         */
+    const double *d;     /* [R_rho] device: the density weights              */
+    double *Jd;          /* [R_f] device, output                             */
+} tc_density;
+
 /* Operation codes for tc_workspace_bytes. */
 #define TC_OP_CONVOLVE 0
 #define TC_OP_TEI_GRAM 1
@@ -255,6 +270,28 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
  */
 tc_status tc_profile_enable(int on);
 int tc_profile_read(int max_kernels, char (*names)[64], double *total_ms, long *calls);
+
+/*
+ * tc_coulomb -- Coulomb entries of the product functions against a density
+ * given in canonical format (Section 3.1: the Hartree potential of the
+ * density Theta' = sum_m d_m v^1_m x v^2_m x v^3_m is the sum over m and the
+ * kernel terms q of tensor products of the 1D convolutions v^l_m * p^l_q, and
+ * the Coulomb entries are its scalar products with the rank-1 products of
+ * basis functions):
+ *   Jd[i] = sum_q c_q sum_m d_m prod_l <U^l[i], (T^l_q V^l)[m]>,
+ * the plain sum over the cells in <.,.> (the cell volume is in c_q).  With
+ * V = U this is J d for the J of tc_tei_gram.
+ *   prob  host descriptor, pointers inside are device.
+ *   prec  TC_FP64 only (otherwise TC_ERR_UNSUPPORTED): the convolutions by
+ *         the direct or FFT route (tuning table of (n_l, R_rho, R_N)), the
+ *         cross Grams U (T_q V)^T on binary64 matrix cores, the sum over q and
+ *         m in a fixed order (bitwise reproducible).
+ *   ws    tc_coulomb_workspace_bytes(prob, prec) bytes of device memory.
+ * Runs on `stream`; the modes in turn.
+ */
+size_t tc_coulomb_workspace_bytes(const tc_density *prob, tc_precision prec);
+tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t ws_bytes,
+                     void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *tc_status_string(tc_status s);

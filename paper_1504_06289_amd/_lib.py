@@ -33,7 +33,7 @@ TC_OP_TEI_GRAM_BACKWARD = 2
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
            "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
-           "tc_term_classes")
+           "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -51,6 +51,21 @@ class TcInstance(ctypes.Structure):
         ("U", ctypes.c_void_p * 3),
         ("J", ctypes.c_void_p),
         ("G_saved", ctypes.c_void_p),
+    ]
+
+
+class TcDensity(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3),
+        ("R_f", ctypes.c_int),
+        ("R_rho", ctypes.c_int),
+        ("R_N", ctypes.c_int),
+        ("c", ctypes.c_void_p),
+        ("p", ctypes.c_void_p * 3),
+        ("U", ctypes.c_void_p * 3),
+        ("V", ctypes.c_void_p * 3),
+        ("d", ctypes.c_void_p),
+        ("Jd", ctypes.c_void_p),
     ]
 
 
@@ -107,6 +122,11 @@ def lib() -> ctypes.CDLL:
         L.tc_profile_read.restype = ctypes.c_int
         L.tc_term_classes.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.tc_term_classes.restype = ctypes.c_int
+        L.tc_coulomb_workspace_bytes.argtypes = [ctypes.POINTER(TcDensity), ctypes.c_int]
+        L.tc_coulomb_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_coulomb.argtypes = [ctypes.POINTER(TcDensity), ctypes.c_int, vp, ctypes.c_size_t,
+                                 vp]
+        L.tc_coulomb.restype = ctypes.c_int
         _lib = L
     return _lib
 

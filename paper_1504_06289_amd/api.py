@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ALGORITHMS, PRECISIONS, TcInstance, check
+from ._lib import ALGORITHMS, PRECISIONS, TcDensity, TcInstance, check
 
 
 def _stream(device: torch.device) -> ctypes.c_void_p:
@@ -81,6 +81,36 @@ def convolve(p: torch.Tensor, U: torch.Tensor, prec="fp64",
     check(_lib.lib().tc_convolve(n, R_f, R_N, _ptr(p), _ptr(U), _ptr(W), _prec(prec), _ptr(ws),
                                  ws_bytes, _stream(U.device)), "tc_convolve")
     return W
+
+
+def coulomb(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],
+            V3: Sequence[torch.Tensor], d: torch.Tensor, prec="fp64",
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """tc_coulomb: Jd[i] = sum_q c_q sum_m d_m prod_l <U^l[i], (T^l_q V^l)[m]>, the
+    Coulomb entries of the product functions (rows of U^l) against the density
+    sum_m d_m v^1_m x v^2_m x v^3_m (rows of V^l)."""
+    _dev_f64(c, "c")
+    _dev_f64(d, "d")
+    R_f, R_rho, R_N = U3[0].shape[0], V3[0].shape[0], c.shape[0]
+    dev = c.device
+    Jd = out if out is not None else torch.empty(R_f, dtype=torch.float64, device=dev)
+    _dev_f64(Jd, "out")
+    D = TcDensity()
+    D.R_f, D.R_rho, D.R_N = R_f, R_rho, R_N
+    D.c, D.d, D.Jd = c.data_ptr(), d.data_ptr(), Jd.data_ptr()
+    for l in range(3):
+        for x, name in ((p3[l], "p"), (U3[l], "U"), (V3[l], "V")):
+            _dev_f64(x, f"{name}[{l}]")
+        D.n[l] = U3[l].shape[1]
+        D.p[l], D.U[l], D.V[l] = p3[l].data_ptr(), U3[l].data_ptr(), V3[l].data_ptr()
+    L = _lib.lib()
+    ws_bytes = L.tc_coulomb_workspace_bytes(ctypes.byref(D), _prec(prec))
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("tc_coulomb: sizes out of range")
+    ws = _workspace(ws_bytes, dev)
+    check(L.tc_coulomb(ctypes.byref(D), _prec(prec), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_coulomb")
+    return Jd
 
 
 def term_classes(p: torch.Tensor) -> np.ndarray:

@@ -430,6 +430,47 @@ size_t convolve_ws(int n, int R_f, int R_N, tc_precision prec)
     return c.used;
 }
 
+// Coulomb entries against a density: every size and pointer present
+bool density_ok(const tc_density &D)
+{
+    if (!D.c || !D.d || !D.Jd)
+        return false;
+    for (int l = 0; l < 3; ++l)
+        if (!size_ok(D.n[l], D.R_f, D.R_N) || !size_ok(D.n[l], D.R_rho, D.R_N) || !D.p[l] ||
+            !D.U[l] || !D.V[l])
+            return false;
+    return true;
+}
+
+// Workspace: [H: 3 x R_N x R_f x R_rho][W: R_N x R_rho x max n][one mode's
+// convolution scratch, sized for the largest mode and reused]
+struct DensityPlan {
+    double *H, *W;
+    ModeScratch ms[3];
+    size_t bytes;
+};
+
+DensityPlan plan_density(void *ws, const tc_density &D)
+{
+    DensityPlan P{};
+    Carver c(ws);
+    P.H = c.take<double>(3 * (size_t)D.R_N * D.R_f * D.R_rho);
+    int nmax = D.n[0];
+    for (int l = 1; l < 3; ++l)
+        nmax = D.n[l] > nmax ? D.n[l] : nmax;
+    P.W = c.take<double>((size_t)D.R_N * D.R_rho * nmax);
+    const size_t scratch0 = c.used;
+    size_t scratch_max = 0;
+    for (int l = 0; l < 3; ++l) {
+        c.used = scratch0;
+        P.ms[l] = carve_mode(c, TC_FP64, D.n[l], D.R_rho, D.R_N, false);
+        if (c.used - scratch0 > scratch_max)
+            scratch_max = c.used - scratch0;
+    }
+    P.bytes = scratch0 + scratch_max;
+    return P;
+}
+
 // ---------------------------------------------------------------------------
 // batches: independent instances run on a fixed pool of internal streams
 // (created once, default priority), forked from and joined back into the
@@ -743,6 +784,45 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double
     const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false);
     return mode_W(prec, resolve(n, R_f, R_N, prec), n, R_f, R_N, p_dev, U_dev, W_dev, s,
                   (hipStream_t)stream);
+}
+
+size_t tc_coulomb_workspace_bytes(const tc_density *prob, tc_precision prec)
+{
+    if (!prob || !prec_known(prec))
+        return (size_t)-1;
+    for (int l = 0; l < 3; ++l)
+        if (!size_ok(prob->n[l], prob->R_f, prob->R_N) ||
+            !size_ok(prob->n[l], prob->R_rho, prob->R_N))
+            return (size_t)-1;
+    return plan_density(nullptr, *prob).bytes;
+}
+
+tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    if (!prob || !prec_known(prec) || !density_ok(*prob))
+        return TC_ERR_INVALID_ARG;
+    if (prec != TC_FP64)
+        return TC_ERR_UNSUPPORTED;
+    const tc_density &D = *prob;
+    const DensityPlan P = plan_density(ws, D);
+    if (!ws || ws_bytes < P.bytes)
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t plane = (size_t)D.R_N * D.R_f * D.R_rho;
+    for (int l = 0; l < 3; ++l) {
+        // the factors T_q V of the Hartree potential, then their scalar
+        // products with the product functions
+        const tc_status r = mode_W(TC_FP64, resolve(D.n[l], D.R_rho, D.R_N, TC_FP64), D.n[l],
+                                   D.R_rho, D.R_N, D.p[l], D.V[l], P.W, P.ms[l], st);
+        if (r != TC_OK)
+            return r;
+        TRYK("cross_gram_f64", launch_cross_gram_f64(D.U[l], P.W, P.H + l * plane, D.n[l],
+                                                     D.R_f, D.R_rho, D.R_N, st));
+    }
+    TRYK("coulomb_reduce",
+         launch_coulomb_reduce(D.c, D.d, P.H, D.R_f, D.R_rho, D.R_N, D.Jd, st));
+    return TC_OK;
 }
 
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec, void *ws,

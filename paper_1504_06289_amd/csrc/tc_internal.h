@@ -130,6 +130,14 @@ hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, in
                            int R_f_pad, int n_pad, long wplane, const double *U,
                            const double *p, const int *band, hipStream_t stream);
 
+// ---- Coulomb entries against a density (coulomb.hip) -----------------------
+// H[q][i][m] = sum_a U[i][a] W[q][m][a] for i < R_f, m < R_rho, q < R_N
+hipError_t launch_cross_gram_f64(const double *U, const double *W, double *H, int n, int R_f,
+                                 int R_rho, int R_N, hipStream_t stream);
+// Jd[i] = sum_q c_q sum_m d_m H0 H1 H2 at [q][i][m], H = [3][R_N][R_f][R_rho]
+hipError_t launch_coulomb_reduce(const double *c, const double *d, const double *H, int R_f,
+                                 int R_rho, int R_N, double *Jd, hipStream_t stream);
+
 // ---- term classes and smooth terms (lowrank.hip) ---------------------------
 constexpr int kBandMax = 16;   // widest band of a narrow term
 constexpr int kPolyRank = 32;  // polynomial degree < kPolyRank for a smooth term

@@ -178,3 +178,14 @@ def small_products(n: int, R_f: int, R_N: int = 12, b: float = 8.0, seed: int = 
     u0, hu = sinc_params(R_N, n if np.isscalar(n) else n[0], b)
     ns = (n, n, n) if np.isscalar(n) else tuple(n)
     return Workload(f"small_{ns}_{R_f}_{R_N}", ns, b, R_N, R_f, u0, hu, U, seed, meta)
+
+
+def density(n, b: float, R_rho: int, seed: int = 0):
+    """A density in canonical format for the Coulomb entries: R_rho terms
+    d_m v^1_m x v^2_m x v^3_m whose factors are Gaussian products from the
+    same generator as the functions (a rank-reduced density is again a short
+    sum of separable terms), with weights d_m uniform in [0.1, 1].  Returns
+    (V: three arrays [R_rho][n_l], d [R_rho])."""
+    V, _ = gaussian_products(n, b, R_rho, seed=seed + 424242)
+    d = np.random.default_rng(seed + 99991).uniform(0.1, 1.0, size=R_rho)
+    return V, d

@@ -213,3 +213,33 @@ def test_term_classes_rejects_bad_arguments(L):
     assert L.tc_term_classes(64, 4, None, v, None) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_term_classes(64, 4, v, None, None) == _lib.TC_ERR_INVALID_ARG
 
+
+def test_coulomb_workspace_and_rejects(L):
+    D = _lib.TcDensity()
+    D.R_f, D.R_rho, D.R_N = 10, 3, 4
+    for l in range(3):
+        D.n[l] = 100
+    up = lambda x: (x + 255) // 256 * 256
+    # H [3][R_N][R_f][R_rho], W [R_N][R_rho][n], FFT scratch of one mode
+    # (twiddles [N], spectra of V [R_rho][N/2+1] and of the kernel [R_N][N/2+1])
+    fft = up(16 * 256) + up(16 * 3 * 129) + up(16 * 4 * 129)
+    assert L.tc_coulomb_workspace_bytes(ctypes.byref(D), _lib.TC_FP64) == \
+        up(8 * 3 * 4 * 10 * 3) + up(8 * 4 * 3 * 100) + fft
+    assert L.tc_coulomb_workspace_bytes(None, _lib.TC_FP64) == ctypes.c_size_t(-1).value
+    bad = _lib.TcDensity()
+    bad.R_f, bad.R_rho, bad.R_N = 10, 0, 4
+    for l in range(3):
+        bad.n[l] = 100
+    assert L.tc_coulomb_workspace_bytes(ctypes.byref(bad), _lib.TC_FP64) == \
+        ctypes.c_size_t(-1).value
+    # null pointers, then a precision the route does not implement
+    assert L.tc_coulomb(ctypes.byref(D), _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    v = 0x1000
+    D.c, D.d, D.Jd = v, v, v
+    for l in range(3):
+        D.p[l], D.U[l], D.V[l] = v, v, v
+    assert L.tc_coulomb(ctypes.byref(D), _lib.TC_OZAKI_I8, None, 0, None) == \
+        _lib.TC_ERR_UNSUPPORTED
+    assert L.tc_coulomb(ctypes.byref(D), _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_coulomb(ctypes.byref(D), 42, None, 0, None) == _lib.TC_ERR_INVALID_ARG
+
