@@ -19,8 +19,9 @@ Prints ONE JSON line.
               the peak of its arithmetic or of HBM.  While timing kernels the
               library runs the three modes in turn (each kernel alone on the
               device); the headline region runs them concurrently.
-  rows        the adjoint (2048 cells, R_f=512, forward + backward of w^T J w)
-              and the 64-instance batched workload, per-step times.
+  rows        the adjoint (2048 cells, R_f=512, forward + backward of w^T J w),
+              the 64-instance batched workload, and the Coulomb entries of the
+              4096-cell functions against a 64-term density, per-step times.
   cpu_baseline  the FP64 oracle on a bounded sample (columns of J).
 """
 from __future__ import annotations
@@ -391,6 +392,33 @@ def extra_rows(tc, wl, torch, dev, args):
         rows[f"batched_c4_{prec}_ms"] = round(msb, 3)
         rows[f"batched_c4_{prec}_GFLOPs"] = round(Fb / (msb * 1e-3) / 1e9, 1)
     rows["batched_c4_flops"] = Fb
+    # Coulomb entries of the 4096-cell functions against a 64-term density
+    w3 = wl.config("c3")
+    R_rho = 64
+    V, d = wl.density(w3.n, w3.b, R_rho, seed=1)
+    t, c, p = tc.newton_kernel(w3.n[0], w3.h[0], w3.R_N, w3.u0, w3.hu, device=dev)
+    cd = torch.from_numpy(c).to(dev)
+    U3 = [torch.from_numpy(u).to(dev) for u in w3.U]
+    V3 = [torch.from_numpy(v).to(dev) for v in V]
+    dd = torch.from_numpy(d).to(dev)
+    msc = timed(lambda: tc.coulomb(cd, [p, p, p], U3, V3, dd), 5, 1, torch)
+    n3 = w3.n[0]
+    Fc = 3.0 * w3.R_N * (2.0 * n3 * n3 * R_rho + 2.0 * n3 * w3.R_f * R_rho)
+    tc.profile_enable(True)
+    tc.profile_read()
+    tc.coulomb(cd, [p, p, p], U3, V3, dd)
+    prof = tc.profile_read()
+    tc.profile_enable(False)
+    cg = prof.get("cross_gram_f64")
+    rows["coulomb_c3_rho64_fp64_ms"] = round(msc, 4)
+    rows["coulomb_c3_rho64_fp64_GFLOPs"] = round(Fc / (msc * 1e-3) / 1e9, 1)
+    if cg:
+        ms_cg = cg[0] / cg[1]
+        fl = 2.0 * n3 * w3.R_f * R_rho * w3.R_N
+        rows["coulomb_cross_gram_f64"] = {"kernel_ms": round(ms_cg, 4),
+                                          "TFLOP/s": round(fl / (ms_cg * 1e-3) / 1e12, 2),
+                                          "frac": round(fl / (ms_cg * 1e-3) / 1e12 / PEAK["fp64"], 4)}
+    rows["coulomb_kernels"] = {k: round(v[0], 4) for k, v in prof.items()}
     return rows
 
 
