@@ -200,3 +200,72 @@ def gauss_legendre(npts: int):
     x, w = np.empty(npts), np.empty(npts)
     lib().oracle_gauss_legendre(npts, _p(x), _p(w))
     return x, w
+
+
+# --------------------------------------------------------------------------
+# 1D density fitting and the factorised TEI matrix (Section 3.2): plain NumPy
+# on explicit matrices, for small sizes.
+# --------------------------------------------------------------------------
+def pivoted_cholesky(A: np.ndarray, tol: float, R_max: int):
+    """Pivoted (diagonally pivoted, rank-revealing) Cholesky of a symmetric
+    positive semi-definite A: at each step the pivot is the largest residual
+    diagonal entry; the step is taken while the residual trace exceeds tol
+    (and fewer than R_max columns exist).  Returns (L [N][R], pivots [R],
+    residual diagonal [N]) with A ~ L L^T, the residual diagonal of A - L L^T
+    and L[pivots[r], s] = 0 for s > r."""
+    A = np.asarray(A, dtype=np.float64)
+    N = A.shape[0]
+    d = np.diag(A).copy()
+    L = np.zeros((N, 0))
+    piv = []
+    while len(piv) < R_max and d.sum() > tol:
+        p = int(np.argmax(d))
+        if d[p] <= 0.0:
+            break
+        col = A[:, p] - L @ L[p, :]
+        l = col / np.sqrt(d[p])
+        l[piv] = 0.0   # the residual vanishes on the earlier pivots
+        L = np.column_stack([L, l])
+        d = d - l * l
+        d[p] = 0.0
+        piv.append(p)
+    return L, np.array(piv, dtype=np.int64), d
+
+
+def density_fit(F: np.ndarray, tol: float, R_max: int):
+    """1D density fitting of one mode's side matrix F [N_pair][n] (rows: pair
+    products on the grid): pivoted Cholesky of A = F^T F over the grid points
+    (truncated when the residual trace is at most tol^2 trace(A)), then
+    F ~ V U with V = F[:, P] (the products at the R pivot points) and
+    U = A[P, P]^-1 A[P, :] (R x n), i.e. U = L[P, :]^-T L^T.
+    Returns (U [R][n], V [N_pair][R], pivots [R], residual trace)."""
+    F = np.asarray(F, dtype=np.float64)
+    A = F.T @ F
+    L, piv, d = pivoted_cholesky(A, tol * tol * np.trace(A), R_max)
+    R = len(piv)
+    if R == 0:
+        return np.zeros((0, F.shape[1])), np.zeros((F.shape[0], 0)), piv, float(d.sum())
+    LP = L[piv, :]                                   # lower triangular in pivot order
+    U = np.linalg.solve(LP.T, L.T)                   # L[P,:]^-T L^T
+    V = F[:, piv]
+    return U, V, piv, float(d.sum())
+
+
+def tei_matrix_factored(c, V3, M3) -> np.ndarray:
+    """B = sum_k c_k  o_l  V^l M^l_k V^l^T  (Section 3.2, the factorised TEI
+    matrix over the pair products; V^l [N_pair][R_l], M^l [R_N][R_l][R_l])."""
+    c = np.asarray(c, dtype=np.float64)
+    B = 0.0
+    for k in range(c.shape[0]):
+        term = c[k]
+        for l in range(3):
+            term = term * (V3[l] @ M3[l][k] @ V3[l].T)
+        B = B + term
+    return B
+
+
+def tei_cholesky(c, V3, M3, tol: float, R_max: int):
+    """Pivoted Cholesky of the factorised B (Section 3.2): B ~ L L^T, the
+    steps taken while the residual trace exceeds tol.
+    Returns (L [N_pair][R_B], pivots [R_B], residual diagonal)."""
+    return pivoted_cholesky(tei_matrix_factored(c, V3, M3), tol, R_max)

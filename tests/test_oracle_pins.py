@@ -326,6 +326,79 @@ def test_coulomb_boys_closed_form_h2(orc):
     assert np.max(np.abs(rich - ref) / np.abs(ref)) < 2e-6, errs
 
 
+def test_pivoted_cholesky_is_greedy_schur_complement(orc):
+    """Pivoted Cholesky against its definition: after r steps the residual
+    A - L L^T is the Schur complement of A on the pivots (zero rows and
+    columns there), the next pivot is its largest diagonal entry, L is
+    triangular in pivot order, and a rank-r matrix is recovered exactly."""
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((40, 9))
+    A = X @ X.T
+    L, piv, d = orc.pivoted_cholesky(A, 1e-10 * np.trace(A), 40)
+    assert len(piv) == 9 and len(set(piv.tolist())) == 9
+    assert np.max(np.abs(A - L @ L.T)) <= 1e-12 * np.max(np.abs(A))
+    for r in range(9):
+        assert np.all(L[piv[r], r + 1:] == 0.0)
+    # truncated: explicit Schur complement on the first pivots
+    L4, piv4, d4 = orc.pivoted_cholesky(A, 0.0, 4)
+    P = piv4
+    S = A - A[:, P] @ np.linalg.solve(A[np.ix_(P, P)], A[P, :])
+    np.testing.assert_allclose(A - L4 @ L4.T, S, atol=1e-10 * np.max(np.abs(A)))
+    np.testing.assert_allclose(d4, np.diag(S), atol=1e-10 * np.max(np.abs(A)))
+    for r in range(4):   # each pivot maximises the residual diagonal of its step
+        Pr = P[:r]
+        Sr = A - (A[:, Pr] @ np.linalg.solve(A[np.ix_(Pr, Pr)], A[Pr, :]) if r else 0.0)
+        assert P[r] == int(np.argmax(np.diag(Sr)))
+
+
+def test_density_fit_error_identity_and_interpolation(orc):
+    """F ~ V U with V = F[:, P] and U = A_PP^-1 A_P: interpolates at the
+    pivot points (U[:, P] = I), and |F - V U|_F^2 equals the residual trace
+    of the pivoted Cholesky of A = F^T F, which the tolerance bounds."""
+    n = 96
+    U0, _ = wl.gaussian_products(n, 8.0, 60, seed=4)
+    for F in U0:
+        for tol in (1e-3, 1e-6):
+            U, V, piv, res = orc.density_fit(F, tol, n)
+            R = len(piv)
+            assert 0 < R < n
+            np.testing.assert_array_equal(V, F[:, piv])
+            np.testing.assert_allclose(U[:, piv], np.eye(R), atol=1e-9)
+            err2 = np.sum((F - V @ U) ** 2)
+            trA = np.sum(F * F)
+            assert abs(err2 - res) <= 1e-9 * trA
+            assert err2 <= tol * tol * trA * (1 + 1e-6)
+
+
+def test_factored_tei_matrix_with_fitted_modes_is_J(orc):
+    """With each mode's side matrix fitted to 1e-10 and M_k = U T_k U^T from
+    the convolution and Gram of the fitted rows, the factorised
+    B = sum_k c_k o_l V M_k V^T reproduces J of the TEI assembly."""
+    w = wl.small_products((48, 40, 56), 30, R_N=8, b=7.0, seed=9)
+    ps = []
+    for l in range(3):
+        t, a, cc, p = orc.newton_kernel(w.n[l], w.h[l], w.R_N, w.u0, w.hu)
+        ps.append(p)
+    c = a * w.h[0] * w.h[1] * w.h[2]
+    J = orc.tei_gram(c, ps, w.U)
+    for tol in (1e-6, 1e-10):
+        V3, M3 = [], []
+        for l in range(3):
+            U, V, piv, res = orc.density_fit(w.U[l], tol, w.n[l])
+            V3.append(V)
+            M3.append(orc.gram(U, orc.convolve(ps[l], U)))
+        B = orc.tei_matrix_factored(c, V3, M3)
+        # the fit error of each side matrix is tol relative (Frobenius)
+        assert np.linalg.norm(B - J) <= max(10 * tol, 1e-11) * np.linalg.norm(J)
+    # and the pivoted Cholesky of B: residual diagonal bounds every entry
+    L, piv, d = orc.tei_cholesky(c, V3, M3, 1e-8 * np.trace(B), B.shape[0])
+    S = B - L @ L.T
+    assert np.all(np.abs(S) <= np.sqrt(np.outer(np.abs(np.diag(S)), np.abs(np.diag(S)))) +
+                  1e-12 * np.max(np.abs(B)))
+    assert d.sum() <= 1e-8 * np.trace(B)
+    assert len(piv) < B.shape[0]
+
+
 def test_J_symmetric_psd_products(orc):
     """J = J^T, J_ii > 0 and J is positive semi-definite up to rounding (each
     T_k is positive definite, Schur products of PSD matrices are PSD and
