@@ -293,6 +293,54 @@ size_t tc_coulomb_workspace_bytes(const tc_density *prob, tc_precision prec);
 tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t ws_bytes,
                      void *stream);
 
+/*
+ * tc_density_fit -- 1D density fitting of one mode's side matrix (Section
+ * 3.2): F [N_pair][n] device (row i: a product of two basis functions on the
+ * mode's grid) is approximated as F ~ V U through the diagonally pivoted
+ * Cholesky of A = F^T F over the grid points (never formed: diagonal and
+ * pivot columns from F).  The steps run while the residual trace exceeds
+ * tol^2 trace(A) and fewer than R_max columns exist; with the R pivots P,
+ *   V = F[:, P]                [N_pair][R]  (the products at the pivots),
+ *   U = A[P,P]^-1 A[P, :]      [R][n]       (U[:, P] = I),
+ * and |F - V U|_F^2 equals the residual trace.  Pivot = first index of the
+ * largest residual diagonal entry.
+ *   U_dev [R_max][n], V_dev [N_pair][R_max] device outputs; rows of U and
+ *   columns of V beyond R are zero (so the padded factors can be used as
+ *   they are).  pivots_host [R_max] (may be NULL), R_out, residual_out
+ *   (residual trace; may be NULL) host outputs.
+ *   ws: tc_density_fit_workspace_bytes(n, N_pair, R_max).
+ * Synchronises `stream` after every step (the stopping test reads the
+ * residual trace on the host).
+ */
+size_t tc_density_fit_workspace_bytes(int n, int N_pair, int R_max);
+tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int R_max,
+                         double *U_dev, double *V_dev, int *pivots_host, int *R_out,
+                         double *residual_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tc_tei_cholesky -- pivoted Cholesky of the factorised TEI matrix over the
+ * N_pair products (Section 3.2):
+ *   B = sum_k c_k  o_l  V^l M^l_k V^l^T  ~ L L^T,
+ * B never formed: its diagonal B(i,i) = sum_k c_k prod_l V^l(i,:) M^l_k
+ * V^l(i,:)^T and, per step, its column at the pivot from the factors.  The
+ * steps run while the residual trace exceeds tol trace(B) and fewer than
+ * R_max columns exist; pivot = first index of the largest residual diagonal
+ * entry.  With V^l from tc_density_fit and M^l_k = U^l T^l_k U^l^T (the Grams
+ * of tc_tei_gram's G_saved for the fitted rows U^l), B approximates the TEI
+ * matrix of the products.
+ *   c_dev [R_N]; V_dev host array [3] of device [N_pair][R]; M_dev host array
+ *   [3] of device [R_N][R][R].
+ *   L_dev [R_max][N_pair] device output: row r = column r of the factor.
+ *   pivots_host [R_max] (may be NULL), R_out, residual_out (may be NULL).
+ *   ws: tc_tei_cholesky_workspace_bytes(N_pair, R, R_N, R_max).
+ * Synchronises `stream` after every step.
+ */
+size_t tc_tei_cholesky_workspace_bytes(int N_pair, int R, int R_N, int R_max);
+tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
+                          const double *const *V_dev, const double *const *M_dev, double tol,
+                          int R_max, double *L_dev, int *pivots_host, int *R_out,
+                          double *residual_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *tc_status_string(tc_status s);
 

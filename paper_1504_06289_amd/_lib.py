@@ -33,7 +33,9 @@ TC_OP_TEI_GRAM_BACKWARD = 2
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
            "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
-           "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes")
+           "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
+           "tc_density_fit_workspace_bytes", "tc_tei_cholesky",
+           "tc_tei_cholesky_workspace_bytes")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -127,6 +129,18 @@ def lib() -> ctypes.CDLL:
         L.tc_coulomb.argtypes = [ctypes.POINTER(TcDensity), ctypes.c_int, vp, ctypes.c_size_t,
                                  vp]
         L.tc_coulomb.restype = ctypes.c_int
+        pi = ctypes.POINTER(ctypes.c_int)
+        L.tc_density_fit_workspace_bytes.argtypes = [ctypes.c_int] * 3
+        L.tc_density_fit_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_density_fit.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.c_double,
+                                     ctypes.c_int, vp, vp, pi, pi, pd, vp, ctypes.c_size_t, vp]
+        L.tc_density_fit.restype = ctypes.c_int
+        L.tc_tei_cholesky_workspace_bytes.argtypes = [ctypes.c_int] * 4
+        L.tc_tei_cholesky_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_tei_cholesky.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
+                                      ctypes.c_int, vp, pi, pi, pd, vp, ctypes.c_size_t, vp]
+        L.tc_tei_cholesky.restype = ctypes.c_int
         _lib = L
     return _lib
 

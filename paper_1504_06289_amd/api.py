@@ -113,6 +113,64 @@ def coulomb(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tens
     return Jd
 
 
+def density_fit(F: torch.Tensor, tol: float, R_max: Optional[int] = None):
+    """tc_density_fit: F [N_pair][n] ~ V U through the pivoted Cholesky of
+    F^T F.  Returns (U [R_max][n], V [N_pair][R_max], pivots numpy [R],
+    R, residual trace); rows of U and columns of V beyond R are zero."""
+    _dev_f64(F, "F")
+    N_pair, n = F.shape
+    R_max = n if R_max is None else int(R_max)
+    dev = F.device
+    U = torch.empty((R_max, n), dtype=torch.float64, device=dev)
+    V = torch.empty((N_pair, R_max), dtype=torch.float64, device=dev)
+    piv = np.zeros(R_max, dtype=np.int32)
+    R = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    L = _lib.lib()
+    ws_bytes = L.tc_density_fit_workspace_bytes(n, N_pair, R_max)
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("tc_density_fit: sizes out of range")
+    ws = _workspace(ws_bytes, dev)
+    check(L.tc_density_fit(n, N_pair, _ptr(F), float(tol), R_max, _ptr(U), _ptr(V),
+                           piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(R),
+                           ctypes.byref(res), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_density_fit")
+    return U, V, piv[:R.value].astype(np.int64), R.value, res.value
+
+
+def tei_cholesky(c: torch.Tensor, V3: Sequence[torch.Tensor], M3: Sequence[torch.Tensor],
+                 tol: float, R_max: Optional[int] = None):
+    """tc_tei_cholesky: B = sum_k c_k o_l V^l M^l_k V^l^T ~ L L^T.  V3: three
+    [N_pair][R] tensors, M3: three [R_N][R][R] tensors.  Returns (L [R_B][N_pair]
+    (row r = column r of the factor), pivots numpy [R_B], residual trace)."""
+    _dev_f64(c, "c")
+    N_pair, R = V3[0].shape
+    R_N = c.shape[0]
+    for l in range(3):
+        _dev_f64(V3[l], f"V[{l}]")
+        _dev_f64(M3[l], f"M[{l}]")
+        if tuple(V3[l].shape) != (N_pair, R) or tuple(M3[l].shape) != (R_N, R, R):
+            raise ValueError("V and M shapes must agree across modes")
+    R_max = N_pair if R_max is None else int(R_max)
+    dev = c.device
+    Lout = torch.empty((R_max, N_pair), dtype=torch.float64, device=dev)
+    piv = np.zeros(R_max, dtype=np.int32)
+    RB = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    vp3 = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in V3])
+    mp3 = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in M3])
+    L = _lib.lib()
+    ws_bytes = L.tc_tei_cholesky_workspace_bytes(N_pair, R, R_N, R_max)
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("tc_tei_cholesky: sizes out of range")
+    ws = _workspace(ws_bytes, dev)
+    check(L.tc_tei_cholesky(N_pair, R, R_N, _ptr(c), vp3, mp3, float(tol), R_max, _ptr(Lout),
+                            piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(RB),
+                            ctypes.byref(res), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_tei_cholesky")
+    return Lout[:RB.value], piv[:RB.value].astype(np.int64), res.value
+
+
 def term_classes(p: torch.Tensor) -> np.ndarray:
     """tc_term_classes: per kernel term, B >= 0 (narrow, band B), -2 (smooth,
     low-rank Gram) or -1 (general), as the int8 FFT route treats it."""

@@ -1,0 +1,312 @@
+// 1D density fitting of a side matrix and the pivoted Cholesky of the
+// factorised TEI matrix (Section 3.2), binary64.
+//
+// Both run the diagonally pivoted Cholesky of a positive semi-definite
+// matrix A (N x N) that is never formed: its diagonal and, per step, the
+// column at the pivot come from the factors.
+//   fit:  A = F^T F over the n grid points of one mode, F [N_pair][n]
+//         (rows: products of basis functions);
+//   TEI:  A = B = sum_k c_k o_l V^l M^l_k V^l^T over the N_pair products.
+// A step r with pivot p: col = A[:, p] - sum_{s<r} L_s L_s[p];
+// L_r = col / sqrt(d[p]), zero on the earlier pivots; d -= L_r^2, d[p] = 0;
+// then the next pivot is the first index of the largest residual diagonal
+// entry, and the residual trace decides whether to go on.  L is stored by
+// columns: L [R_max][N], row r = column r of the factor.
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int CT = 256;  // threads of the elementwise kernels
+
+// d[a] = sum_i F[i][a]^2
+__global__ __launch_bounds__(CT) void fit_diag_kernel(const double *__restrict__ F, int n,
+                                                      int N_pair, double *__restrict__ d)
+{
+    const int a = blockIdx.x * CT + threadIdx.x;
+    if (a >= n)
+        return;
+    double s = 0.0;
+    for (int i = 0; i < N_pair; ++i) {
+        const double f = F[(long)i * n + a];
+        s = fma(f, f, s);
+    }
+    d[a] = s;
+}
+
+// col[a] = sum_i F[i][a] F[i][p]  (p read from the device state)
+__global__ __launch_bounds__(CT) void fit_column_kernel(const double *__restrict__ F, int n,
+                                                        int N_pair,
+                                                        const int *__restrict__ state,
+                                                        double *__restrict__ col)
+{
+    const int a = blockIdx.x * CT + threadIdx.x;
+    if (a >= n)
+        return;
+    const int p = state[0];
+    double s = 0.0;
+    for (int i = 0; i < N_pair; ++i)
+        s = fma(F[(long)i * n + a], F[(long)i * n + p], s);
+    col[a] = s;
+}
+
+// y[l][k][s] = sum_t M^l_k[s][t] V^l[j][t] for the pivot j (one workgroup per
+// (l, k), threads over s)
+__global__ __launch_bounds__(CT) void tei_y_kernel(const double *__restrict__ V0,
+                                                   const double *__restrict__ V1,
+                                                   const double *__restrict__ V2,
+                                                   const double *__restrict__ M0,
+                                                   const double *__restrict__ M1,
+                                                   const double *__restrict__ M2, int R,
+                                                   int R_N, const int *__restrict__ state,
+                                                   double *__restrict__ y)
+{
+    const int l = blockIdx.x / R_N, k = blockIdx.x % R_N;
+    const double *V = l == 0 ? V0 : (l == 1 ? V1 : V2);
+    const double *M = (l == 0 ? M0 : (l == 1 ? M1 : M2)) + (long)k * R * R;
+    const double *vj = V + (long)state[0] * R;
+    for (int s = threadIdx.x; s < R; s += CT) {
+        double acc = 0.0;
+        for (int t = 0; t < R; ++t)
+            acc = fma(M[(long)s * R + t], vj[t], acc);
+        y[((long)l * R_N + k) * R + s] = acc;
+    }
+}
+
+// col[i] = sum_k c_k prod_l V^l[i] . y[l][k]   (the column of B at the pivot)
+__global__ __launch_bounds__(CT) void tei_column_kernel(const double *__restrict__ c,
+                                                        const double *__restrict__ V0,
+                                                        const double *__restrict__ V1,
+                                                        const double *__restrict__ V2, int R,
+                                                        int R_N, int N_pair,
+                                                        const double *__restrict__ y,
+                                                        double *__restrict__ col)
+{
+    const int i = blockIdx.x * CT + threadIdx.x;
+    if (i >= N_pair)
+        return;
+    const double *v[3] = {V0 + (long)i * R, V1 + (long)i * R, V2 + (long)i * R};
+    double s = 0.0;
+    for (int k = 0; k < R_N; ++k) {
+        double prod = c[k];
+        for (int l = 0; l < 3; ++l) {
+            const double *yk = y + ((long)l * R_N + k) * R;
+            double dot = 0.0;
+            for (int t = 0; t < R; ++t)
+                dot = fma(v[l][t], yk[t], dot);
+            prod *= dot;
+        }
+        s += prod;
+    }
+    col[i] = s;
+}
+
+// d[i] = B(i, i) = sum_k c_k prod_l V^l[i] M^l_k V^l[i]^T
+__global__ __launch_bounds__(CT) void tei_diag_kernel(const double *__restrict__ c,
+                                                      const double *__restrict__ V0,
+                                                      const double *__restrict__ V1,
+                                                      const double *__restrict__ V2,
+                                                      const double *__restrict__ M0,
+                                                      const double *__restrict__ M1,
+                                                      const double *__restrict__ M2, int R,
+                                                      int R_N, int N_pair,
+                                                      double *__restrict__ d)
+{
+    const int i = blockIdx.x * CT + threadIdx.x;
+    if (i >= N_pair)
+        return;
+    const double *v[3] = {V0 + (long)i * R, V1 + (long)i * R, V2 + (long)i * R};
+    const double *M[3] = {M0, M1, M2};
+    double s = 0.0;
+    for (int k = 0; k < R_N; ++k) {
+        double prod = c[k];
+        for (int l = 0; l < 3; ++l) {
+            const double *Mk = M[l] + (long)k * R * R;
+            double q = 0.0;
+            for (int a = 0; a < R; ++a) {
+                double row = 0.0;
+                for (int b = 0; b < R; ++b)
+                    row = fma(Mk[(long)a * R + b], v[l][b], row);
+                q = fma(v[l][a], row, q);
+            }
+            prod *= q;
+        }
+        s += prod;
+    }
+    d[i] = s;
+}
+
+// step r: L_r = (col - sum_{s<r} L_s L_s[p]) / sqrt(d[p]), zero on the
+// earlier pivots; d -= L_r^2; d[p] = 0
+__global__ __launch_bounds__(CT) void chol_step_kernel(const double *__restrict__ col,
+                                                       double *__restrict__ L, int N, int r,
+                                                       const int *__restrict__ piv,
+                                                       const int *__restrict__ state,
+                                                       double *__restrict__ d)
+{
+    const int a = blockIdx.x * CT + threadIdx.x;
+    if (a >= N)
+        return;
+    const int p = state[0];
+    double v = col[a];
+    for (int s = 0; s < r; ++s)
+        v -= L[(long)s * N + a] * L[(long)s * N + p];
+    double l = v / sqrt(d[p]);
+    for (int s = 0; s < r; ++s)
+        if (piv[s] == a)
+            l = 0.0;
+    L[(long)r * N + a] = l;
+    // every thread reads d[p], so the pivot's own entry is cleared by the
+    // next kernel (chol_select), not here
+    if (a != p)
+        d[a] -= l * l;
+}
+
+// the largest residual diagonal entry (first index among equals) and the
+// residual trace; one workgroup.  state = {pivot}, stats = {max, trace}.
+// `clear`: the previous pivot's entry is set to zero first.
+__global__ __launch_bounds__(1024) void chol_select_kernel(double *__restrict__ d, int N,
+                                                           int clear, int *__restrict__ state,
+                                                           double *__restrict__ stats)
+{
+    __shared__ double smax[1024], ssum[1024];
+    __shared__ int sidx[1024];
+    const int tid = threadIdx.x;
+    if (clear) {
+        const int p = state[0];
+        if (tid == 0)
+            d[p] = 0.0;
+        __syncthreads();
+    }
+    double m = -1.0, s = 0.0;
+    int idx = 0x7fffffff;
+    for (int a = tid; a < N; a += 1024) {
+        const double v = d[a];
+        s += v;
+        if (v > m) {
+            m = v;
+            idx = a;
+        }
+    }
+    smax[tid] = m;
+    ssum[tid] = s;
+    sidx[tid] = idx;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double m2 = smax[tid + w];
+            const int i2 = sidx[tid + w];
+            if (m2 > smax[tid] || (m2 == smax[tid] && i2 < sidx[tid])) {
+                smax[tid] = m2;
+                sidx[tid] = i2;
+            }
+            ssum[tid] += ssum[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        state[0] = sidx[0];
+        stats[0] = smax[0];
+        stats[1] = ssum[0];
+    }
+}
+
+// fit result: T[r][s] = L_s[P[r]] is lower triangular (pivot order); for each
+// grid point a solve T^T u_a = (L_0[a], ..., L_{R-1}[a]) by back substitution
+// and store U[s][a] = u_a[s] (rows s >= R of U zero)
+__global__ __launch_bounds__(CT) void fit_u_kernel(const double *__restrict__ L, int n, int R,
+                                                   int R_max, const int *__restrict__ piv,
+                                                   double *__restrict__ U)
+{
+    const int a = blockIdx.x * CT + threadIdx.x;
+    if (a >= n)
+        return;
+    for (int s = R - 1; s >= 0; --s) {
+        double v = L[(long)s * n + a];
+        for (int r = s + 1; r < R; ++r)
+            v -= L[(long)s * n + piv[r]] * U[(long)r * n + a];  // T[r][s] u[r]
+        U[(long)s * n + a] = v / L[(long)s * n + piv[s]];        // T[s][s]
+    }
+    for (int s = R; s < R_max; ++s)
+        U[(long)s * n + a] = 0.0;
+}
+
+// V[i][r] = F[i][P[r]] for r < R, zero for R <= r < R_max
+__global__ __launch_bounds__(CT) void fit_v_kernel(const double *__restrict__ F, int n,
+                                                   int N_pair, int R, int R_max,
+                                                   const int *__restrict__ piv,
+                                                   double *__restrict__ V)
+{
+    const long e = (long)blockIdx.x * CT + threadIdx.x;
+    if (e >= (long)N_pair * R_max)
+        return;
+    const long i = e / R_max;
+    const int r = (int)(e % R_max);
+    V[e] = r < R ? F[i * n + piv[r]] : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStream_t st)
+{
+    hipLaunchKernelGGL(fit_diag_kernel, dim3((n + CT - 1) / CT), dim3(CT), 0, st, F, n, N_pair,
+                       d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *col,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(fit_column_kernel, dim3((n + CT - 1) / CT), dim3(CT), 0, st, F, n,
+                       N_pair, state, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_tei_diag(const double *c, const double *const *V, const double *const *M,
+                           int R, int R_N, int N_pair, double *d, hipStream_t st)
+{
+    hipLaunchKernelGGL(tei_diag_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, V[0],
+                       V[1], V[2], M[0], M[1], M[2], R, R_N, N_pair, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
+                             int R, int R_N, int N_pair, const int *state, double *y,
+                             double *col, hipStream_t st)
+{
+    hipLaunchKernelGGL(tei_y_kernel, dim3(3 * R_N), dim3(CT), 0, st, V[0], V[1], V[2], M[0],
+                       M[1], M[2], R, R_N, state, y);
+    hipLaunchKernelGGL(tei_column_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c,
+                       V[0], V[1], V[2], R, R_N, N_pair, y, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
+                            const int *state, double *d, hipStream_t st)
+{
+    hipLaunchKernelGGL(chol_step_kernel, dim3((N + CT - 1) / CT), dim3(CT), 0, st, col, L, N, r,
+                       piv, state, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_select(double *d, int N, int clear, int *state, double *stats,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(chol_select_kernel, dim3(1), dim3(1024), 0, st, d, N, clear, state,
+                       stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
+                             int R_max, const int *piv, double *U, double *V, hipStream_t st)
+{
+    hipLaunchKernelGGL(fit_u_kernel, dim3((n + CT - 1) / CT), dim3(CT), 0, st, L, n, R, R_max,
+                       piv, U);
+    const long e = (long)N_pair * R_max;
+    hipLaunchKernelGGL(fit_v_kernel, dim3((unsigned)((e + CT - 1) / CT)), dim3(CT), 0, st, F, n,
+                       N_pair, R, R_max, piv, V);
+    return hipGetLastError();
+}
+
+}  // namespace tc

@@ -660,6 +660,84 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
     return TC_OK;
 }
 
+// ---- pivoted Cholesky drivers --------------------------------------------
+
+// Scratch of one pivoted Cholesky: residual diagonal, pivot column, device
+// pivots, pivot state and statistics, and (fit only) the factor L.
+struct CholScratch {
+    double *d, *col, *L, *y, *stats;
+    int *piv, *state;
+};
+
+CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len)
+{
+    CholScratch s{};
+    s.d = c.take<double>(N);
+    s.col = c.take<double>(N);
+    s.L = own_L ? c.take<double>((size_t)R_max * N) : nullptr;
+    s.y = y_len ? c.take<double>(y_len) : nullptr;
+    s.stats = c.take<double>(2);
+    s.piv = c.take<int>(R_max);
+    s.state = c.take<int>(1);
+    return s;
+}
+
+// Runs the loop: `column` enqueues the column of A at the pivot into s.col.
+// thr_rel: the steps run while the residual trace exceeds thr_rel * trace(A).
+template <class Column>
+tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &s, double *L,
+                           Column column, int *pivots_host, int *R_out, double *residual_out,
+                           hipStream_t st)
+{
+    double stats[2];
+    int p = 0;
+    auto fetch = [&]() {
+        return hipMemcpyAsync(stats, s.stats, sizeof stats, hipMemcpyDeviceToHost, st) ==
+                       hipSuccess &&
+               hipMemcpyAsync(&p, s.state, sizeof p, hipMemcpyDeviceToHost, st) ==
+                       hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    };
+    TRYK("chol_select", launch_chol_select(s.d, N, 0, s.state, s.stats, st));
+    if (!fetch())
+        return TC_ERR_HIP;
+    const double thr = thr_rel * stats[1];
+    int r = 0;
+    while (r < R_max && stats[1] > thr && stats[0] > 0.0) {
+        if (pivots_host)
+            pivots_host[r] = p;
+        if (hipMemcpyAsync(s.piv + r, s.state, sizeof(int), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return TC_ERR_HIP;
+        const tc_status cs = column(st);
+        if (cs != TC_OK)
+            return cs;
+        TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.piv, s.state, s.d, st));
+        TRYK("chol_select", launch_chol_select(s.d, N, 1, s.state, s.stats, st));
+        if (!fetch())
+            return TC_ERR_HIP;
+        ++r;
+    }
+    *R_out = r;
+    if (residual_out)
+        *residual_out = stats[1];
+    return TC_OK;
+}
+
+size_t fit_ws(int n, int R_max)
+{
+    Carver c(nullptr);
+    carve_chol(c, n, R_max, true, 0);
+    return c.used;
+}
+
+size_t tei_chol_ws(int N_pair, int R, int R_N, int R_max)
+{
+    Carver c(nullptr);
+    carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * R);
+    return c.used;
+}
+
 }  // namespace
 
 extern "C" {
@@ -784,6 +862,77 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double
     const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false);
     return mode_W(prec, resolve(n, R_f, R_N, prec), n, R_f, R_N, p_dev, U_dev, W_dev, s,
                   (hipStream_t)stream);
+}
+
+
+size_t tc_density_fit_workspace_bytes(int n, int N_pair, int R_max)
+{
+    if (n < 1 || n > TC_MAX_N || N_pair < 1 || N_pair > TC_MAX_RF || R_max < 1 || R_max > n)
+        return (size_t)-1;
+    return fit_ws(n, R_max);
+}
+
+tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int R_max,
+                         double *U_dev, double *V_dev, int *pivots_host, int *R_out,
+                         double *residual_out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (n < 1 || n > TC_MAX_N || N_pair < 1 || N_pair > TC_MAX_RF || R_max < 1 || R_max > n ||
+        !F_dev || !U_dev || !V_dev || !R_out || !(tol >= 0.0) || !std::isfinite(tol))
+        return TC_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < fit_ws(n, R_max))
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carver c(ws);
+    const CholScratch s = carve_chol(c, n, R_max, true, 0);
+    TRYK("fit_diag", launch_fit_diag(F_dev, n, N_pair, s.d, st));
+    auto column = [&](hipStream_t cst) -> tc_status {
+        if (launch_fit_column(F_dev, n, N_pair, s.state, s.col, cst) != hipSuccess)
+            return TC_ERR_HIP;
+        return TC_OK;
+    };
+    const tc_status r = pivoted_cholesky(n, R_max, tol * tol, s, s.L, column, pivots_host,
+                                         R_out, residual_out, st);
+    if (r != TC_OK)
+        return r;
+    TRYK("fit_finish", launch_fit_finish(F_dev, s.L, n, N_pair, *R_out, R_max, s.piv, U_dev,
+                                         V_dev, st));
+    return hipStreamSynchronize(st) == hipSuccess ? TC_OK : TC_ERR_HIP;
+}
+
+size_t tc_tei_cholesky_workspace_bytes(int N_pair, int R, int R_N, int R_max)
+{
+    if (N_pair < 1 || N_pair > TC_MAX_RF || R < 1 || R > TC_MAX_RF || R_N < 1 ||
+        R_N > TC_MAX_RN || R_max < 1 || R_max > N_pair)
+        return (size_t)-1;
+    return tei_chol_ws(N_pair, R, R_N, R_max);
+}
+
+tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
+                          const double *const *V_dev, const double *const *M_dev, double tol,
+                          int R_max, double *L_dev, int *pivots_host, int *R_out,
+                          double *residual_out, void *ws, size_t ws_bytes, void *stream)
+{
+    if (N_pair < 1 || N_pair > TC_MAX_RF || R < 1 || R > TC_MAX_RF || R_N < 1 ||
+        R_N > TC_MAX_RN || R_max < 1 || R_max > N_pair || !c_dev || !V_dev || !M_dev ||
+        !L_dev || !R_out || !(tol >= 0.0) || !std::isfinite(tol))
+        return TC_ERR_INVALID_ARG;
+    for (int l = 0; l < 3; ++l)
+        if (!V_dev[l] || !M_dev[l])
+            return TC_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < tei_chol_ws(N_pair, R, R_N, R_max))
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carver c(ws);
+    const CholScratch s = carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * R);
+    TRYK("tei_diag", launch_tei_diag(c_dev, V_dev, M_dev, R, R_N, N_pair, s.d, st));
+    auto column = [&](hipStream_t cst) -> tc_status {
+        if (launch_tei_column(c_dev, V_dev, M_dev, R, R_N, N_pair, s.state, s.y, s.col, cst) !=
+            hipSuccess)
+            return TC_ERR_HIP;
+        return TC_OK;
+    };
+    return pivoted_cholesky(N_pair, R_max, tol, s, L_dev, column, pivots_host, R_out,
+                            residual_out, st);
 }
 
 size_t tc_coulomb_workspace_bytes(const tc_density *prob, tc_precision prec)

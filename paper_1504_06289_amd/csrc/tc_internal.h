@@ -138,6 +138,24 @@ hipError_t launch_cross_gram_f64(const double *U, const double *W, double *H, in
 hipError_t launch_coulomb_reduce(const double *c, const double *d, const double *H, int R_f,
                                  int R_rho, int R_N, double *Jd, hipStream_t stream);
 
+// ---- pivoted Cholesky: density fitting and the factorised TEI matrix -------
+// (cholesky.hip).  state = {pivot} (device int), stats = {max, trace}
+hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStream_t st);
+hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *col,
+                             hipStream_t st);
+hipError_t launch_tei_diag(const double *c, const double *const *V, const double *const *M,
+                           int R, int R_N, int N_pair, double *d, hipStream_t st);
+// y: scratch [3][R_N][R]
+hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
+                             int R, int R_N, int N_pair, const int *state, double *y,
+                             double *col, hipStream_t st);
+hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
+                            const int *state, double *d, hipStream_t st);
+hipError_t launch_chol_select(double *d, int N, int clear, int *state, double *stats,
+                              hipStream_t st);
+hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
+                             int R_max, const int *piv, double *U, double *V, hipStream_t st);
+
 // ---- term classes and smooth terms (lowrank.hip) ---------------------------
 constexpr int kBandMax = 16;   // widest band of a narrow term
 constexpr int kPolyRank = 32;  // polynomial degree < kPolyRank for a smooth term

@@ -243,3 +243,25 @@ def test_coulomb_workspace_and_rejects(L):
     assert L.tc_coulomb(ctypes.byref(D), _lib.TC_FP64, None, 0, None) == _lib.TC_ERR_WORKSPACE
     assert L.tc_coulomb(ctypes.byref(D), 42, None, 0, None) == _lib.TC_ERR_INVALID_ARG
 
+
+def test_density_fit_and_tei_cholesky_reject(L):
+    v = ctypes.c_void_p(0x1000)
+    R = ctypes.c_int(0)
+    assert L.tc_density_fit_workspace_bytes(0, 5, 3) == ctypes.c_size_t(-1).value
+    assert L.tc_density_fit_workspace_bytes(10, 5, 11) == ctypes.c_size_t(-1).value
+    assert L.tc_density_fit(10, 5, v, 1e-6, 3, v, v, None, ctypes.byref(R), None, None, 0,
+                            None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_density_fit(10, 5, None, 1e-6, 3, v, v, None, ctypes.byref(R), None, None, 0,
+                            None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_density_fit(10, 5, v, -1.0, 3, v, v, None, ctypes.byref(R), None, None, 0,
+                            None) == _lib.TC_ERR_INVALID_ARG
+    vp3 = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    nul3 = (ctypes.c_void_p * 3)(0x1000, None, 0x1000)
+    assert L.tc_tei_cholesky_workspace_bytes(10, 4, 3, 11) == ctypes.c_size_t(-1).value
+    assert L.tc_tei_cholesky(10, 4, 3, v, vp3, vp3, 1e-6, 5, v, None, ctypes.byref(R), None,
+                             None, 0, None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_tei_cholesky(10, 4, 3, v, nul3, vp3, 1e-6, 5, v, None, ctypes.byref(R), None,
+                             None, 0, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tei_cholesky(10, 4, 300, v, vp3, vp3, 1e-6, 5, v, None, ctypes.byref(R), None,
+                             None, 0, None) == _lib.TC_ERR_INVALID_ARG
+
