@@ -329,7 +329,7 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
  * of tc_tei_gram's G_saved for the fitted rows U^l), B approximates the TEI
  * matrix of the products.
  *   c_dev [R_N]; V_dev host array [3] of device [N_pair][R]; M_dev host array
- *   [3] of device [R_N][R][R].
+ *   [3] of device [R_N][R][R], each M^l_k symmetric.
  *   L_dev [R_max][N_pair] device output: row r = column r of the factor.
  *   pivots_host [R_max] (may be NULL), R_out, residual_out (may be NULL).
  *   ws: tc_tei_cholesky_workspace_bytes(N_pair, R, R_N, R_max).

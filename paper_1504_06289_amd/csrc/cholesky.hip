@@ -35,19 +35,36 @@ __global__ __launch_bounds__(CT) void fit_diag_kernel(const double *__restrict__
     d[a] = s;
 }
 
-// col[a] = sum_i F[i][a] F[i][p]  (p read from the device state)
+// col[a] = sum_i F[i][a] F[i][p]  (p read from the device state), rows split
+// into kFitSplit contiguous chunks (blockIdx.y); part[z][a] the chunk sums
+constexpr int kFitSplit = 16;
+
 __global__ __launch_bounds__(CT) void fit_column_kernel(const double *__restrict__ F, int n,
                                                         int N_pair,
                                                         const int *__restrict__ state,
-                                                        double *__restrict__ col)
+                                                        double *__restrict__ part)
 {
     const int a = blockIdx.x * CT + threadIdx.x;
     if (a >= n)
         return;
     const int p = state[0];
+    const int z = blockIdx.y;
+    const int ib = (int)((long)z * N_pair / kFitSplit), ie = (int)((long)(z + 1) * N_pair / kFitSplit);
     double s = 0.0;
-    for (int i = 0; i < N_pair; ++i)
+    for (int i = ib; i < ie; ++i)
         s = fma(F[(long)i * n + a], F[(long)i * n + p], s);
+    part[(long)z * n + a] = s;
+}
+
+__global__ __launch_bounds__(CT) void fit_column_reduce(const double *__restrict__ part, int n,
+                                                        double *__restrict__ col)
+{
+    const int a = blockIdx.x * CT + threadIdx.x;
+    if (a >= n)
+        return;
+    double s = 0.0;
+    for (int z = 0; z < kFitSplit; ++z)
+        s += part[(long)z * n + a];
     col[a] = s;
 }
 
@@ -74,42 +91,31 @@ __global__ __launch_bounds__(CT) void tei_y_kernel(const double *__restrict__ V0
     }
 }
 
-// col[i] = sum_k c_k prod_l V^l[i] . y[l][k]   (the column of B at the pivot)
+// col[i] = sum_k c_k prod_l Z^l[i][k] with Z^l = V^l y^l^T (the column of B
+// at the pivot; Z from cross_gram_f64)
 __global__ __launch_bounds__(CT) void tei_column_kernel(const double *__restrict__ c,
-                                                        const double *__restrict__ V0,
-                                                        const double *__restrict__ V1,
-                                                        const double *__restrict__ V2, int R,
-                                                        int R_N, int N_pair,
-                                                        const double *__restrict__ y,
-                                                        double *__restrict__ col)
+                                                        const double *__restrict__ Z, int R_N,
+                                                        int N_pair, double *__restrict__ col)
 {
     const int i = blockIdx.x * CT + threadIdx.x;
     if (i >= N_pair)
         return;
-    const double *v[3] = {V0 + (long)i * R, V1 + (long)i * R, V2 + (long)i * R};
+    const long plane = (long)N_pair * R_N;
     double s = 0.0;
     for (int k = 0; k < R_N; ++k) {
-        double prod = c[k];
-        for (int l = 0; l < 3; ++l) {
-            const double *yk = y + ((long)l * R_N + k) * R;
-            double dot = 0.0;
-            for (int t = 0; t < R; ++t)
-                dot = fma(v[l][t], yk[t], dot);
-            prod *= dot;
-        }
-        s += prod;
+        const long o = (long)i * R_N + k;
+        s += c[k] * (Z[o] * Z[plane + o] * Z[2 * plane + o]);
     }
     col[i] = s;
 }
 
-// d[i] = B(i, i) = sum_k c_k prod_l V^l[i] M^l_k V^l[i]^T
+// d[i] = B(i, i) = sum_k c_k prod_l V^l[i] . Y^l[k][i] with Y^l_k = V^l M^l_k
+// (from cross_gram_f64; M symmetric)
 __global__ __launch_bounds__(CT) void tei_diag_kernel(const double *__restrict__ c,
                                                       const double *__restrict__ V0,
                                                       const double *__restrict__ V1,
                                                       const double *__restrict__ V2,
-                                                      const double *__restrict__ M0,
-                                                      const double *__restrict__ M1,
-                                                      const double *__restrict__ M2, int R,
+                                                      const double *__restrict__ Y, int R,
                                                       int R_N, int N_pair,
                                                       double *__restrict__ d)
 {
@@ -117,19 +123,15 @@ __global__ __launch_bounds__(CT) void tei_diag_kernel(const double *__restrict__
     if (i >= N_pair)
         return;
     const double *v[3] = {V0 + (long)i * R, V1 + (long)i * R, V2 + (long)i * R};
-    const double *M[3] = {M0, M1, M2};
+    const long plane = (long)R_N * N_pair * R;
     double s = 0.0;
     for (int k = 0; k < R_N; ++k) {
         double prod = c[k];
         for (int l = 0; l < 3; ++l) {
-            const double *Mk = M[l] + (long)k * R * R;
+            const double *yk = Y + l * plane + ((long)k * N_pair + i) * R;
             double q = 0.0;
-            for (int a = 0; a < R; ++a) {
-                double row = 0.0;
-                for (int b = 0; b < R; ++b)
-                    row = fma(Mk[(long)a * R + b], v[l][b], row);
-                q = fma(v[l][a], row, q);
-            }
+            for (int a = 0; a < R; ++a)
+                q = fma(v[l][a], yk[a], q);
             prod *= q;
         }
         s += prod;
@@ -255,30 +257,50 @@ hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *col,
-                             hipStream_t st)
+hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *part,
+                             double *col, hipStream_t st)
 {
-    hipLaunchKernelGGL(fit_column_kernel, dim3((n + CT - 1) / CT), dim3(CT), 0, st, F, n,
-                       N_pair, state, col);
+    hipLaunchKernelGGL(fit_column_kernel, dim3((n + CT - 1) / CT, kFitSplit), dim3(CT), 0, st, F,
+                       n, N_pair, state, part);
+    hipLaunchKernelGGL(fit_column_reduce, dim3((n + CT - 1) / CT), dim3(CT), 0, st, part, n,
+                       col);
     return hipGetLastError();
 }
 
+int fit_column_parts() { return kFitSplit; }
+
 hipError_t launch_tei_diag(const double *c, const double *const *V, const double *const *M,
-                           int R, int R_N, int N_pair, double *d, hipStream_t st)
+                           int R, int R_N, int N_pair, double *Y, double *d, hipStream_t st)
 {
+    const long plane = (long)R_N * N_pair * R;
+    for (int l = 0; l < 3; ++l) {
+        // Y^l[k][i][m] = sum_a V^l[i][a] M^l_k[m][a] = (V^l M^l_k)[i][m]
+        const hipError_t e = launch_cross_gram_f64(V[l], M[l], Y + l * plane, R, N_pair, R, R_N,
+                                                   st);
+        if (e != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(tei_diag_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, V[0],
-                       V[1], V[2], M[0], M[1], M[2], R, R_N, N_pair, d);
+                       V[1], V[2], Y, R, R_N, N_pair, d);
     return hipGetLastError();
 }
 
 hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
-                             int R, int R_N, int N_pair, const int *state, double *y,
+                             int R, int R_N, int N_pair, const int *state, double *y, double *Z,
                              double *col, hipStream_t st)
 {
     hipLaunchKernelGGL(tei_y_kernel, dim3(3 * R_N), dim3(CT), 0, st, V[0], V[1], V[2], M[0],
                        M[1], M[2], R, R_N, state, y);
-    hipLaunchKernelGGL(tei_column_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c,
-                       V[0], V[1], V[2], R, R_N, N_pair, y, col);
+    const long plane = (long)N_pair * R_N;
+    for (int l = 0; l < 3; ++l) {
+        // Z^l[i][k] = sum_a V^l[i][a] y^l[k][a]
+        const hipError_t e = launch_cross_gram_f64(V[l], y + (long)l * R_N * R, Z + l * plane, R,
+                                                   N_pair, R_N, 1, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(tei_column_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, Z,
+                       R_N, N_pair, col);
     return hipGetLastError();
 }
 

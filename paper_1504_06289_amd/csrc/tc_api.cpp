@@ -665,17 +665,19 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
 // Scratch of one pivoted Cholesky: residual diagonal, pivot column, device
 // pivots, pivot state and statistics, and (fit only) the factor L.
 struct CholScratch {
-    double *d, *col, *L, *y, *stats;
+    double *d, *col, *L, *y, *Yd, *stats;
     int *piv, *state;
 };
 
-CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len)
+CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
+                       size_t Yd_len = 0)
 {
     CholScratch s{};
     s.d = c.take<double>(N);
     s.col = c.take<double>(N);
     s.L = own_L ? c.take<double>((size_t)R_max * N) : nullptr;
     s.y = y_len ? c.take<double>(y_len) : nullptr;
+    s.Yd = Yd_len ? c.take<double>(Yd_len) : nullptr;
     s.stats = c.take<double>(2);
     s.piv = c.take<int>(R_max);
     s.state = c.take<int>(1);
@@ -727,14 +729,15 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
 size_t fit_ws(int n, int R_max)
 {
     Carver c(nullptr);
-    carve_chol(c, n, R_max, true, 0);
+    carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n);
     return c.used;
 }
 
 size_t tei_chol_ws(int N_pair, int R, int R_N, int R_max)
 {
     Carver c(nullptr);
-    carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * R);
+    carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * (R + N_pair),
+               (size_t)3 * R_N * N_pair * R);
     return c.used;
 }
 
@@ -883,10 +886,10 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
-    const CholScratch s = carve_chol(c, n, R_max, true, 0);
+    const CholScratch s = carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n);
     TRYK("fit_diag", launch_fit_diag(F_dev, n, N_pair, s.d, st));
     auto column = [&](hipStream_t cst) -> tc_status {
-        if (launch_fit_column(F_dev, n, N_pair, s.state, s.col, cst) != hipSuccess)
+        if (launch_fit_column(F_dev, n, N_pair, s.state, s.y, s.col, cst) != hipSuccess)
             return TC_ERR_HIP;
         return TC_OK;
     };
@@ -923,11 +926,12 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
-    const CholScratch s = carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * R);
-    TRYK("tei_diag", launch_tei_diag(c_dev, V_dev, M_dev, R, R_N, N_pair, s.d, st));
+    const CholScratch s = carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * (R + N_pair),
+                                     (size_t)3 * R_N * N_pair * R);
+    TRYK("tei_diag", launch_tei_diag(c_dev, V_dev, M_dev, R, R_N, N_pair, s.Yd, s.d, st));
     auto column = [&](hipStream_t cst) -> tc_status {
-        if (launch_tei_column(c_dev, V_dev, M_dev, R, R_N, N_pair, s.state, s.y, s.col, cst) !=
-            hipSuccess)
+        if (launch_tei_column(c_dev, V_dev, M_dev, R, R_N, N_pair, s.state, s.y,
+                              s.y + (size_t)3 * R_N * R, s.col, cst) != hipSuccess)
             return TC_ERR_HIP;
         return TC_OK;
     };

@@ -141,13 +141,16 @@ hipError_t launch_coulomb_reduce(const double *c, const double *d, const double 
 // ---- pivoted Cholesky: density fitting and the factorised TEI matrix -------
 // (cholesky.hip).  state = {pivot} (device int), stats = {max, trace}
 hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStream_t st);
-hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *col,
-                             hipStream_t st);
+// part: scratch [fit_column_parts()][n]
+int fit_column_parts();
+hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *state, double *part,
+                             double *col, hipStream_t st);
+// Y: scratch [3][R_N][N_pair][R] (V^l M^l_k; M symmetric)
 hipError_t launch_tei_diag(const double *c, const double *const *V, const double *const *M,
-                           int R, int R_N, int N_pair, double *d, hipStream_t st);
-// y: scratch [3][R_N][R]
+                           int R, int R_N, int N_pair, double *Y, double *d, hipStream_t st);
+// y: scratch [3][R_N][R]; Z: scratch [3][N_pair][R_N]
 hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
-                             int R, int R_N, int N_pair, const int *state, double *y,
+                             int R, int R_N, int N_pair, const int *state, double *y, double *Z,
                              double *col, hipStream_t st);
 hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
                             const int *state, double *d, hipStream_t st);
