@@ -20,8 +20,10 @@ Prints ONE JSON line.
               library runs the three modes in turn (each kernel alone on the
               device); the headline region runs them concurrently.
   rows        the adjoint (2048 cells, R_f=512, forward + backward of w^T J w),
-              the 64-instance batched workload, and the Coulomb entries of the
-              4096-cell functions against a 64-term density, per-step times.
+              the 64-instance batched workload, the Coulomb entries of the
+              4096-cell functions against a 64-term density, and the density
+              fitting + pivoted Cholesky of the factorised TEI matrix of the
+              4096-cell products, per-call times.
   cpu_baseline  the FP64 oracle on a bounded sample (columns of J).
 """
 from __future__ import annotations
@@ -419,6 +421,29 @@ def extra_rows(tc, wl, torch, dev, args):
                                           "TFLOP/s": round(fl / (ms_cg * 1e-3) / 1e12, 2),
                                           "frac": round(fl / (ms_cg * 1e-3) / 1e12 / PEAK["fp64"], 4)}
     rows["coulomb_kernels"] = {k: round(v[0], 4) for k, v in prof.items()}
+    # 1D density fitting of the three side matrices of the 4096-cell products
+    # (tolerance 1e-6), the Grams of the fitted rows, and the pivoted Cholesky
+    # of the factorised TEI matrix (tolerance 1e-8 of its trace)
+    import time as _time
+    for _rep in range(2):  # the second pass is reported
+        torch.cuda.synchronize()
+        t0 = _time.perf_counter()
+        fits = [tc.density_fit(U3[l], 1e-6) for l in range(3)]
+        torch.cuda.synchronize()
+        t1 = _time.perf_counter()
+        R = max(f[3] for f in fits)
+        Ud = [f[0][:R].contiguous() for f in fits]
+        Vd = [f[1][:, :R].contiguous() for f in fits]
+        J, G = tc.tei_gram(cd, [p, p, p], Ud, prec="fp64", save_G=True)
+        torch.cuda.synchronize()
+        t2 = _time.perf_counter()
+        Lb, piv, res = tc.tei_cholesky(cd, Vd, [G[l].contiguous() for l in range(3)], 1e-8)
+        torch.cuda.synchronize()
+        t3 = _time.perf_counter()
+    rows["tei_cholesky_c3"] = {"fit_ranks": [int(f[3]) for f in fits], "R_B": int(Lb.shape[0]),
+                               "fit_ms": round(1e3 * (t1 - t0), 2),
+                               "fitted_grams_ms": round(1e3 * (t2 - t1), 2),
+                               "cholesky_ms": round(1e3 * (t3 - t2), 2)}
     return rows
 
 

@@ -11,7 +11,9 @@
 // L_r = col / sqrt(d[p]), zero on the earlier pivots; d -= L_r^2, d[p] = 0;
 // then the next pivot is the first index of the largest residual diagonal
 // entry, and the residual trace decides whether to go on.  L is stored by
-// columns: L [R_max][N], row r = column r of the factor.
+// columns: L [R_max][N], row r = column r of the factor.  The stopping test
+// runs on the device (a `done` flag that turns the later kernels into no-ops),
+// so the host enqueues several steps between synchronisations.
 #include "tc_internal.h"
 
 namespace tc {
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(CT) void fit_column_kernel(const double *__restrict
                                                         double *__restrict__ part)
 {
     const int a = blockIdx.x * CT + threadIdx.x;
-    if (a >= n)
+    if (a >= n || state[1])
         return;
     const int p = state[0];
     const int z = blockIdx.y;
@@ -57,10 +59,11 @@ __global__ __launch_bounds__(CT) void fit_column_kernel(const double *__restrict
 }
 
 __global__ __launch_bounds__(CT) void fit_column_reduce(const double *__restrict__ part, int n,
+                                                        const int *__restrict__ state,
                                                         double *__restrict__ col)
 {
     const int a = blockIdx.x * CT + threadIdx.x;
-    if (a >= n)
+    if (a >= n || state[1])
         return;
     double s = 0.0;
     for (int z = 0; z < kFitSplit; ++z)
@@ -79,6 +82,8 @@ __global__ __launch_bounds__(CT) void tei_y_kernel(const double *__restrict__ V0
                                                    int R_N, const int *__restrict__ state,
                                                    double *__restrict__ y)
 {
+    if (state[1])
+        return;
     const int l = blockIdx.x / R_N, k = blockIdx.x % R_N;
     const double *V = l == 0 ? V0 : (l == 1 ? V1 : V2);
     const double *M = (l == 0 ? M0 : (l == 1 ? M1 : M2)) + (long)k * R * R;
@@ -95,10 +100,12 @@ __global__ __launch_bounds__(CT) void tei_y_kernel(const double *__restrict__ V0
 // at the pivot; Z from cross_gram_f64)
 __global__ __launch_bounds__(CT) void tei_column_kernel(const double *__restrict__ c,
                                                         const double *__restrict__ Z, int R_N,
-                                                        int N_pair, double *__restrict__ col)
+                                                        int N_pair,
+                                                        const int *__restrict__ state,
+                                                        double *__restrict__ col)
 {
     const int i = blockIdx.x * CT + threadIdx.x;
-    if (i >= N_pair)
+    if (i >= N_pair || state[1])
         return;
     const long plane = (long)N_pair * R_N;
     double s = 0.0;
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(CT) void chol_step_kernel(const double *__restrict_
                                                        double *__restrict__ d)
 {
     const int a = blockIdx.x * CT + threadIdx.x;
-    if (a >= N)
+    if (a >= N || state[1])
         return;
     const int p = state[0];
     double v = col[a];
@@ -165,16 +172,22 @@ __global__ __launch_bounds__(CT) void chol_step_kernel(const double *__restrict_
         d[a] -= l * l;
 }
 
-// the largest residual diagonal entry (first index among equals) and the
-// residual trace; one workgroup.  state = {pivot}, stats = {max, trace}.
-// `clear`: the previous pivot's entry is set to zero first.
+// The largest residual diagonal entry (first index among equals) and the
+// residual trace; one workgroup.  state = {pivot, done, steps}, stats = {max,
+// trace}.  Nothing happens once done is set.  `clear`: the last pivot's entry
+// is set to zero first; `steps`: the steps completed so far.  The process is
+// done when steps >= R_max, the trace is at most thr or the maximum is not
+// positive; otherwise the maximum's index is the next pivot.
 __global__ __launch_bounds__(1024) void chol_select_kernel(double *__restrict__ d, int N,
-                                                           int clear, int *__restrict__ state,
+                                                           int clear, int steps, double thr,
+                                                           int R_max, int *__restrict__ state,
                                                            double *__restrict__ stats)
 {
     __shared__ double smax[1024], ssum[1024];
     __shared__ int sidx[1024];
     const int tid = threadIdx.x;
+    if (state[1])
+        return;
     if (clear) {
         const int p = state[0];
         if (tid == 0)
@@ -208,10 +221,29 @@ __global__ __launch_bounds__(1024) void chol_select_kernel(double *__restrict__ 
         __syncthreads();
     }
     if (tid == 0) {
-        state[0] = sidx[0];
         stats[0] = smax[0];
         stats[1] = ssum[0];
+        if (steps >= R_max || !(ssum[0] > thr) || !(smax[0] > 0.0)) {
+            state[1] = 1;
+            state[2] = steps;
+        } else {
+            state[0] = sidx[0];
+        }
     }
+}
+
+__global__ void fill_int_kernel(int *__restrict__ x, int count, int value)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        x[i] = value;
+}
+
+// piv[r] = the current pivot (unless done)
+__global__ void chol_record_kernel(int r, const int *__restrict__ state, int *__restrict__ piv)
+{
+    if (threadIdx.x == 0 && !state[1])
+        piv[r] = state[0];
 }
 
 // fit result: T[r][s] = L_s[P[r]] is lower triangular (pivot order); for each
@@ -263,7 +295,7 @@ hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *stat
     hipLaunchKernelGGL(fit_column_kernel, dim3((n + CT - 1) / CT, kFitSplit), dim3(CT), 0, st, F,
                        n, N_pair, state, part);
     hipLaunchKernelGGL(fit_column_reduce, dim3((n + CT - 1) / CT), dim3(CT), 0, st, part, n,
-                       col);
+                       state, col);
     return hipGetLastError();
 }
 
@@ -300,7 +332,7 @@ hipError_t launch_tei_column(const double *c, const double *const *V, const doub
             return e;
     }
     hipLaunchKernelGGL(tei_column_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, Z,
-                       R_N, N_pair, col);
+                       R_N, N_pair, state, col);
     return hipGetLastError();
 }
 
@@ -312,11 +344,24 @@ hipError_t launch_chol_step(const double *col, double *L, int N, int r, const in
     return hipGetLastError();
 }
 
-hipError_t launch_chol_select(double *d, int N, int clear, int *state, double *stats,
-                              hipStream_t st)
+hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
+                              int *state, double *stats, hipStream_t st)
 {
-    hipLaunchKernelGGL(chol_select_kernel, dim3(1), dim3(1024), 0, st, d, N, clear, state,
-                       stats);
+    hipLaunchKernelGGL(chol_select_kernel, dim3(1), dim3(1024), 0, st, d, N, clear, steps, thr,
+                       R_max, state, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_int_kernel, dim3((count + 255) / 256), dim3(256), 0, st, x, count,
+                       value);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_record(int r, const int *state, int *piv, hipStream_t st)
+{
+    hipLaunchKernelGGL(chol_record_kernel, dim3(1), dim3(64), 0, st, r, state, piv);
     return hipGetLastError();
 }
 

@@ -680,49 +680,63 @@ CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
     s.Yd = Yd_len ? c.take<double>(Yd_len) : nullptr;
     s.stats = c.take<double>(2);
     s.piv = c.take<int>(R_max);
-    s.state = c.take<int>(1);
+    s.state = c.take<int>(3);
     return s;
 }
 
 // Runs the loop: `column` enqueues the column of A at the pivot into s.col.
 // thr_rel: the steps run while the residual trace exceeds thr_rel * trace(A).
+// After one synchronisation for trace(A), the steps are enqueued in groups of
+// kCholGroup; the device stops itself (done flag) and the host checks the
+// flag once per group.
+constexpr int kCholGroup = 16;
+
 template <class Column>
 tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &s, double *L,
                            Column column, int *pivots_host, int *R_out, double *residual_out,
                            hipStream_t st)
 {
     double stats[2];
-    int p = 0;
+    int state[3];
     auto fetch = [&]() {
         return hipMemcpyAsync(stats, s.stats, sizeof stats, hipMemcpyDeviceToHost, st) ==
                        hipSuccess &&
-               hipMemcpyAsync(&p, s.state, sizeof p, hipMemcpyDeviceToHost, st) ==
+               hipMemcpyAsync(state, s.state, sizeof state, hipMemcpyDeviceToHost, st) ==
                        hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
     };
-    TRYK("chol_select", launch_chol_select(s.d, N, 0, s.state, s.stats, st));
+    TRYK("chol_init", launch_fill_int(s.state, 3, 0, st));
+    TRYK("chol_select", launch_chol_select(s.d, N, 0, 0, -1.0, R_max, s.state, s.stats, st));
     if (!fetch())
         return TC_ERR_HIP;
     const double thr = thr_rel * stats[1];
+    if (!state[1] && !(stats[1] > thr)) {  // nothing to do: zero steps
+        state[1] = 1;
+        state[2] = 0;
+    }
     int r = 0;
-    while (r < R_max && stats[1] > thr && stats[0] > 0.0) {
-        if (pivots_host)
-            pivots_host[r] = p;
-        if (hipMemcpyAsync(s.piv + r, s.state, sizeof(int), hipMemcpyDeviceToDevice, st) !=
-            hipSuccess)
-            return TC_ERR_HIP;
-        const tc_status cs = column(st);
-        if (cs != TC_OK)
-            return cs;
-        TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.piv, s.state, s.d, st));
-        TRYK("chol_select", launch_chol_select(s.d, N, 1, s.state, s.stats, st));
+    while (!state[1]) {
+        for (int g = 0; g < kCholGroup && r < R_max; ++g, ++r) {
+            TRYK("chol_record", launch_chol_record(r, s.state, s.piv, st));
+            const tc_status cs = column(st);
+            if (cs != TC_OK)
+                return cs;
+            TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.piv, s.state, s.d, st));
+            TRYK("chol_select", launch_chol_select(s.d, N, 1, r + 1, thr, R_max, s.state,
+                                                   s.stats, st));
+        }
         if (!fetch())
             return TC_ERR_HIP;
-        ++r;
     }
-    *R_out = r;
+    const int R = state[2];
+    *R_out = R;
     if (residual_out)
         *residual_out = stats[1];
+    if (pivots_host && R > 0 &&
+        (hipMemcpyAsync(pivots_host, s.piv, sizeof(int) * R, hipMemcpyDeviceToHost, st) !=
+             hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+        return TC_ERR_HIP;
     return TC_OK;
 }
 

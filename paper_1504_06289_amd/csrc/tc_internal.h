@@ -139,7 +139,7 @@ hipError_t launch_coulomb_reduce(const double *c, const double *d, const double 
                                  int R_rho, int R_N, double *Jd, hipStream_t stream);
 
 // ---- pivoted Cholesky: density fitting and the factorised TEI matrix -------
-// (cholesky.hip).  state = {pivot} (device int), stats = {max, trace}
+// (cholesky.hip).  stats = {max, trace}
 hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStream_t st);
 // part: scratch [fit_column_parts()][n]
 int fit_column_parts();
@@ -154,8 +154,11 @@ hipError_t launch_tei_column(const double *c, const double *const *V, const doub
                              double *col, hipStream_t st);
 hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
                             const int *state, double *d, hipStream_t st);
-hipError_t launch_chol_select(double *d, int N, int clear, int *state, double *stats,
-                              hipStream_t st);
+// state = {pivot, done, steps}; see cholesky.hip
+hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
+                              int *state, double *stats, hipStream_t st);
+hipError_t launch_chol_record(int r, const int *state, int *piv, hipStream_t st);
+hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st);
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
                              int R_max, const int *piv, double *U, double *V, hipStream_t st);
 
