@@ -269,3 +269,78 @@ def tei_cholesky(c, V3, M3, tol: float, R_max: int):
     steps taken while the residual trace exceeds tol.
     Returns (L [N_pair][R_B], pivots [R_B], residual diagonal)."""
     return pivoted_cholesky(tei_matrix_factored(c, V3, M3), tol, R_max)
+
+
+# --------------------------------------------------------------------------
+# Assembled lattice sums of the Newton kernel (Section 4.1) and the lattice
+# interaction energy (Section 4.2).  The lattice has L_l unit cells of n0
+# grid cells per direction (n_l = n0 L_l); the charge of unit cell j sits in
+# grid cell j n0 + n0 // 2 (the cell at the unit cell's centre).
+# --------------------------------------------------------------------------
+def lattice_sum(p: np.ndarray, n0: int, L: int) -> np.ndarray:
+    """Assembled vectors of one direction: A[q][i] = sum_j p_q[i - (j n0 + n0//2)],
+    i < n = n0 L, the kernel vector p [R][2n-1] indexed by lag (lag m at m + n - 1):
+    the sum over the lattice of the shifted and windowed kernel vectors."""
+    p = np.asarray(p, dtype=np.float64)
+    n = n0 * L
+    R = p.shape[0]
+    assert p.shape[1] == 2 * n - 1
+    A = np.zeros((R, n))
+    i = np.arange(n)
+    for j in range(L):
+        A += p[:, i - (j * n0 + n0 // 2) + n - 1]
+    return A
+
+
+def lattice_potential_direct(c, p3, h3, n0, L3, points) -> np.ndarray:
+    """The separable kernel summed over the lattice, point by point: for grid
+    points (i1, i2, i3), V = sum_j sum_q (c_q / (h1 h2 h3)^2) prod_l p^l_q[i_l - x_jl]
+    (x_j the charge cells), i.e. sum_j K(x_i - x_j) with K the kernel's
+    approximation of 1/|x| (its cell integrals divided by the cell volume)."""
+    c = np.asarray(c, dtype=np.float64)
+    w = c / (h3[0] * h3[1] * h3[2]) ** 2
+    out = []
+    for (i1, i2, i3) in points:
+        idx = (i1, i2, i3)
+        s = 0.0
+        for j1 in range(L3[0]):
+            for j2 in range(L3[1]):
+                for j3 in range(L3[2]):
+                    js = (j1, j2, j3)
+                    prod = w.copy()
+                    for l in range(3):
+                        n = n0 * L3[l]
+                        prod = prod * p3[l][:, idx[l] - (js[l] * n0 + n0 // 2) + n - 1]
+                    s += prod.sum()
+        out.append(s)
+    return np.array(out)
+
+
+def lattice_energy_direct(c, p3, h3, n0, L3, Z: float) -> float:
+    """E = Z^2/2 sum_{k != j} K(x_k - x_j) over the charge cells, pair by pair,
+    with the separable kernel K of lattice_potential_direct."""
+    c = np.asarray(c, dtype=np.float64)
+    w = c / (h3[0] * h3[1] * h3[2]) ** 2
+    pts = [(j1, j2, j3) for j1 in range(L3[0]) for j2 in range(L3[1]) for j3 in range(L3[2])]
+    E = 0.0
+    for a in pts:
+        for b in pts:
+            if a == b:
+                continue
+            prod = w.copy()
+            for l in range(3):
+                n = n0 * L3[l]
+                prod = prod * p3[l][:, (a[l] - b[l]) * n0 + n - 1]
+            E += prod.sum()
+    return 0.5 * Z * Z * E
+
+
+def coulomb_lattice_energy_exact(b: float, L3, Z: float) -> float:
+    """E = Z^2/2 sum_{k != j} 1/|x_k - x_j| for charges on the lattice b Z^3."""
+    g = np.stack(np.meshgrid(*[np.arange(Ll) for Ll in L3], indexing="ij"), -1).reshape(-1, 3)
+    E = 0.0
+    for a in range(len(g)):
+        d = np.sqrt(np.sum(((g - g[a]) * b) ** 2, axis=1))
+        d[a] = np.inf
+        E += np.sum(1.0 / d)
+    return 0.5 * Z * Z * E

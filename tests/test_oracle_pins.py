@@ -399,6 +399,78 @@ def test_factored_tei_matrix_with_fitted_modes_is_J(orc):
     assert len(piv) < B.shape[0]
 
 
+def test_lattice_sum_is_the_separable_lattice_loop(orc):
+    """The assembled vectors of each direction reproduce, through the rank-R
+    product, the kernel summed over every lattice point one by one (the sum
+    over a Cartesian lattice of products is the product of the sums)."""
+    n0, L3 = 5, (3, 4, 2)
+    b = 2.0
+    h = b / n0
+    R_N, lo, hu = 14, math.log(0.05), 0.45
+    p3, hs = [], []
+    for l in range(3):
+        n = n0 * L3[l]
+        t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+        p3.append(p)
+        hs.append(h)
+    c = a * h ** 3
+    A3 = [orc.lattice_sum(p3[l], n0, L3[l]) for l in range(3)]
+    rng = np.random.default_rng(2)
+    pts = [tuple(int(rng.integers(0, n0 * L3[l])) for l in range(3)) for _ in range(12)]
+    w = c / h ** 6
+    V = np.array([np.sum(w * A3[0][:, i] * A3[1][:, j] * A3[2][:, k]) for (i, j, k) in pts])
+    Vd = orc.lattice_potential_direct(c, p3, hs, n0, L3, pts)
+    assert np.max(np.abs(V - Vd) / np.abs(Vd)) <= 1e-13
+
+
+@pytest.mark.slow
+def test_lattice_potential_and_energy_against_coulomb_sums(orc):
+    """The lattice-summed kernel against the Coulomb sum sum_j 1/|x - x_j| at
+    grid points at least b/2 from every charge, and the pair energy
+    Z^2/2 sum_{k != j} K(x_k - x_j) against the exact Coulomb lattice energy
+    (O(h^4) here: the cell average of a harmonic function has no h^2 term),
+    with Richardson extrapolation."""
+    b, L3, Z = 2.0, (3, 3, 2), 1.0
+    Eex = orc.coulomb_lattice_energy_exact(b, L3, Z)
+    errs, Es = [], {}
+    for n0 in (4, 8, 16):
+        h = b / n0
+        R_N, lo, hu = accurate_rule(h)
+        p3 = []
+        for l in range(3):
+            t, a, c, p = orc.newton_kernel(n0 * L3[l], h, R_N, lo, hu)
+            p3.append(p)
+        c = a * h ** 3
+        E = orc.lattice_energy_direct(c, p3, [h, h, h], n0, L3, Z)
+        Es[n0] = E
+        errs.append(abs(E - Eex) / Eex)
+        if n0 == 8:
+            # potential at a few grid points away from the charges
+            grid = [(np.arange(n0 * Ll) + 0.5) * h for Ll in L3]
+            charges = np.stack(np.meshgrid(*[(np.arange(Ll) * n0 + n0 // 2 + 0.5) * h
+                                             for Ll in L3], indexing="ij"), -1).reshape(-1, 3)
+            rng = np.random.default_rng(4)
+            pts = []
+            while len(pts) < 4:
+                cand = tuple(int(rng.integers(0, n0 * Ll)) for Ll in L3)
+                x = np.array([grid[0][cand[0]], grid[1][cand[1]], grid[2][cand[2]]])
+                if np.sqrt(np.sum((charges - x) ** 2, axis=1)).min() >= b / 2:
+                    pts.append(cand)
+            Vd = orc.lattice_potential_direct(c, p3, [h, h, h], n0, L3, pts)
+            for (i, j, k), v in zip(pts, Vd):
+                x = np.array([grid[0][i], grid[1][j], grid[2][k]])
+                dist = np.sqrt(np.sum((charges - x) ** 2, axis=1))
+                assert abs(v - np.sum(1.0 / dist)) <= 5e-3 * np.sum(1.0 / dist)
+    # the cell average of the harmonic 1/|x| has no h^2 term away from the
+    # origin, so the pair energy converges at O(h^4)
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert errs[-1] < 1e-6
+    for r in ratios:
+        assert 12.0 < r < 20.0, (errs, ratios)
+    rich = (16 * Es[16] - Es[8]) / 15
+    assert abs(rich - Eex) / Eex < errs[-1] / 5, (errs, rich, Eex)
+
+
 def test_J_symmetric_psd_products(orc):
     """J = J^T, J_ii > 0 and J is positive semi-definite up to rounding (each
     T_k is positive definite, Schur products of PSD matrices are PSD and
