@@ -341,6 +341,38 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
                           int R_max, double *L_dev, int *pivots_host, int *R_out,
                           double *residual_out, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * tc_lattice_sum -- assembled canonical vectors of the Newton kernel summed
+ * over a rectangular lattice of charges (Section 4.1): L[l] unit cells of n0
+ * grid cells along direction l (n_l = n0 L[l] cells of width h_l), the charge
+ * of unit cell j in grid cell j n0 + n0/2.  Per direction and kernel term,
+ *   A^l[q][i] = sum_{j < L[l]} p^l[q][i - (j n0 + n0/2) + n_l - 1],  i < n_l,
+ * so that sum_q c_q/(h1 h2 h3)^2 prod_l A^l[q][i_l] is the lattice sum of the
+ * kernel's approximation of 1/|x| at grid cell (i1, i2, i3): rank R_N, the
+ * rank of the kernel.
+ *   n0 >= 1; L host [3], 1 <= L[l], n0 L[l] <= TC_MAX_N; R_N 1..TC_MAX_RN.
+ *   p_dev host array [3] of device [R_N][2 n_l - 1] (tc_newton_kernel with
+ *   n = n_l); A_dev host array [3] of device [R_N][n_l] outputs.
+ */
+tc_status tc_lattice_sum(int n0, const int *L, int R_N, const double *const *p_dev,
+                         double *const *A_dev, void *stream);
+
+/*
+ * tc_lattice_energy -- interaction energy of equal charges Z on the lattice
+ * of tc_lattice_sum (Section 4.2, eq. EnergyLattice): the kernel traced at
+ * the lattice lags and summed over all ordered pairs, minus the self terms,
+ *   E = Z^2/2 sum_q w_q (prod_l S^l_q - L1 L2 L3 prod_l p^l_q[0]),
+ *   S^l_q = sum_{|j| < L[l]} (L[l] - |j|) p^l_q[j n0],  w_q = c_q/(h1 h2 h3)^2,
+ * which is Z^2/2 sum_{k != j} K(x_k - x_j) for the kernel's approximation K
+ * of 1/|x| (O(L) work per term instead of O(L^6)).
+ *   c_dev [R_N] device (c_q = a_q h1 h2 h3); h host [3]; p_dev as for
+ *   tc_lattice_sum; E_host host output.  ws: 8 (R_N + 1) bytes of device
+ *   memory.  Synchronises `stream`.
+ */
+tc_status tc_lattice_energy(int n0, const int *L, int R_N, const double *c_dev, const double *h,
+                            const double *const *p_dev, double Z, double *E_host, void *ws,
+                            size_t ws_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *tc_status_string(tc_status s);
 

@@ -35,7 +35,7 @@ EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backwa
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
            "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
            "tc_density_fit_workspace_bytes", "tc_tei_cholesky",
-           "tc_tei_cholesky_workspace_bytes")
+           "tc_tei_cholesky_workspace_bytes", "tc_lattice_sum", "tc_lattice_energy")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -141,6 +141,13 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
                                       ctypes.c_int, vp, pi, pi, pd, vp, ctypes.c_size_t, vp]
         L.tc_tei_cholesky.restype = ctypes.c_int
+        L.tc_lattice_sum.argtypes = [ctypes.c_int, pi, ctypes.c_int, ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), vp]
+        L.tc_lattice_sum.restype = ctypes.c_int
+        L.tc_lattice_energy.argtypes = [ctypes.c_int, pi, ctypes.c_int, vp, pd,
+                                        ctypes.POINTER(vp), ctypes.c_double, pd, vp,
+                                        ctypes.c_size_t, vp]
+        L.tc_lattice_energy.restype = ctypes.c_int
         _lib = L
     return _lib
 

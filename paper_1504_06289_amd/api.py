@@ -171,6 +171,46 @@ def tei_cholesky(c: torch.Tensor, V3: Sequence[torch.Tensor], M3: Sequence[torch
     return Lout[:RB.value], piv[:RB.value].astype(np.int64), res.value
 
 
+def lattice_sum(p3: Sequence[torch.Tensor], n0: int, L: Sequence[int]):
+    """tc_lattice_sum: assembled vectors A^l [R_N][n0 L[l]] of the kernel
+    summed over the lattice (p3: the kernel vectors of the three directions,
+    each [R_N][2 n0 L[l] - 1])."""
+    R_N = p3[0].shape[0]
+    dev = p3[0].device
+    A3 = []
+    for l in range(3):
+        _dev_f64(p3[l], f"p[{l}]")
+        n = int(n0) * int(L[l])
+        if tuple(p3[l].shape) != (R_N, 2 * n - 1):
+            raise ValueError(f"p[{l}] must be [R_N][2 n0 L[{l}] - 1]")
+        A3.append(torch.empty((R_N, n), dtype=torch.float64, device=dev))
+    Li = (ctypes.c_int * 3)(*[int(x) for x in L])
+    pv = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in p3])
+    av = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in A3])
+    check(_lib.lib().tc_lattice_sum(int(n0), Li, R_N, pv, av, _stream(dev)), "tc_lattice_sum")
+    return A3
+
+
+def lattice_energy(c: torch.Tensor, p3: Sequence[torch.Tensor], h: Sequence[float], n0: int,
+                   L: Sequence[int], Z: float = 1.0) -> float:
+    """tc_lattice_energy: Z^2/2 sum_{k != j} K(x_k - x_j) over the lattice."""
+    _dev_f64(c, "c")
+    R_N = c.shape[0]
+    dev = c.device
+    for l in range(3):
+        _dev_f64(p3[l], f"p[{l}]")
+    Li = (ctypes.c_int * 3)(*[int(x) for x in L])
+    hd = (ctypes.c_double * 3)(*[float(x) for x in h])
+    pv = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in p3])
+    E = ctypes.c_double(0.0)
+    ws_bytes = 8 * (R_N + 1)
+    ws = _workspace(ws_bytes, dev)
+    check(_lib.lib().tc_lattice_energy(int(n0), Li, R_N, _ptr(c), hd, pv, float(Z),
+                                       ctypes.byref(E), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_lattice_energy")
+    return E.value
+
+
 def term_classes(p: torch.Tensor) -> np.ndarray:
     """tc_term_classes: per kernel term, B >= 0 (narrow, band B), -2 (smooth,
     low-rank Gram) or -1 (general), as the int8 FFT route treats it."""

@@ -953,6 +953,47 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
                             residual_out, st);
 }
 
+static bool lattice_ok(int n0, const int *L, int R_N, const double *const *p)
+{
+    if (n0 < 1 || !L || !p || R_N < 1 || R_N > TC_MAX_RN)
+        return false;
+    for (int l = 0; l < 3; ++l)
+        if (L[l] < 1 || (long)n0 * L[l] > TC_MAX_N || !p[l])
+            return false;
+    return true;
+}
+
+tc_status tc_lattice_sum(int n0, const int *L, int R_N, const double *const *p_dev,
+                         double *const *A_dev, void *stream)
+{
+    if (!lattice_ok(n0, L, R_N, p_dev) || !A_dev || !A_dev[0] || !A_dev[1] || !A_dev[2])
+        return TC_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    TRYK("lattice_sum", launch_lattice_sum(n0, L, R_N, p_dev, A_dev, st));
+    return TC_OK;
+}
+
+tc_status tc_lattice_energy(int n0, const int *L, int R_N, const double *c_dev, const double *h,
+                            const double *const *p_dev, double Z, double *E_host, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    if (!lattice_ok(n0, L, R_N, p_dev) || !c_dev || !h || !E_host || !std::isfinite(Z))
+        return TC_ERR_INVALID_ARG;
+    for (int l = 0; l < 3; ++l)
+        if (!(h[l] > 0.0) || !std::isfinite(h[l]))
+            return TC_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < sizeof(double) * ((size_t)R_N + 1))
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double *term = (double *)ws;
+    double *E = term + R_N;
+    TRYK("lattice_energy", launch_lattice_energy(n0, L, R_N, c_dev, h, p_dev, Z, term, E, st));
+    if (hipMemcpyAsync(E_host, E, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return TC_ERR_HIP;
+    return TC_OK;
+}
+
 size_t tc_coulomb_workspace_bytes(const tc_density *prob, tc_precision prec)
 {
     if (!prob || !prec_known(prec))

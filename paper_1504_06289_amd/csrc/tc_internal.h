@@ -162,6 +162,14 @@ hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st);
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
                              int R_max, const int *piv, double *U, double *V, hipStream_t st);
 
+// ---- lattice sums and lattice energy (lattice.hip) -------------------------
+hipError_t launch_lattice_sum(int n0, const int *L, int R_N, const double *const *p,
+                              double *const *A, hipStream_t st);
+// term: scratch [R_N]; E: device scalar
+hipError_t launch_lattice_energy(int n0, const int *L, int R_N, const double *c,
+                                 const double *h, const double *const *p, double Z,
+                                 double *term, double *E, hipStream_t st);
+
 // ---- term classes and smooth terms (lowrank.hip) ---------------------------
 constexpr int kBandMax = 16;   // widest band of a narrow term
 constexpr int kPolyRank = 32;  // polynomial degree < kPolyRank for a smooth term

@@ -265,3 +265,27 @@ def test_density_fit_and_tei_cholesky_reject(L):
     assert L.tc_tei_cholesky(10, 4, 300, v, vp3, vp3, 1e-6, 5, v, None, ctypes.byref(R), None,
                              None, 0, None) == _lib.TC_ERR_INVALID_ARG
 
+
+
+def test_lattice_rejects(L):
+    v = ctypes.c_void_p(0x1000)
+    vp3 = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    nul3 = (ctypes.c_void_p * 3)(0x1000, None, 0x1000)
+    Lok = (ctypes.c_int * 3)(3, 4, 2)
+    Lbad = (ctypes.c_int * 3)(3, 0, 2)
+    Lbig = (ctypes.c_int * 3)(3, 100000, 2)
+    for n0, Ls, R_N, p, A in [(0, Lok, 5, vp3, vp3), (5, Lbad, 5, vp3, vp3),
+                              (5, Lbig, 5, vp3, vp3), (5, Lok, 0, vp3, vp3),
+                              (5, Lok, 5, nul3, vp3), (5, Lok, 5, vp3, nul3)]:
+        assert L.tc_lattice_sum(n0, Ls, R_N, p, A, None) == _lib.TC_ERR_INVALID_ARG
+    h = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    hbad = (ctypes.c_double * 3)(0.1, 0.0, 0.1)
+    E = ctypes.c_double(0.0)
+    assert L.tc_lattice_energy(5, Lok, 5, v, h, vp3, 1.0, ctypes.byref(E), v, 47,
+                               None) == _lib.TC_ERR_WORKSPACE
+    assert L.tc_lattice_energy(5, Lok, 5, v, hbad, vp3, 1.0, ctypes.byref(E), v, 48,
+                               None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_lattice_energy(5, Lok, 5, None, h, vp3, 1.0, ctypes.byref(E), v, 48,
+                               None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_lattice_energy(5, Lok, 5, v, h, nul3, 1.0, ctypes.byref(E), v, 48,
+                               None) == _lib.TC_ERR_INVALID_ARG

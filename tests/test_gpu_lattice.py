@@ -1,0 +1,108 @@
+"""Parity of the assembled lattice sums (tc_lattice_sum, Section 4.1) and the
+lattice pair energy (tc_lattice_energy, Section 4.2) with the oracle, through
+the C ABI, binary64.
+
+Bounds: every A^l[q][i] is a sum of L_l kernel values in the oracle's order
+(bitwise equal is expected; the test allows 4 L u |A|, u = 2^-53).  The energy
+sums O(L) weighted lags per direction where the oracle loops over all ordered
+pairs, so the two round differently: the test asserts |dE| <= 1e-13 times the
+sum of the absolute pair terms (the condition scale of the pair sum)."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(1, (1, 1, 1), 4), (5, (3, 4, 2), 14), (8, (3, 3, 2), 20), (6, (7, 1, 5), 11),
+         (16, (9, 4, 3), 37), (3, (60, 50, 40), 25)]
+
+
+def kernel3(orc, n0, L3, h, R_N):
+    lo, hu = np.log(0.05), 0.45
+    p3 = []
+    for l in range(3):
+        t, a, c, p = orc.newton_kernel(n0 * L3[l], h, R_N, lo, hu)
+        p3.append(p)
+    return a * h ** 3, p3
+
+
+def energy_scale(c, p3, h, n0, L3):
+    """sum over ordered pairs k != j and terms q of |w_q prod_l p^l_q[lag_l]|."""
+    w = np.abs(c) / h ** 6
+    S, z = [], []
+    for l in range(3):
+        n = n0 * L3[l]
+        j = np.arange(-(L3[l] - 1), L3[l])
+        S.append(((L3[l] - np.abs(j))[None, :] * np.abs(p3[l][:, j * n0 + n - 1])).sum(1))
+        z.append(np.abs(p3[l][:, n - 1]))
+    return float(np.sum(w * (S[0] * S[1] * S[2] - L3[0] * L3[1] * L3[2] * z[0] * z[1] * z[2])))
+
+
+@pytest.mark.parametrize("n0,L3,R_N", CASES)
+def test_lattice_sum(tc, orc, n0, L3, R_N):
+    say(f"lattice_sum n0={n0} L={L3} R_N={R_N}")
+    h = 2.0 / n0
+    c, p3 = kernel3(orc, n0, L3, h, R_N)
+    A3 = tc.lattice_sum([dev(p) for p in p3], n0, L3)
+    for l in range(3):
+        Ag = host(A3[l])
+        Ar = orc.lattice_sum(p3[l], n0, L3[l])
+        assert Ag.shape == Ar.shape
+        tol = 4 * L3[l] * 2.0 ** -53 * np.abs(p3[l]).max() * L3[l]
+        err = np.max(np.abs(Ag - Ar))
+        say(f"   direction {l}: max |dA| = {err:.2e} (bitwise {np.array_equal(Ag, Ar)})")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("n0,L3,R_N", [c for c in CASES if np.prod(c[1]) <= 300])
+@pytest.mark.parametrize("Z", [1.0, -2.5])
+def test_lattice_energy(tc, orc, n0, L3, R_N, Z):
+    say(f"lattice_energy n0={n0} L={L3} R_N={R_N} Z={Z}")
+    h = 2.0 / n0
+    c, p3 = kernel3(orc, n0, L3, h, R_N)
+    E = tc.lattice_energy(dev(c), [dev(p) for p in p3], [h, h, h], n0, L3, Z)
+    Er = orc.lattice_energy_direct(c, p3, [h, h, h], n0, L3, Z)
+    sc = 0.5 * Z * Z * energy_scale(c, p3, h, n0, L3)
+    say(f"   E = {E:.15e}  oracle {Er:.15e}  |dE|/scale = {abs(E - Er) / max(sc, 1e-300):.2e}")
+    if np.prod(L3) == 1:
+        assert E == 0.0 and Er == 0.0
+    else:
+        assert abs(E - Er) <= 1e-13 * sc
+
+
+def test_lattice_energy_large_against_weighted_lags(tc, orc):
+    """A lattice too large for the pair loop (60 x 50 x 40 charges): the energy
+    against the oracle's lattice sums traced at the charge cells, which is the
+    same quantity written through A (sum_j prod_l A^l[q][x_j] over the charges,
+    minus the self terms)."""
+    n0, L3, R_N = 3, (60, 50, 40), 25
+    h = 2.0 / n0
+    c, p3 = kernel3(orc, n0, L3, h, R_N)
+    E = tc.lattice_energy(dev(c), [dev(p) for p in p3], [h, h, h], n0, L3, 1.0)
+    w = c / h ** 6
+    T = np.ones(R_N)
+    for l in range(3):
+        A = orc.lattice_sum(p3[l], n0, L3[l])
+        T = T * A[:, np.arange(L3[l]) * n0 + n0 // 2].sum(1)
+    z = np.prod([p3[l][:, n0 * L3[l] - 1] for l in range(3)], axis=0)
+    Er = 0.5 * np.sum(w * (T - np.prod(L3) * z))
+    say(f"   E = {E:.15e}  via A {Er:.15e}")
+    assert abs(E - Er) <= 1e-12 * abs(Er)
+
+
+def test_lattice_from_device_kernel(tc, orc):
+    """tc_newton_kernel's vectors fed to tc_lattice_sum agree with the oracle's
+    chain (kernel vectors within 1e-12 relative, summed over 4 cells)."""
+    n0, L3, R_N = 8, (4, 3, 2), 18
+    h = 2.0 / n0
+    lo, hu = np.log(0.05), 0.45
+    pd = []
+    for l in range(3):
+        t, cc, p = tc.newton_kernel(n0 * L3[l], h, R_N, lo, hu)
+        pd.append(p)
+    A3 = tc.lattice_sum(pd, n0, L3)
+    _, p3 = kernel3(orc, n0, L3, h, R_N)
+    for l in range(3):
+        Ar = orc.lattice_sum(p3[l], n0, L3[l])
+        assert np.max(np.abs(host(A3[l]) - Ar)) <= 1e-12 * np.abs(Ar).max()
