@@ -444,6 +444,34 @@ def extra_rows(tc, wl, torch, dev, args):
                                "fit_ms": round(1e3 * (t1 - t0), 2),
                                "fitted_grams_ms": round(1e3 * (t2 - t1), 2),
                                "cholesky_ms": round(1e3 * (t3 - t2), 2)}
+    # lattices of hydrogen atoms (Z = 1, spacing 2 bohr): the interaction
+    # energy of the 256^3 lattice on the n = 128 L grid, and the assembled
+    # lattice sum of the 128^3 lattice on a 34304-cell grid, each with the
+    # generation of its kernel vectors on the device
+    import math as _m
+    L, n0 = 256, 128
+    h = 2.0 / n0
+    lo, hu = _m.log(1e-14), 0.25
+    R_N = int(_m.ceil((_m.log(200.0) - lo) / hu)) + 1
+
+    def energy():
+        t, c, p = tc.newton_kernel(n0 * L, h, R_N, lo, hu, device=dev)
+        return tc.lattice_energy(torch.from_numpy(c).to(dev), [p, p, p], [h, h, h], n0,
+                                 (L, L, L), 1.0)
+    mse = timed(energy, 5, 1, torch)
+    rows["lattice_energy_L256"] = {"ms": round(mse, 3), "E": energy(), "R_N": R_N,
+                                   "n": n0 * L}
+    L, n0 = 128, 268
+    h = 2.0 / n0
+    R_N = int(_m.ceil((_m.log(2e4 / h) - lo) / hu)) + 1
+    t, c, p = tc.newton_kernel(n0 * L, h, R_N, lo, hu, device=dev)
+    msk = timed(lambda: tc.newton_kernel(n0 * L, h, R_N, lo, hu, device=dev), 5, 1, torch)
+    mss = timed(lambda: tc.lattice_sum([p, p, p], n0, (L, L, L)), 5, 1, torch)
+    n = n0 * L
+    rows["lattice_sum_L128"] = {"kernel_ms": round(msk, 3), "sum_ms": round(mss, 3),
+                                "R_N": R_N, "n": n,
+                                "sum_GBps_algorithmic": round(
+                                    3 * 8.0 * R_N * (3 * n - 1) / (mss * 1e-3) / 1e9, 1)}
     return rows
 
 

@@ -343,9 +343,11 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
 
 /*
  * tc_lattice_sum -- assembled canonical vectors of the Newton kernel summed
- * over a rectangular lattice of charges (Section 4.1): L[l] unit cells of n0
- * grid cells along direction l (n_l = n0 L[l] cells of width h_l), the charge
- * of unit cell j in grid cell j n0 + n0/2.  Per direction and kernel term,
+ * over a rectangular lattice of charges (Section 5.1, eq. CoulombLatTensCan):
+ * L[l] unit cells of n0 grid cells along direction l (n_l = n0 L[l] cells of
+ * width h_l), the charge of unit cell j in grid cell j n0 + n0/2 (the paper's
+ * symmetric lattice, shifted so that indices start at 0).  Per direction and
+ * kernel term,
  *   A^l[q][i] = sum_{j < L[l]} p^l[q][i - (j n0 + n0/2) + n_l - 1],  i < n_l,
  * so that sum_q c_q/(h1 h2 h3)^2 prod_l A^l[q][i_l] is the lattice sum of the
  * kernel's approximation of 1/|x| at grid cell (i1, i2, i3): rank R_N, the
@@ -359,7 +361,7 @@ tc_status tc_lattice_sum(int n0, const int *L, int R_N, const double *const *p_d
 
 /*
  * tc_lattice_energy -- interaction energy of equal charges Z on the lattice
- * of tc_lattice_sum (Section 4.2, eq. EnergyLattice): the kernel traced at
+ * of tc_lattice_sum (Section 5.2, eq. EnergyLattice): the kernel traced at
  * the lattice lags and summed over all ordered pairs, minus the self terms,
  *   E = Z^2/2 sum_q w_q (prod_l S^l_q - L1 L2 L3 prod_l p^l_q[0]),
  *   S^l_q = sum_{|j| < L[l]} (L[l] - |j|) p^l_q[j n0],  w_q = c_q/(h1 h2 h3)^2,

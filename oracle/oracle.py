@@ -272,9 +272,9 @@ def tei_cholesky(c, V3, M3, tol: float, R_max: int):
 
 
 # --------------------------------------------------------------------------
-# Assembled lattice sums of the Newton kernel (Section 4.1) and the lattice
-# interaction energy (Section 4.2).  The lattice has L_l unit cells of n0
-# grid cells per direction (n_l = n0 L_l); the charge of unit cell j sits in
+# Assembled lattice sums of the Newton kernel (Section 5.1, eq. CoulombLatTensCan)
+# and the lattice interaction energy (Section 5.2, eq. EnergyLattice).  The
+# lattice has L_l unit cells of n0 grid cells per direction (n_l = n0 L_l); the charge of unit cell j sits in
 # grid cell j n0 + n0 // 2 (the cell at the unit cell's centre).
 # --------------------------------------------------------------------------
 def lattice_sum(p: np.ndarray, n0: int, L: int) -> np.ndarray:
@@ -332,6 +332,22 @@ def lattice_energy_direct(c, p3, h3, n0, L3, Z: float) -> float:
                 n = n0 * L3[l]
                 prod = prod * p3[l][:, (a[l] - b[l]) * n0 + n - 1]
             E += prod.sum()
+    return 0.5 * Z * Z * E
+
+
+def coulomb_lattice_energy_lags(b: float, L3, Z: float) -> float:
+    """The same energy grouped by lattice lag: the lag d occurs in
+    prod_l (L_l - |d_l|) ordered pairs, so
+    E = Z^2/2 sum_{d != 0} prod_l (L_l - |d_l|) / (b |d|), O(L^3) terms."""
+    j = [np.arange(-(Ll - 1), Ll) for Ll in L3]
+    m = [(Ll - np.abs(jl)).astype(np.float64) for Ll, jl in zip(L3, j)]
+    E = 0.0
+    for a in range(len(j[0])):
+        d2 = (j[0][a] ** 2 + j[1][:, None] ** 2 + j[2][None, :] ** 2).astype(np.float64)
+        mult = m[0][a] * m[1][:, None] * m[2][None, :]
+        if j[0][a] == 0:
+            d2[L3[1] - 1, L3[2] - 1] = np.inf   # the zero lag: no pair
+        E += np.sum(mult / (b * np.sqrt(d2)))
     return 0.5 * Z * Z * E
 
 

@@ -1,5 +1,6 @@
-// Assembled lattice sums of the Newton kernel (Section 4.1) and the pair
-// energy of a charge lattice (Section 4.2), binary64.
+// Assembled lattice sums of the Newton kernel (Section 5.1, eq. CoulombLatTensCan)
+// and the pair energy of a charge lattice (Section 5.2, eq. EnergyLattice),
+// binary64.
 //
 // The lattice has L_l unit cells of n0 grid cells along direction l
 // (n_l = n0 L_l); the charge of unit cell j sits in grid cell j n0 + n0/2.

@@ -7,6 +7,7 @@ a plausible mistake anywhere in the oracle (a dropped term, a wrong sign or
 index, a transposed operand, a missing h^3) fails at least one of them.
 """
 import math
+import os
 
 import mpmath as mp
 import numpy as np
@@ -584,3 +585,46 @@ def test_grid_reproduces_printed_mesh_sizes():
         assert math.isclose(h, 40.0 / n, rel_tol=1e-12)
         assert x[0] == pytest.approx(-20.0 + h / 2, abs=1e-12)
         assert float(f"{h:.{digits}g}") == printed
+
+def _lattice_table():
+    path = os.path.join(os.path.dirname(__file__), "golden", "lattice_energy_table.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            L, E, digits, reading = line.split()
+            rows.append((int(L), float(E), int(digits), reading))
+    return rows
+
+
+def printed_value_holds(E, printed, digits, reading):
+    """E agrees with a value printed to `digits` significant digits, to within
+    one unit of the last printed digit."""
+    if reading != "digit":
+        raise ValueError(reading)
+    ulp = 10.0 ** (math.floor(math.log10(abs(printed))) - digits + 1)
+    return abs(E - printed) < ulp
+
+
+@pytest.mark.slow
+def test_exact_lattice_energy_against_printed_table(orc):
+    """The exact Coulomb energy 1/2 sum_{k != j} 1/|x_k - x_j| of the 24^3
+    hydrogen lattice of Section 5.2 (Z = 1, spacing 2 bohr), pair by pair,
+    against the energy printed there (fixture
+    tests/golden/lattice_energy_table.txt; the tensor values printed agree
+    with direct summation to 2e-8).  The larger lattices are checked on the
+    GPU path, whose energy is O(L) per term."""
+    rows = {r[0]: r for r in _lattice_table()}
+    for L in (24,):
+        _, printed, digits, reading = rows[L]
+        E = orc.coulomb_lattice_energy_exact(2.0, (L, L, L), 1.0)
+        assert printed_value_holds(E, printed, digits, reading), (L, E, printed)
+
+
+def test_lattice_energy_by_lags_is_the_pair_sum(orc):
+    """Grouping the pairs of a lattice by lag changes only the order of the
+    sum: brute force over all ordered pairs on small rectangular lattices."""
+    for b, L3, Z in [(2.0, (1, 1, 1), 1.0), (1.5, (2, 3, 4), 2.0), (0.7, (5, 1, 3), -1.0),
+                     (2.0, (6, 7, 5), 1.0)]:
+        El = orc.coulomb_lattice_energy_lags(b, L3, Z)
+        Ep = orc.coulomb_lattice_energy_exact(b, L3, Z)
+        assert abs(El - Ep) <= 1e-13 * max(abs(Ep), 1.0), (L3, El, Ep)
