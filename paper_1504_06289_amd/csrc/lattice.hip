@@ -18,7 +18,9 @@
 //                   difference of products is taken in the telescoped form
 //                   s_1 S_2 S_3 + a_1 s_2 S_3 + a_1 a_2 s_3, which holds no
 //                   cancellation of the (largest) self term.
-// Sums run in a fixed order (bitwise reproducible).
+// Sums run in a fixed order (bitwise reproducible).  The lattice sum has two
+// forms: one thread per output summing its L terms (O(n L) per term), and
+// running sums over the stride-n0 subsequences (O(n) per term).
 #include "tc_internal.h"
 
 namespace tc {
@@ -26,6 +28,9 @@ namespace tc {
 namespace {
 
 constexpr int LT = 256;
+// (r, q) pairs from which the running-sum form is used (fewer: one thread per
+// output, L terms each, for parallelism)
+constexpr long kLatticeScanThreads = 2048;
 
 // one thread per (i, q): the L terms in increasing j; blockIdx.z = direction
 __global__ __launch_bounds__(LT) void lattice_sum_kernel(const double *__restrict__ p0,
@@ -48,6 +53,44 @@ __global__ __launch_bounds__(LT) void lattice_sum_kernel(const double *__restric
     for (int j = 0; j < L; ++j)
         s += p[i - (j * n0 + n0 / 2)];
     A[i] = s;
+}
+
+// The same sums in O(n_l) per term: with i = r + k n0 (r < n0, k < L) and
+// s_r[m] = p_q[r - n0/2 + m n0], A[i] is the sum of s_r over the window
+// m = k-L+1..k, and every such window holds m = 0, so
+//   A[r + k n0] = SL(k-L+1) + PR(k),  SL(a) = sum_{a <= m < 0} s_r[m],
+//                                      PR(k) = sum_{0 <= m <= k} s_r[m],
+// two running sums without cancellation.  One thread per (r, q): a
+// descending pass writes SL into A, an ascending pass adds PR.
+__global__ __launch_bounds__(LT) void lattice_scan_kernel(const double *__restrict__ p0,
+                                                          const double *__restrict__ p1,
+                                                          const double *__restrict__ p2,
+                                                          double *__restrict__ A0,
+                                                          double *__restrict__ A1,
+                                                          double *__restrict__ A2, int n0,
+                                                          int L0, int L1, int L2)
+{
+    const int l = blockIdx.z, q = blockIdx.y;
+    const int L = l == 0 ? L0 : (l == 1 ? L1 : L2);
+    const int n = n0 * L;
+    const int r = blockIdx.x * LT + threadIdx.x;
+    if (r >= n0)
+        return;
+    // s[m] at s + m n0, m in [-(L-1), L-1]
+    const double *s = (l == 0 ? p0 : (l == 1 ? p1 : p2)) + (long)q * (2L * n - 1) + (n - 1) +
+                      (r - n0 / 2);
+    double *A = (l == 0 ? A0 : (l == 1 ? A1 : A2)) + (long)q * n + r;
+    double acc = 0.0;
+    A[(long)(L - 1) * n0] = 0.0;
+    for (int k = L - 2; k >= 0; --k) {
+        acc += s[(long)(k - L + 1) * n0];
+        A[(long)k * n0] = acc;
+    }
+    acc = 0.0;
+    for (int k = 0; k < L; ++k) {
+        acc += s[(long)k * n0];
+        A[(long)k * n0] += acc;
+    }
 }
 
 // one workgroup per q: term[q] = w_q (prod_l S^l_q - L1 L2 L3 prod_l p^l_q[0]),
@@ -105,6 +148,13 @@ __global__ void lattice_energy_sum_kernel(const double *__restrict__ term, int R
 hipError_t launch_lattice_sum(int n0, const int *L, int R_N, const double *const *p,
                               double *const *A, hipStream_t st)
 {
+    if ((long)n0 * R_N >= kLatticeScanThreads) {
+        // enough (r, q) pairs to fill the chip: the O(n) running sums
+        dim3 grid((n0 + LT - 1) / LT, R_N, 3);
+        hipLaunchKernelGGL(lattice_scan_kernel, grid, dim3(LT), 0, st, p[0], p[1], p[2], A[0],
+                           A[1], A[2], n0, L[0], L[1], L[2]);
+        return hipGetLastError();
+    }
     int nmax = 0;
     for (int l = 0; l < 3; ++l)
         nmax = n0 * L[l] > nmax ? n0 * L[l] : nmax;

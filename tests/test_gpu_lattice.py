@@ -2,8 +2,10 @@
 lattice pair energy (tc_lattice_energy, Section 5.2) with the oracle, through
 the C ABI, binary64.
 
-Bounds: every A^l[q][i] is a sum of L_l kernel values in the oracle's order
-(bitwise equal is expected; the test allows 4 L u |A|, u = 2^-53).  The energy
+Bounds: every A^l[q][i] is a sum of L_l kernel values, in the oracle's order
+when n0 R_N is small (bitwise equal is expected) and as a suffix plus a prefix
+running sum otherwise (error below (L_l + 1) u sum|p|); the test allows
+4 L_l^2 u max|p|, u = 2^-53.  The energy
 sums O(L) weighted lags per direction where the oracle loops over all ordered
 pairs, so the two round differently: the test asserts |dE| <= 1e-13 times the
 sum of the absolute pair terms (the condition scale of the pair sum)."""
@@ -15,7 +17,9 @@ from tests.gpu_common import dev, host, say
 pytestmark = pytest.mark.gpu
 
 CASES = [(1, (1, 1, 1), 4), (5, (3, 4, 2), 14), (8, (3, 3, 2), 20), (6, (7, 1, 5), 11),
-         (16, (9, 4, 3), 37), (3, (60, 50, 40), 25)]
+         (16, (9, 4, 3), 37), (3, (60, 50, 40), 25),
+         # n0 R_N >= 2048: the running-sum form
+         (64, (40, 17, 33), 40), (128, (24, 2, 1), 20), (37, (5, 70, 3), 60)]
 
 
 def kernel3(orc, n0, L3, h, R_N):
