@@ -360,3 +360,53 @@ def coulomb_lattice_energy_exact(b: float, L3, Z: float) -> float:
         d[a] = np.inf
         E += np.sum(1.0 / d)
     return 0.5 * Z * Z * E
+
+
+# --------------------------------------------------------------------------
+# Nuclear potential operator (Section 3.3): the master kernel shifted to each
+# nucleus, summed with the charges, and its Galerkin matrix in the basis of
+# rank-1 products.  Nuclei sit at grid-cell centres (the windowing shifts by
+# whole cells): pos[alpha][l] is the cell of nucleus alpha along mode l.
+# --------------------------------------------------------------------------
+def nuclear(c, p3, h3, U3, Z, pos) -> np.ndarray:
+    """V[k][m] = -sum_alpha Z_alpha sum_q (c_q / (h1 h2 h3))
+                 prod_l sum_a U^l[k][a] U^l[m][a] p^l_q[a - pos_alpha,l],
+    i.e. vol sum_x g_k(x) g_m(x) V_c(x) over the grid cells x, with
+    V_c(x) = -sum_alpha Z_alpha K(x - x_alpha) and K the kernel's
+    approximation of 1/|x| (c_q/(h1 h2 h3)^2 prod_l p^l_q)."""
+    c = _f64(c)
+    U3 = [_f64(u) for u in U3]
+    p3 = [_f64(p) for p in p3]
+    vol = float(h3[0] * h3[1] * h3[2])
+    R_f = U3[0].shape[0]
+    V = np.zeros((R_f, R_f))
+    for alpha in range(len(Z)):
+        for q in range(c.shape[0]):
+            prod = np.ones((R_f, R_f))
+            for l in range(3):
+                n = U3[l].shape[1]
+                s = p3[l][q, np.arange(n) - int(pos[alpha][l]) + n - 1]
+                prod = prod * ((U3[l] * s[None, :]) @ U3[l].T)
+            V -= Z[alpha] * c[q] / vol * prod
+    return V
+
+
+def nuclear_bruteforce(c, p3, h3, U3, Z, pos) -> np.ndarray:
+    """The same matrix on the full 3D grid (tiny grids only): the potential
+    V_c on every cell, then vol sum_x g_k(x) g_m(x) V_c(x)."""
+    c = _f64(c)
+    n = [u.shape[1] for u in U3]
+    vol = float(h3[0] * h3[1] * h3[2])
+    Vc = np.zeros(n)
+    for alpha in range(len(Z)):
+        for q in range(c.shape[0]):
+            f = [p3[l][q, np.arange(n[l]) - int(pos[alpha][l]) + n[l] - 1] for l in range(3)]
+            Vc -= Z[alpha] * c[q] / vol ** 2 * np.einsum("a,b,c->abc", f[0], f[1], f[2])
+    R_f = U3[0].shape[0]
+    V = np.zeros((R_f, R_f))
+    for k in range(R_f):
+        gk = np.einsum("a,b,c->abc", U3[0][k], U3[1][k], U3[2][k])
+        for m in range(R_f):
+            gm = np.einsum("a,b,c->abc", U3[0][m], U3[1][m], U3[2][m])
+            V[k, m] = vol * np.sum(gk * gm * Vc)
+    return V

@@ -628,3 +628,67 @@ def test_lattice_energy_by_lags_is_the_pair_sum(orc):
         El = orc.coulomb_lattice_energy_lags(b, L3, Z)
         Ep = orc.coulomb_lattice_energy_exact(b, L3, Z)
         assert abs(El - Ep) <= 1e-13 * max(abs(Ep), 1.0), (L3, El, Ep)
+
+
+def test_nuclear_matrix_is_the_grid_sum(orc):
+    """The separable nuclear-potential matrix against the potential formed on
+    the whole 3D grid and integrated cell by cell (tiny grids, unequal modes,
+    nuclei on the boundary cells too)."""
+    rng = np.random.default_rng(5)
+    n3, b = (9, 7, 8), 3.0
+    h3 = [2 * b / nl for nl in n3]
+    R_N = 6
+    p3 = []
+    for l in range(3):
+        t, a, c, p = orc.newton_kernel(n3[l], h3[l], R_N, -2.0, 0.6)
+        p3.append(p)
+    c = a * h3[0] * h3[1] * h3[2]
+    U3 = [rng.standard_normal((5, nl)) for nl in n3]
+    Z = np.array([1.0, 8.0, 2.5])
+    pos = [(0, 6, 3), (4, 3, 7), (8, 0, 0)]
+    V = orc.nuclear(c, p3, h3, U3, Z, pos)
+    Vb = orc.nuclear_bruteforce(c, p3, h3, U3, Z, pos)
+    assert np.max(np.abs(V - Vb)) <= 1e-12 * np.max(np.abs(Vb))
+    assert np.max(np.abs(V - V.T)) <= 1e-14 * np.max(np.abs(V))
+
+
+def _nuclear_ss(a1, A1, a2, A2, C):
+    """Nuclear attraction of two unnormalised s Gaussians with a unit charge
+    at C: -(2 pi / p) exp(-a1 a2/p |A1 - A2|^2) F0(p |P - C|^2)."""
+    with mp.workdps(40):
+        a1, a2 = mp.mpf(a1), mp.mpf(a2)
+        p = a1 + a2
+        AB2 = sum((mp.mpf(x) - mp.mpf(y)) ** 2 for x, y in zip(A1, A2))
+        P = [(a1 * mp.mpf(x) + a2 * mp.mpf(y)) / p for x, y in zip(A1, A2)]
+        T = p * sum((Pi - mp.mpf(ci)) ** 2 for Pi, ci in zip(P, C))
+        F0 = mp.mpf(1) if T == 0 else mp.sqrt(mp.pi / T) * mp.erf(mp.sqrt(T)) / 2
+        return -2 * mp.pi / p * mp.exp(-a1 * a2 / p * AB2) * F0
+
+
+@pytest.mark.slow
+def test_nuclear_matrix_boys_closed_form_h2(orc):
+    """s Gaussians against two nuclei at cell centres: the matrix converges to
+    the closed-form nuclear attraction integrals at O(h^2) (the cell average of
+    1/|x| is integrated exactly, the smooth factor by the midpoint rule)."""
+    b = 10.0
+    alphas = np.array([0.6, 1.3, 0.8])
+    centres = np.array([[0.3, -0.4, 0.1], [-1.1, 0.7, 0.5], [1.4, 1.0, -0.8]])
+    Z = np.array([1.0, 3.0])
+    targets = np.array([[0.37, -0.52, 0.21], [-0.8, 0.6, -0.3]])
+    errs = []
+    for n in (64, 128, 256, 512):
+        h = 2 * b / n
+        R_N, lo, hu = accurate_rule(h)
+        t, a, c, p = orc.newton_kernel(n, h, R_N, lo, hu)
+        U, _ = wl.s_gaussians(n, b, 3, alphas=alphas, centres=centres)
+        pos = [tuple(int(np.floor((x + b) / h)) for x in tg) for tg in targets]
+        C = [[-b + (i + 0.5) * h for i in ps] for ps in pos]
+        ref = np.array([[float(sum(Z[g] * _nuclear_ss(alphas[i], centres[i], alphas[j],
+                                                       centres[j], C[g]) for g in range(2)))
+                         for j in range(3)] for i in range(3)])
+        V = orc.nuclear(c, [p, p, p], [h, h, h], U, Z, pos)
+        errs.append(np.max(np.abs(V - ref) / np.abs(ref)))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert errs[-1] < 2e-4, errs
+    for r in ratios[1:]:
+        assert 3.5 < r < 4.6, (errs, ratios)
