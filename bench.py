@@ -444,6 +444,27 @@ def extra_rows(tc, wl, torch, dev, args):
                                "fit_ms": round(1e3 * (t1 - t0), 2),
                                "fitted_grams_ms": round(1e3 * (t2 - t1), 2),
                                "cholesky_ms": round(1e3 * (t3 - t2), 2)}
+    # nuclear potential matrix of the 4096-cell products: three nuclei (a
+    # water-like geometry in bohr) on the grid of the functions
+    geom = np.array([[0.0, 0.0, 0.0], [1.43, 1.11, 0.0], [-1.43, 1.11, 0.0]])
+    Zn = np.array([8.0, 1.0, 1.0])
+    posn = [[int((x + w3.b) / w3.h[l]) for l, x in enumerate(g)] for g in geom]
+    msn = timed(lambda: tc.nuclear(cd, [p, p, p], U3, w3.h, Zn, posn), 3, 1, torch)
+    tc.profile_enable(True)
+    tc.profile_read()
+    tc.nuclear(cd, [p, p, p], U3, w3.h, Zn, posn)
+    prof = tc.profile_read()
+    tc.profile_enable(False)
+    dg = prof.get("diag_gram_f64")
+    Tn = len(Zn) * w3.R_N
+    fl = 3 * Tn * 2.0 * n3 * w3.R_f * (w3.R_f + 1) / 2   # upper triangles
+    row = {"ms": round(msn, 3), "nuclei": len(Zn), "terms": Tn}
+    if dg:
+        ms_dg = dg[0] / dg[1]
+        row["diag_gram_f64"] = {"kernel_ms": round(ms_dg, 4),
+                                "TFLOP/s": round(fl / 3 / (ms_dg * 1e-3) / 1e12, 2),
+                                "frac": round(fl / 3 / (ms_dg * 1e-3) / 1e12 / PEAK["fp64"], 4)}
+    rows["nuclear_c3_h2o"] = row
     # lattices of hydrogen atoms (Z = 1, spacing 2 bohr): the interaction
     # energy of the 256^3 lattice on the n = 128 L grid, and the assembled
     # lattice sum of the 128^3 lattice on a 34304-cell grid, each with the

@@ -118,6 +118,23 @@ typedef struct {
     double *G_saved;     /* [3][R_N][R_f][R_f] device output, or NULL        */
 } tc_instance;
 
+/* Nuclei against a set of product functions, for tc_nuclear (Section 3.3,
+ * the nuclear potential operator of the core Hamiltonian). */
+typedef struct {
+    int n[3];            /* cells per mode, 1 <= n_l <= TC_MAX_N             */
+    double h[3];         /* cell widths (> 0)                                */
+    int R_f;             /* number of product functions (rows of U)          */
+    int R_N;             /* number of kernel terms                           */
+    int M;               /* number of nuclei, 1 <= M, M R_N <= 65535         */
+    const double *c;     /* [R_N] device: weights c_q = a_q h_1 h_2 h_3      */
+    const double *p[3];  /* [R_N][2 n_l - 1] device; may alias across modes  */
+    const double *U[3];  /* [R_f][n_l] device: the product functions         */
+    const double *Z;     /* [M] host: nuclear charges (finite)               */
+    const int *pos;      /* [M][3] host: grid cell of nucleus a along mode l,
+                            0 <= pos[3a + l] < n_l (nuclei at cell centres) */
+    double *V;           /* [R_f][R_f] device, output, both triangles        */
+} tc_nuclear_problem;
+
 /* A density in canonical format against a set of product functions, for
  * tc_coulomb (Section 3.1, the Hartree potential and the Coulomb matrix). */
 typedef struct {
@@ -340,6 +357,29 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
                           const double *const *V_dev, const double *const *M_dev, double tol,
                           int R_max, double *L_dev, int *pivots_host, int *R_out,
                           double *residual_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tc_nuclear -- Galerkin matrix of the nuclear potential operator
+ * V_c(x) = -sum_a Z_a / |x - x_a| in the basis of product functions
+ * (Section 3.3: the master kernel is shifted to each nucleus by a rank-1
+ * windowing, the shifted kernels are summed with the charges, and the matrix
+ * entries are scalar products of the rank-1 products with that sum):
+ *   V[i][j] = -sum_a Z_a sum_q (c_q/(h1 h2 h3)) prod_l sum_x U^l[i][x] U^l[j][x]
+ *                                                    p^l_q[x - pos[a][l] + n_l - 1],
+ * i.e. the cell volume times the sum over grid cells of g_i g_j V_c, with the
+ * kernel's approximation of 1/|x| (its cell average) in place of 1/|x|.
+ *   prob  host descriptor; c, p, U, V device, Z and pos host (read before
+ *         the call returns; the tables travel as kernel arguments).
+ *   The 1D matrices U^l diag(p^l_q shifted) U^l^T of every (nucleus, term)
+ *   pair on binary64 matrix cores, then the product over the modes and the
+ *   sum over the pairs in a fixed order (bitwise reproducible).
+ *   ws    tc_nuclear_workspace_bytes(prob) bytes of device memory
+ *         (3 M R_N R_f^2 doubles for the 1D matrices, plus tables); returns
+ *         (size_t)-1 for an invalid descriptor.
+ * Runs on `stream`, stream-ordered, no synchronisation.
+ */
+size_t tc_nuclear_workspace_bytes(const tc_nuclear_problem *prob);
+tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * tc_lattice_sum -- assembled canonical vectors of the Newton kernel summed

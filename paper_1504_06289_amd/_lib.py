@@ -35,7 +35,8 @@ EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backwa
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
            "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
            "tc_density_fit_workspace_bytes", "tc_tei_cholesky",
-           "tc_tei_cholesky_workspace_bytes", "tc_lattice_sum", "tc_lattice_energy")
+           "tc_tei_cholesky_workspace_bytes", "tc_lattice_sum", "tc_lattice_energy", "tc_nuclear",
+           "tc_nuclear_workspace_bytes")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -68,6 +69,22 @@ class TcDensity(ctypes.Structure):
         ("V", ctypes.c_void_p * 3),
         ("d", ctypes.c_void_p),
         ("Jd", ctypes.c_void_p),
+    ]
+
+
+class TcNuclear(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3),
+        ("h", ctypes.c_double * 3),
+        ("R_f", ctypes.c_int),
+        ("R_N", ctypes.c_int),
+        ("M", ctypes.c_int),
+        ("c", ctypes.c_void_p),
+        ("p", ctypes.c_void_p * 3),
+        ("U", ctypes.c_void_p * 3),
+        ("Z", ctypes.c_void_p),
+        ("pos", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
     ]
 
 
@@ -141,6 +158,10 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
                                       ctypes.c_int, vp, pi, pi, pd, vp, ctypes.c_size_t, vp]
         L.tc_tei_cholesky.restype = ctypes.c_int
+        L.tc_nuclear_workspace_bytes.argtypes = [ctypes.POINTER(TcNuclear)]
+        L.tc_nuclear_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_nuclear.argtypes = [ctypes.POINTER(TcNuclear), vp, ctypes.c_size_t, vp]
+        L.tc_nuclear.restype = ctypes.c_int
         L.tc_lattice_sum.argtypes = [ctypes.c_int, pi, ctypes.c_int, ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp]
         L.tc_lattice_sum.restype = ctypes.c_int

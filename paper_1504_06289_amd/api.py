@@ -113,6 +113,38 @@ def coulomb(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tens
     return Jd
 
 
+def nuclear(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],
+            h: Sequence[float], Z, pos) -> torch.Tensor:
+    """tc_nuclear: V[i][j] = -sum_a Z_a sum_q (c_q/(h1 h2 h3)) prod_l
+    sum_x U^l[i][x] U^l[j][x] p^l_q[x - pos[a][l]], the nuclear potential
+    matrix of the product functions (Z [M] charges, pos [M][3] grid cells)."""
+    _dev_f64(c, "c")
+    R_f, R_N = U3[0].shape[0], c.shape[0]
+    dev = c.device
+    Zh = np.ascontiguousarray(Z, dtype=np.float64).reshape(-1)
+    ph = np.ascontiguousarray(pos, dtype=np.int32).reshape(-1, 3)
+    if ph.shape[0] != Zh.shape[0]:
+        raise ValueError("pos must be [M][3] with M = len(Z)")
+    V = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+    P = _lib.TcNuclear()
+    P.R_f, P.R_N, P.M = R_f, R_N, Zh.shape[0]
+    P.c, P.V = c.data_ptr(), V.data_ptr()
+    P.Z, P.pos = Zh.ctypes.data, ph.ctypes.data
+    for l in range(3):
+        _dev_f64(p3[l], f"p[{l}]")
+        _dev_f64(U3[l], f"U[{l}]")
+        P.n[l] = U3[l].shape[1]
+        P.h[l] = float(h[l])
+        P.p[l], P.U[l] = p3[l].data_ptr(), U3[l].data_ptr()
+    L = _lib.lib()
+    ws_bytes = L.tc_nuclear_workspace_bytes(ctypes.byref(P))
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("tc_nuclear: sizes, charges or cells out of range")
+    ws = _workspace(ws_bytes, dev)
+    check(L.tc_nuclear(ctypes.byref(P), _ptr(ws), ws_bytes, _stream(dev)), "tc_nuclear")
+    return V
+
+
 def density_fit(F: torch.Tensor, tol: float, R_max: Optional[int] = None):
     """tc_density_fit: F [N_pair][n] ~ V U through the pivoted Cholesky of
     F^T F.  Returns (U [R_max][n], V [N_pair][R_max], pivots numpy [R],

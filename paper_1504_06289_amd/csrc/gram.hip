@@ -6,6 +6,11 @@
 // computed; each computed entry with i <= j is written to (i, j) and (j, i),
 // which makes the stored Gram exactly symmetric.
 //
+// The diagonal form (nuclear potential matrices) takes a diagonal operator in
+// place of T_k: term k = alpha R_N + q scales row j of the second operand by
+// the kernel vector p_q shifted to the cell shift[alpha],
+//   G[k][i][j] = sum_a U[i][a] U[j][a] p_q[a - shift[alpha]].
+//
 // Both operands are contiguous along the contraction index a.  Tiles:
 // 64 x 64 per workgroup, 4 waves as 2 x 2 wave tiles of 32 x 32, K-step 16,
 // v_mfma_f64_16x16x4_f64 (lane l supplies A[l%16][l/16], B[l/16][l%16];
@@ -22,10 +27,12 @@ constexpr int BT = 64;  // tile edge (i and j)
 constexpr int BK = 16;
 constexpr int PAD = 1;
 
+template <bool DIAG>
 __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict__ U,
                                                        const double *__restrict__ W,
                                                        double *__restrict__ G, int n, int R_f,
-                                                       int ntiles, int mirror)
+                                                       int ntiles, int mirror,
+                                                       const int *__restrict__ shift, int R_N)
 {
     __shared__ double As[2][BT][BK + PAD];
     __shared__ double Bs[2][BT][BK + PAD];
@@ -40,7 +47,14 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
     const int tj = ti + t;
     const int k = blockIdx.y;
     const int i0 = ti * BT, j0 = tj * BT;
-    const double *Wk = W + (long)k * R_f * n;
+    const double *Wk;
+    if constexpr (DIAG) {
+        // Wk[a] = p_q[a - shift]: lag a - shift lies in [-(n-1), n-1]
+        const int alpha = k / R_N, q = k - alpha * R_N;
+        Wk = W + (long)q * (2L * n - 1) + (n - 1) - shift[alpha];
+    } else {
+        Wk = W + (long)k * R_f * n;
+    }
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -60,7 +74,10 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
         for (int q = 0; q < 4; ++q) {
             const int a = a0 + lcol + q;
             areg[q] = (i < R_f && a < n) ? U[(long)i * n + a] : 0.0;
-            breg[q] = (j < R_f && a < n) ? Wk[(long)j * n + a] : 0.0;
+            if constexpr (DIAG)
+                breg[q] = (j < R_f && a < n) ? U[(long)j * n + a] * Wk[a] : 0.0;
+            else
+                breg[q] = (j < R_f && a < n) ? Wk[(long)j * n + a] : 0.0;
         }
     };
     auto store_stage = [&](int buf) {
@@ -132,8 +149,18 @@ hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n, i
 {
     const int nt = (R_f + BT - 1) / BT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(gram_f64_kernel, grid, dim3(256), 0, stream, U, W, G, n, R_f, nt,
-                       (int)mirror);
+    hipLaunchKernelGGL(gram_f64_kernel<false>, grid, dim3(256), 0, stream, U, W, G, n, R_f, nt,
+                       (int)mirror, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift, double *G,
+                                int n, int R_f, int R_N, int M, bool mirror, hipStream_t stream)
+{
+    const int nt = (R_f + BT - 1) / BT;
+    dim3 grid(nt * (nt + 1) / 2, M * R_N);
+    hipLaunchKernelGGL(gram_f64_kernel<true>, grid, dim3(256), 0, stream, U, p, G, n, R_f, nt,
+                       (int)mirror, shift, R_N);
     return hipGetLastError();
 }
 

@@ -953,6 +953,84 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
                             residual_out, st);
 }
 
+// ---- nuclear potential matrix ----------------------------------------------
+static bool nuclear_ok(const tc_nuclear_problem &P)
+{
+    if (!P.c || !P.V || !P.Z || !P.pos || P.M < 1 || (long)P.M * P.R_N > 65535)
+        return false;
+    for (int l = 0; l < 3; ++l) {
+        if (!size_ok(P.n[l], P.R_f, P.R_N) || !P.p[l] || !P.U[l] || !(P.h[l] > 0.0) ||
+            !std::isfinite(P.h[l]))
+            return false;
+    }
+    for (int a = 0; a < P.M; ++a) {
+        if (!std::isfinite(P.Z[a]))
+            return false;
+        for (int l = 0; l < 3; ++l)
+            if (P.pos[3 * a + l] < 0 || P.pos[3 * a + l] >= P.n[l])
+                return false;
+    }
+    return true;
+}
+
+// Workspace: [shift: 3 x M ints][cw: M R_N][G: 3 x M R_N x R_f x R_f]
+struct NuclearPlan {
+    int *shift;
+    double *cw, *G;
+    size_t bytes;
+};
+
+static NuclearPlan plan_nuclear(void *ws, const tc_nuclear_problem &P)
+{
+    NuclearPlan N{};
+    Carver c(ws);
+    const size_t T = (size_t)P.M * P.R_N;
+    N.shift = c.take<int>(3 * (size_t)P.M);
+    N.cw = c.take<double>(T);
+    N.G = c.take<double>(3 * T * P.R_f * P.R_f);
+    N.bytes = c.used;
+    return N;
+}
+
+size_t tc_nuclear_workspace_bytes(const tc_nuclear_problem *prob)
+{
+    if (!prob || !nuclear_ok(*prob))
+        return (size_t)-1;
+    return plan_nuclear(nullptr, *prob).bytes;
+}
+
+tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!prob || !nuclear_ok(*prob))
+        return TC_ERR_INVALID_ARG;
+    const tc_nuclear_problem &P = *prob;
+    const NuclearPlan N = plan_nuclear(ws, P);
+    if (!ws || ws_bytes < N.bytes)
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const double inv_vol = 1.0 / (P.h[0] * P.h[1] * P.h[2]);
+    for (int base = 0; base < P.M; base += kNuclearChunk) {
+        NuclearChunk ch{};
+        ch.base = base;
+        ch.count = std::min(kNuclearChunk, P.M - base);
+        for (int a = 0; a < ch.count; ++a) {
+            ch.Z[a] = P.Z[base + a];
+            for (int l = 0; l < 3; ++l)
+                ch.pos[l][a] = P.pos[3 * (base + a) + l];
+        }
+        TRYK("nuclear_table",
+             launch_nuclear_table(ch, P.c, P.R_N, P.M, inv_vol, N.shift, N.cw, st));
+    }
+    const size_t plane = (size_t)P.M * P.R_N * P.R_f * P.R_f;
+    for (int l = 0; l < 3; ++l)
+        TRYK("diag_gram_f64", launch_diag_gram_f64(P.U[l], P.p[l], N.shift + l * P.M,
+                                                   N.G + l * plane, P.n[l], P.R_f, P.R_N, P.M,
+                                                   false, st));
+    TRYK("hadamard_sum", launch_hadamard_sum(N.cw, N.G, N.G + plane, N.G + 2 * plane, P.V, P.R_f,
+                                             P.M * P.R_N, st));
+    return TC_OK;
+}
+
 static bool lattice_ok(int n0, const int *L, int R_N, const double *const *p)
 {
     if (n0 < 1 || !L || !p || R_N < 1 || R_N > TC_MAX_RN)

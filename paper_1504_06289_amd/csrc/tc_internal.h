@@ -27,6 +27,23 @@ hipError_t launch_toeplitz_f64(const double *p, const double *U, double *W, int 
 hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n,
                            int R_f, int R_N, bool mirror, hipStream_t stream);
 
+// Diagonal form: term k = alpha R_N + q (k < M R_N) with p_q shifted to the
+// cell shift[alpha] (0 <= shift < n) in place of W_k:
+// G[k][i][j] = sum_a U[i][a] U[j][a] p[q][a - shift[alpha] + n - 1].
+hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift, double *G,
+                                int n, int R_f, int R_N, int M, bool mirror, hipStream_t stream);
+
+// ---- nuclear potential tables (nuclear.hip) -------------------------------
+constexpr int kNuclearChunk = 64;
+struct NuclearChunk {
+    int base, count;                 // nuclei base .. base + count - 1
+    double Z[kNuclearChunk];         // charges
+    int pos[3][kNuclearChunk];       // cell of each nucleus per mode
+};
+// cw[alpha R_N + q] = -Z_alpha c_q inv_vol; shift[l M + alpha] = pos[alpha][l]
+hipError_t launch_nuclear_table(const NuclearChunk &ch, const double *c, int R_N, int M,
+                                double inv_vol, int *shift, double *cw, hipStream_t st);
+
 // ---- binary32 matrix-core variants (fp32.hip) ------------------------------
 // E[r] = exponent of the largest |X[r][.]| (max < 2^E[r]; 0 for a zero row).
 hipError_t launch_row_exponents(const double *X, long rows, int len, int *E,

@@ -289,3 +289,38 @@ def test_lattice_rejects(L):
                                None) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_lattice_energy(5, Lok, 5, v, h, nul3, 1.0, ctypes.byref(E), v, 48,
                                None) == _lib.TC_ERR_INVALID_ARG
+
+
+def _nuclear_problem(M=2, pos=None, Z=None):
+    import numpy as np
+    P = _lib.TcNuclear()
+    P.R_f, P.R_N, P.M = 16, 4, M
+    v = 0x1000
+    P.c, P.V = v, v
+    for l in range(3):
+        P.n[l] = 10
+        P.h[l] = 0.1
+        P.p[l], P.U[l] = v, v
+    Zh = np.ones(M) if Z is None else np.asarray(Z, dtype=np.float64)
+    ph = np.zeros((M, 3), dtype=np.int32) if pos is None else np.asarray(pos, dtype=np.int32)
+    P.Z, P.pos = Zh.ctypes.data, ph.ctypes.data
+    return P, (Zh, ph)
+
+
+def test_nuclear_workspace_and_rejects(L):
+    P, keep = _nuclear_problem()
+    need = L.tc_nuclear_workspace_bytes(ctypes.byref(P))
+    assert need >= 3 * 2 * 4 * 16 * 16 * 8
+    assert L.tc_nuclear(ctypes.byref(P), None, 0, None) == _lib.TC_ERR_WORKSPACE
+    for kw in [dict(pos=[[0, 0, 10], [1, 1, 1]]), dict(pos=[[0, -1, 0], [1, 1, 1]]),
+               dict(Z=[1.0, float("nan")])]:
+        Pb, keep2 = _nuclear_problem(**kw)
+        assert L.tc_nuclear_workspace_bytes(ctypes.byref(Pb)) == ctypes.c_size_t(-1).value
+        assert L.tc_nuclear(ctypes.byref(Pb), ctypes.c_void_p(0x1000), 1 << 30, None) == \
+            _lib.TC_ERR_INVALID_ARG
+    Pm, keep3 = _nuclear_problem(M=20000)
+    assert L.tc_nuclear(ctypes.byref(Pm), ctypes.c_void_p(0x1000), 1 << 30, None) == \
+        _lib.TC_ERR_INVALID_ARG
+    P.h[1] = 0.0
+    assert L.tc_nuclear(ctypes.byref(P), ctypes.c_void_p(0x1000), 1 << 30, None) == \
+        _lib.TC_ERR_INVALID_ARG
