@@ -410,3 +410,68 @@ def nuclear_bruteforce(c, p3, h3, U3, Z, pos) -> np.ndarray:
             gm = np.einsum("a,b,c->abc", U3[0][m], U3[1][m], U3[2][m])
             V[k, m] = vol * np.sum(gk * gm * Vc)
     return V
+
+
+# --------------------------------------------------------------------------
+# Canonical-to-Tucker transform (Appendix, part 1): the SVD of each side
+# matrix gives a first mode basis, the side matrices are projected onto it,
+# alternating sweeps replace each mode's basis by the dominant left singular
+# vectors of the partially projected image, and the core is the fully
+# projected tensor.  Side matrices are stored as A^l [R][n_l] (row k = the
+# mode-l vector of term k), bases as Z^l [r_l][n_l] (orthonormal rows).
+# --------------------------------------------------------------------------
+def _sign_rows(Z: np.ndarray) -> np.ndarray:
+    """Fix the sign of each basis vector: its entry of largest magnitude (the
+    first such) is positive."""
+    Z = Z.copy()
+    for i in range(Z.shape[0]):
+        if Z[i, np.argmax(np.abs(Z[i]))] < 0:
+            Z[i] = -Z[i]
+    return Z
+
+
+def _leading_left(Mt: np.ndarray, r: int):
+    """The r dominant left singular vectors of the n x m matrix Mt^T (Mt is
+    [m][n]) as rows [r][n], and the singular values."""
+    Zf, s, _ = np.linalg.svd(Mt.T, full_matrices=False)
+    Z = np.zeros((r, Mt.shape[1]))
+    k = min(r, Zf.shape[1])
+    Z[:k] = Zf[:, :k].T
+    return _sign_rows(Z), s
+
+
+def canonical_to_tucker(c, A3, ranks, m_max: int):
+    """Returns (Z3 [r_l][n_l] each, beta [r1][r2][r3], sv3: singular values of
+    the last SVD of each mode)."""
+    c = _f64(c)
+    A3 = [_f64(a) for a in A3]
+    # (A) dominant subspace of each side matrix; (B) projection
+    Z3, sv3 = [], []
+    for l in range(3):
+        Z, s = _leading_left(A3[l], ranks[l])
+        Z3.append(Z)
+        sv3.append(s)
+    Ut = [Z3[l] @ A3[l].T for l in range(3)]            # [r_l][R]
+    # (C, D) alternating sweeps over the modes
+    for _ in range(m_max):
+        for l in range(3):
+            m1, m2 = [x for x in range(3) if x != l]
+            # partially projected image, mode l in physical space:
+            # M[a][(i, j)] = sum_k c_k A^l[k][a] Ut^m1[i][k] Ut^m2[j][k]
+            K = (c[None, None, :] * Ut[m1][:, None, :] * Ut[m2][None, :, :]).reshape(-1, c.shape[0])
+            Mt = K @ A3[l]                                # [r_m1 r_m2][n_l] = M^T
+            Z3[l], sv3[l] = _leading_left(Mt, ranks[l])
+            Ut[l] = Z3[l] @ A3[l].T
+    # (E) core
+    beta = np.einsum("k,ik,jk,mk->ijm", c, Ut[0], Ut[1], Ut[2])
+    return Z3, beta, sv3
+
+
+def tucker_full(Z3, beta) -> np.ndarray:
+    """The full tensor of a Tucker representation (small grids only)."""
+    return np.einsum("ijm,ia,jb,mc->abc", beta, Z3[0], Z3[1], Z3[2])
+
+
+def canonical_full(c, A3) -> np.ndarray:
+    """The full tensor of a canonical representation (small grids only)."""
+    return np.einsum("k,ka,kb,kc->abc", _f64(c), A3[0], A3[1], A3[2])

@@ -692,3 +692,51 @@ def test_nuclear_matrix_boys_closed_form_h2(orc):
     assert errs[-1] < 2e-4, errs
     for r in ratios[1:]:
         assert 3.5 < r < 4.6, (errs, ratios)
+
+
+def test_canonical_to_tucker_recovers_low_multilinear_rank(orc):
+    """A canonical tensor of rank 40 whose side matrices span r_l-dimensional
+    subspaces has multilinear rank (r1, r2, r3): the transform with those ranks
+    reproduces the full tensor, with orthonormal bases, for any sweep count;
+    with ranks equal to n_l it is exact as well."""
+    rng = np.random.default_rng(7)
+    n3, r3, R = (11, 9, 13), (3, 4, 5), 40
+    A3 = [rng.standard_normal((R, r3[l])) @ rng.standard_normal((r3[l], n3[l])) for l in range(3)]
+    c = rng.uniform(0.5, 2.0, R)
+    T = orc.canonical_full(c, A3)
+    for m_max in (0, 1, 3):
+        Z3, beta, sv = orc.canonical_to_tucker(c, A3, r3, m_max)
+        for l in range(3):
+            np.testing.assert_allclose(Z3[l] @ Z3[l].T, np.eye(r3[l]), atol=1e-13)
+        assert np.max(np.abs(orc.tucker_full(Z3, beta) - T)) <= 1e-12 * np.max(np.abs(T))
+    Z3, beta, sv = orc.canonical_to_tucker(c, A3, n3, 1)
+    assert np.max(np.abs(orc.tucker_full(Z3, beta) - T)) <= 1e-12 * np.max(np.abs(T))
+
+
+def test_canonical_to_tucker_sweep_is_the_unfolding_svd(orc):
+    """One alternating step against the full tensor: after a sweep, Z^3 spans
+    the dominant left singular vectors of the mode-3 unfolding of the full
+    tensor projected onto Z^1, Z^2 (formed in 3D), and the core is the full
+    tensor projected onto all three bases."""
+    rng = np.random.default_rng(8)
+    n3, R, r3 = (10, 12, 8), 30, (4, 3, 5)
+    A3 = [rng.standard_normal((R, n3[l])) for l in range(3)]
+    c = rng.standard_normal(R)
+    T = orc.canonical_full(c, A3)
+    Z3, beta, sv = orc.canonical_to_tucker(c, A3, r3, 1)
+    # the bases of modes 1, 2 at the time mode 3 was updated are the final ones
+    P = np.einsum("abc,ia,jb->ijc", T, Z3[0], Z3[1]).reshape(-1, n3[2])   # [(i j)][c]
+    u, s, vt = np.linalg.svd(P.T, full_matrices=False)
+    Pz = Z3[2].T @ Z3[2]
+    Pu = u[:, :r3[2]] @ u[:, :r3[2]].T
+    assert np.max(np.abs(Pz - Pu)) <= 1e-12
+    np.testing.assert_allclose(sv[2][:r3[2]], s[:r3[2]], rtol=1e-12)
+    beta_ref = np.einsum("abc,ia,jb,mc->ijm", T, Z3[0], Z3[1], Z3[2])
+    assert np.max(np.abs(beta - beta_ref)) <= 1e-12 * np.max(np.abs(beta_ref))
+    # the sweep does not increase the error of the first (RHOSVD) step
+    Z0, b0, _ = orc.canonical_to_tucker(c, A3, r3, 0)
+    e0 = np.linalg.norm(orc.tucker_full(Z0, b0) - T)
+    e1 = np.linalg.norm(orc.tucker_full(Z3, beta) - T)
+    assert e1 <= e0 * (1 + 1e-12)
+    # the core of orthonormal bases holds the projected norm
+    assert abs(np.linalg.norm(beta) - np.linalg.norm(beta_ref)) <= 1e-12 * np.linalg.norm(beta_ref)
