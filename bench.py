@@ -465,6 +465,20 @@ def extra_rows(tc, wl, torch, dev, args):
                                 "TFLOP/s": round(fl / 3 / (ms_dg * 1e-3) / 1e12, 2),
                                 "frac": round(fl / 3 / (ms_dg * 1e-3) / 1e12 / PEAK["fp64"], 4)}
     rows["nuclear_c3_h2o"] = row
+    # canonical-to-Tucker transform of a density with 2048 terms on the
+    # 4096-cell grid, Tucker ranks 24, two sweeps, 20 subspace steps
+    Vt_, dt_ = wl.density(w3.n, w3.b, 2048, seed=5)
+    At = [torch.from_numpy(v).to(dev) for v in Vt_]
+    ctd = torch.from_numpy(dt_).to(dev)
+    c2t = lambda: tc.canonical_to_tucker(ctd, At, (24, 24, 24), 2, 20)
+    msc2t = timed(c2t, 2, 1, torch)
+    tc.profile_enable(True)
+    tc.profile_read()
+    c2t()
+    prof = tc.profile_read()
+    tc.profile_enable(False)
+    rows["c2t_n4096_R2048_r24"] = {"ms": round(msc2t, 2),
+                                   "kernels_ms": {k: round(v[0], 3) for k, v in prof.items()}}
     # lattices of hydrogen atoms (Z = 1, spacing 2 bohr): the interaction
     # energy of the 256^3 lattice on the n = 128 L grid, and the assembled
     # lattice sum of the 128^3 lattice on a 34304-cell grid, each with the

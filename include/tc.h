@@ -382,6 +382,41 @@ size_t tc_nuclear_workspace_bytes(const tc_nuclear_problem *prob);
 tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * tc_canonical_to_tucker -- Tucker form of a canonical tensor
+ * T = sum_k c_k a^1_k x a^2_k x a^3_k (Appendix, part 1, the
+ * Canonical-to-Tucker transform):
+ *   (A) Z^l = the r_l dominant left singular vectors of the side matrix,
+ *   (B) the side matrices projected onto them, U~^l = Z^l A^l^T,
+ *   (C, D) m_max sweeps over l = 1, 2, 3: Z^l = the r_l dominant left
+ *       singular vectors of the partially projected image
+ *       M^l = sum_k c_k a^l_k x u~^m1_k x u~^m2_k (n_l x r_m1 r_m2), then
+ *       U~^l updated,
+ *   (E) the core beta = sum_k c_k u~^1_k x u~^2_k x u~^3_k,
+ * so that T ~ sum beta[i][j][m] z^1_i x z^2_j x z^3_m.  Each dominant
+ * subspace comes from `its` steps of orthogonal iteration on a subspace of
+ * k = min(n_l, 64, max(2 r_l, r_l + 8)) vectors (pseudo-random start, or the
+ * previous basis in a sweep) and a Rayleigh-Ritz step; with a gap between
+ * the r_l-th and the (k+1)-th singular value the basis converges like
+ * (sigma_{k+1}/sigma_{r_l})^{2 its}.  Each basis vector's entry of largest
+ * magnitude is positive.
+ *   n host [3], 1 <= n_l <= TC_MAX_N; R >= 1 terms; c [R] device;
+ *   A_dev host array [3] of device [R][n_l] (row k = the mode-l vector of
+ *   term k); r host [3], 1 <= r_l <= min(48, n_l, R), and with m_max > 0
+ *   r_l <= r_m1 r_m2; 0 <= m_max <= 100; 1 <= its <= 1000.
+ *   Z_dev host array [3] of device [r_l][n_l] outputs (orthonormal rows);
+ *   beta_dev device [r1][r2][r3] output; sv_dev device [r1 + r2 + r3] output
+ *   (the singular values of the last step of each mode) or NULL.
+ *   ws    tc_canonical_to_tucker_workspace_bytes(n, R, r) bytes of device
+ *         memory ((size_t)-1 for invalid sizes).
+ * Runs on `stream`, stream-ordered, no synchronisation.
+ */
+size_t tc_canonical_to_tucker_workspace_bytes(const int *n, int R, const int *r);
+tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
+                                 const double *const *A_dev, const int *r, int m_max, int its,
+                                 double *const *Z_dev, double *beta_dev, double *sv_dev,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/*
  * tc_lattice_sum -- assembled canonical vectors of the Newton kernel summed
  * over a rectangular lattice of charges (Section 5.1, eq. CoulombLatTensCan):
  * L[l] unit cells of n0 grid cells along direction l (n_l = n0 L[l] cells of

@@ -2,7 +2,8 @@
 two-electron-integral Gram assembly of Khoromskaia & Khoromskij
 (arXiv:1504.06289).  The C ABI is include/tc.h; this package is its thin
 Python binding (see api.py) plus the seeded synthetic workloads."""
-from .api import (TeiGram, TeiGramGraph, autotune, autotune_batched, convolve,  # noqa: F401
+from .api import (TeiGram, TeiGramGraph, autotune, autotune_batched,  # noqa: F401
+                  canonical_to_tucker, convolve,
                   coulomb, density_fit, lattice_energy, lattice_sum, newton_kernel, nuclear,
                   profile_enable, profile_read,
                   tei_cholesky, tei_gram, tei_gram_backward, tei_gram_batched, term_classes,

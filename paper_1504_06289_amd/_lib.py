@@ -36,7 +36,8 @@ EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backwa
            "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
            "tc_density_fit_workspace_bytes", "tc_tei_cholesky",
            "tc_tei_cholesky_workspace_bytes", "tc_lattice_sum", "tc_lattice_energy", "tc_nuclear",
-           "tc_nuclear_workspace_bytes")
+           "tc_nuclear_workspace_bytes", "tc_canonical_to_tucker",
+           "tc_canonical_to_tucker_workspace_bytes")
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -158,6 +159,12 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
                                       ctypes.c_int, vp, pi, pi, pd, vp, ctypes.c_size_t, vp]
         L.tc_tei_cholesky.restype = ctypes.c_int
+        L.tc_canonical_to_tucker_workspace_bytes.argtypes = [pi, ctypes.c_int, pi]
+        L.tc_canonical_to_tucker_workspace_bytes.restype = ctypes.c_size_t
+        L.tc_canonical_to_tucker.argtypes = [pi, ctypes.c_int, vp, ctypes.POINTER(vp), pi,
+                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), vp,
+                                             vp, vp, ctypes.c_size_t, vp]
+        L.tc_canonical_to_tucker.restype = ctypes.c_int
         L.tc_nuclear_workspace_bytes.argtypes = [ctypes.POINTER(TcNuclear)]
         L.tc_nuclear_workspace_bytes.restype = ctypes.c_size_t
         L.tc_nuclear.argtypes = [ctypes.POINTER(TcNuclear), vp, ctypes.c_size_t, vp]

@@ -113,6 +113,39 @@ def coulomb(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tens
     return Jd
 
 
+def canonical_to_tucker(c: torch.Tensor, A3: Sequence[torch.Tensor], ranks: Sequence[int],
+                        m_max: int = 2, its: int = 20):
+    """tc_canonical_to_tucker: Tucker form of sum_k c_k a^1_k x a^2_k x a^3_k
+    (A3[l] [R][n_l]).  Returns (Z3: [r_l][n_l] orthonormal rows, beta
+    [r1][r2][r3], sv: numpy singular values of the last step of each mode)."""
+    _dev_f64(c, "c")
+    R = c.shape[0]
+    dev = c.device
+    n = [int(A3[l].shape[1]) for l in range(3)]
+    for l in range(3):
+        _dev_f64(A3[l], f"A[{l}]")
+        if A3[l].shape[0] != R:
+            raise ValueError(f"A[{l}] must be [R][n_{l}]")
+    r = [int(x) for x in ranks]
+    Z3 = [torch.empty((r[l], n[l]), dtype=torch.float64, device=dev) for l in range(3)]
+    beta = torch.empty((r[0], r[1], r[2]), dtype=torch.float64, device=dev)
+    sv = torch.empty(sum(r), dtype=torch.float64, device=dev)
+    ni = (ctypes.c_int * 3)(*n)
+    ri = (ctypes.c_int * 3)(*r)
+    L = _lib.lib()
+    ws_bytes = L.tc_canonical_to_tucker_workspace_bytes(ni, R, ri)
+    if ws_bytes == ctypes.c_size_t(-1).value:
+        raise ValueError("tc_canonical_to_tucker: sizes or ranks out of range")
+    ws = _workspace(ws_bytes, dev)
+    av = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in A3])
+    zv = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in Z3])
+    check(L.tc_canonical_to_tucker(ni, R, _ptr(c), av, ri, int(m_max), int(its), zv,
+                                   _ptr(beta), _ptr(sv), _ptr(ws), ws_bytes, _stream(dev)),
+          "tc_canonical_to_tucker")
+    s = sv.cpu().numpy()
+    return Z3, beta, [s[:r[0]], s[r[0]:r[0] + r[1]], s[r[0] + r[1]:]]
+
+
 def nuclear(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],
             h: Sequence[float], Z, pos) -> torch.Tensor:
     """tc_nuclear: V[i][j] = -sum_a Z_a sum_q (c_q/(h1 h2 h3)) prod_l

@@ -953,6 +953,159 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
                             residual_out, st);
 }
 
+// ---- canonical-to-Tucker transform ------------------------------------------
+static bool tucker_sizes_ok(const int *n, int R, const int *r)
+{
+    if (!n || !r || R < 1 || R > (1 << 24))
+        return false;
+    for (int l = 0; l < 3; ++l)
+        if (n[l] < 1 || n[l] > TC_MAX_N || r[l] < 1 || r[l] > kTuckerMaxRank || r[l] > n[l] ||
+            r[l] > R)
+            return false;
+    return true;
+}
+
+static int tucker_sub(int n, int r)
+{
+    return std::min(std::min(n, kTuckerMaxSub), std::max(2 * r, r + 8));
+}
+
+// Workspace: [X: 64 x nmax][P: 64 x mmax][part: slices x 64 x max(nmax, mmax)]
+// [H: 64 x 64][lam: 64][Vt: 64 x 64][Ut: 3 x 48 x R][K: 48^2 x R][Mt: 48^2 x nmax]
+struct TuckerPlan {
+    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt;
+    size_t bytes;
+};
+
+static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
+{
+    TuckerPlan T{};
+    Carver c(ws);
+    int nmax = std::max(n[0], std::max(n[1], n[2]));
+    long rr = 0;
+    for (int l = 0; l < 3; ++l)
+        for (int m = l + 1; m < 3; ++m)
+            rr = std::max(rr, (long)r[l] * r[m]);
+    const long mmax = std::max((long)R, rr);
+    T.X = c.take<double>((size_t)kTuckerMaxSub * nmax);
+    T.P = c.take<double>((size_t)kTuckerMaxSub * mmax);
+    // split-slice scratch: the largest of the products the transform forms
+    size_t part = 0;
+    auto need = [&](long I, long N, long K) {
+        part = std::max(part, (size_t)gemm_splits((int)I, (int)N, (int)K) * I * N);
+    };
+    for (int l = 0; l < 3; ++l) {
+        const int k = tucker_sub(n[l], r[l]);
+        const int m1 = l == 0 ? 1 : 0, m2 = l == 2 ? 1 : 2;
+        const long q = (long)r[m1] * r[m2];
+        for (long m : {(long)R, q}) {
+            need(k, m, n[l]);
+            need(k, n[l], m);
+            need(k, k, m);
+        }
+        need(r[l], n[l], k);
+        need(r[l], R, n[l]);
+        need(q, n[l], R);
+    }
+    need(r[0], (long)r[1] * r[2], R);
+    T.part = c.take<double>(part);
+    T.H = c.take<double>((size_t)kTuckerMaxSub * kTuckerMaxSub);
+    T.lam = c.take<double>(kTuckerMaxSub);
+    T.Vt = c.take<double>((size_t)kTuckerMaxSub * kTuckerMaxSub);
+    for (int l = 0; l < 3; ++l)
+        T.Ut[l] = c.take<double>((size_t)r[l] * R);
+    T.K = c.take<double>((size_t)rr * R);
+    T.Mt = c.take<double>((size_t)rr * nmax);
+    T.bytes = c.used;
+    return T;
+}
+
+// The r dominant left singular vectors of B^T (B [m][n] rows) as the rows of
+// Z [r][n]: orthogonal iteration, then Rayleigh-Ritz.  warm: the first r rows
+// of the start are Z itself.
+static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int n, int r,
+                               int its, bool warm, double *Z, double *sv,
+                               unsigned long long salt, hipStream_t st)
+{
+    const int k = tucker_sub(n, r);
+    if (warm && hipMemcpyAsync(T.X, Z, sizeof(double) * (size_t)r * n, hipMemcpyDeviceToDevice,
+                               st) != hipSuccess)
+        return TC_ERR_HIP;
+    TRYK("random_rows", launch_random_rows(T.X, warm ? r : 0, k, n, salt, st));
+    TRYK("orth_rows", launch_orth_rows(T.X, k, n, salt + 1, st));
+    for (int it = 0; it < its; ++it) {
+        TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));  // X B^T
+        TRYK("gemm_f64", launch_gemm_f64(true, T.P, B, T.X, k, n, m, T.part, st));   // (X B^T) B
+        TRYK("orth_rows", launch_orth_rows(T.X, k, n, salt + 2 + it, st));
+    }
+    TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));
+    TRYK("gemm_f64", launch_gemm_f64(false, T.P, T.P, T.H, k, k, m, T.part, st));
+    TRYK("jacobi_eig", launch_jacobi_eig(T.H, k, T.lam, T.Vt, st));
+    TRYK("gemm_f64", launch_gemm_f64(true, T.Vt, T.X, Z, r, n, k, T.part, st));
+    TRYK("sign_rows", launch_sign_rows(Z, r, n, T.lam, sv, st));
+    return TC_OK;
+}
+
+size_t tc_canonical_to_tucker_workspace_bytes(const int *n, int R, const int *r)
+{
+    if (!tucker_sizes_ok(n, R, r))
+        return (size_t)-1;
+    return plan_tucker(nullptr, n, R, r).bytes;
+}
+
+tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
+                                 const double *const *A_dev, const int *r, int m_max, int its,
+                                 double *const *Z_dev, double *beta_dev, double *sv_dev,
+                                 void *ws, size_t ws_bytes, void *stream)
+{
+    if (!tucker_sizes_ok(n, R, r) || !c_dev || !A_dev || !Z_dev || !beta_dev || m_max < 0 ||
+        m_max > 100 || its < 1 || its > 1000)
+        return TC_ERR_INVALID_ARG;
+    for (int l = 0; l < 3; ++l) {
+        if (!A_dev[l] || !Z_dev[l])
+            return TC_ERR_INVALID_ARG;
+        const int m1 = l == 0 ? 1 : 0, m2 = l == 2 ? 1 : 2;
+        if (m_max > 0 && (long)r[l] > (long)r[m1] * r[m2])
+            return TC_ERR_INVALID_ARG;
+    }
+    const TuckerPlan T = plan_tucker(ws, n, R, r);
+    if (!ws || ws_bytes < T.bytes)
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double *sv3[3] = {sv_dev, sv_dev ? sv_dev + r[0] : nullptr,
+                      sv_dev ? sv_dev + r[0] + r[1] : nullptr};
+    // (A) dominant subspaces of the side matrices, (B) projections
+    for (int l = 0; l < 3; ++l) {
+        const tc_status s = dominant_rows(T, A_dev[l], R, n[l], r[l], its, false, Z_dev[l],
+                                          sv3[l], 1000ull * (l + 1), st);
+        if (s != TC_OK)
+            return s;
+        TRYK("gemm_f64", launch_gemm_f64(false, Z_dev[l], A_dev[l], T.Ut[l], r[l], R, n[l],
+                                         T.part, st));
+    }
+    // (C, D) sweeps: mode l from the image projected on the other two modes
+    for (int sweep = 0; sweep < m_max; ++sweep)
+        for (int l = 0; l < 3; ++l) {
+            const int m1 = l == 0 ? 1 : 0, m2 = l == 2 ? 1 : 2;
+            const int rr = r[m1] * r[m2];
+            TRYK("khatri_rao",
+                 launch_khatri_rao(c_dev, T.Ut[m1], T.Ut[m2], r[m1], r[m2], R, T.K, st));
+            TRYK("gemm_f64", launch_gemm_f64(true, T.K, A_dev[l], T.Mt, rr, n[l], R, T.part, st));
+            const tc_status s =
+                dominant_rows(T, T.Mt, rr, n[l], r[l], its, true, Z_dev[l], sv3[l],
+                              1000000ull + 1000ull * (3 * sweep + l), st);
+            if (s != TC_OK)
+                return s;
+            TRYK("gemm_f64", launch_gemm_f64(false, Z_dev[l], A_dev[l], T.Ut[l], r[l], R, n[l],
+                                             T.part, st));
+        }
+    // (E) core: beta[i][(j m)] = sum_t Ut1[i][t] (c_t Ut2[j][t] Ut3[m][t])
+    TRYK("khatri_rao", launch_khatri_rao(c_dev, T.Ut[1], T.Ut[2], r[1], r[2], R, T.K, st));
+    TRYK("gemm_f64", launch_gemm_f64(false, T.Ut[0], T.K, beta_dev, r[0], r[1] * r[2], R,
+                                     T.part, st));
+    return TC_OK;
+}
+
 // ---- nuclear potential matrix ----------------------------------------------
 static bool nuclear_ok(const tc_nuclear_problem &P)
 {

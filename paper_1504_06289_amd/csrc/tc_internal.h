@@ -179,6 +179,33 @@ hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st);
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
                              int R_max, const int *piv, double *U, double *V, hipStream_t st);
 
+// ---- canonical-to-Tucker pieces (tucker.hip) -------------------------------
+constexpr int kTuckerMaxSub = 64;   // rows of the iterated subspace
+constexpr int kTuckerMaxRank = 48;  // Tucker rank per mode
+constexpr int kGemmMaxSplit = 16;   // contraction slices of launch_gemm_f64
+// Slices launch_gemm_f64 uses for C [I][N] over K (part then holds
+// slices x I x N doubles).
+int gemm_splits(int I, int N, int K);
+// nn: C[i][j] = sum_t A[i][t] B[t][j] (A [I][K], B [K][N]); otherwise
+// C[i][j] = sum_t A[i][t] B[j][t] (B [N][K]).  part: split-slice scratch, or
+// NULL for one slice.
+hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C, int I, int N,
+                           int K, double *part, hipStream_t st);
+// orthonormal rows of X [k][n] (k <= kTuckerMaxSub <= n), in place
+hipError_t launch_orth_rows(double *X, int k, int n, unsigned long long salt, hipStream_t st);
+// rows i0..k-1 of X [k][n] pseudo-random in [-1, 1)
+hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
+                              hipStream_t st);
+// eigenpairs of the symmetric H [k][k] (k <= kTuckerMaxSub): lam decreasing,
+// Vt [k][k] rows the eigenvectors
+hipError_t launch_jacobi_eig(const double *H, int k, double *lam, double *Vt, hipStream_t st);
+// K[(i rb + j)][t] = c[t] Ua[i][t] Ub[j][t]
+hipError_t launch_khatri_rao(const double *c, const double *Ua, const double *Ub, int ra, int rb,
+                             int R, double *K, hipStream_t st);
+// sign of each row of Z [r][n] fixed; sv[i] = sqrt(max(lam[i], 0)) if sv
+hipError_t launch_sign_rows(double *Z, int r, int n, const double *lam, double *sv,
+                            hipStream_t st);
+
 // ---- lattice sums and lattice energy (lattice.hip) -------------------------
 hipError_t launch_lattice_sum(int n0, const int *L, int R_N, const double *const *p,
                               double *const *A, hipStream_t st);

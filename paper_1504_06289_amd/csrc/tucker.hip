@@ -1,0 +1,519 @@
+// Canonical-to-Tucker transform (Appendix, part 1), binary64.
+//
+// Every step that the transform takes an SVD for needs only the r dominant
+// left singular vectors of a matrix B^T given as rows B [m][n] (the side
+// matrix of a mode, or the transposed partially projected image).  They are
+// found by orthogonal iteration on B^T B acting on the rows of X [k][n]
+// (k = a few more than r), each step X <- orth((X B^T) B), and a final
+// Rayleigh-Ritz step: the k x k matrix H = (X B^T)(X B^T)^T is diagonalised
+// by Jacobi rotations and the r leading Ritz vectors are rotated out of X.
+//
+//   gemm_f64      C = A B^T (NT: both operands contiguous along the
+//                 contraction) or C = A B (NN: B contiguous along the output
+//                 column), 64 x 64 tiles on binary64 matrix cores, the
+//                 contraction split over blockIdx.z into fixed slices whose
+//                 partial tiles are summed in order (bitwise reproducible);
+//   orth_rows     classical Gram-Schmidt applied twice to the rows of X in one
+//                 workgroup; a row that loses all but 1e-10 of its norm is
+//                 replaced by pseudo-random values and orthogonalised again;
+//   jacobi_eig    cyclic Jacobi on a symmetric k x k matrix (k <= 64) held in
+//                 LDS, the k/2 disjoint rotations of a round-robin round at
+//                 once; eigenvalues sorted in decreasing order, eigenvectors
+//                 as rows;
+//   khatri_rao    K[(i, j)][t] = c_t Ua[i][t] Ub[j][t];
+//   sign_rows     each basis vector's entry of largest magnitude positive.
+#include "tc_internal.h"
+
+namespace tc {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;  // output tile edge
+constexpr int GK = 16;  // contraction step
+constexpr int GPAD = 1;
+
+template <bool NN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict__ A,
+                                                       const double *__restrict__ B,
+                                                       double *__restrict__ C, int I, int N,
+                                                       int K, int kchunk)
+{
+    __shared__ double As[2][GT][GK + GPAD];
+    __shared__ double Bs[2][GT][GK + GPAD];
+
+    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    double *Cs = C + (long)blockIdx.z * I * N;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wi = (wave >> 1) * 32;
+    const int wj = (wave & 1) * 32;
+    const int l16 = lane & 15;
+    const int lk = lane >> 4;
+
+    // A (and NT B): row tid/4 of the tile, four consecutive contraction indices
+    const int lrow = tid >> 2;
+    const int lcol = (tid & 3) * 4;
+    // NN B: contraction row tid/16 of the slice, four consecutive columns
+    const int nrow = tid >> 4;
+    const int ncol = (tid & 15) * 4;
+    double areg[4], breg[4];
+
+    auto load_stage = [&](int k0) {
+        const int i = i0 + lrow;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = k0 + lcol + q;
+            areg[q] = (i < I && kk < kend) ? A[(long)i * K + kk] : 0.0;
+        }
+        if constexpr (NN) {
+            const int kk = k0 + nrow;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + ncol + q;
+                breg[q] = (kk < kend && j < N) ? B[(long)kk * N + j] : 0.0;
+            }
+        } else {
+            const int j = j0 + lrow;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = k0 + lcol + q;
+                breg[q] = (j < N && kk < kend) ? B[(long)j * K + kk] : 0.0;
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            As[buf][lrow][lcol + q] = areg[q];
+        if constexpr (NN) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Bs[buf][ncol + q][nrow] = breg[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Bs[buf][lrow][lcol + q] = breg[q];
+        }
+    };
+
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int nsteps = kend > kbeg ? (kend - kbeg + GK - 1) / GK : 0;
+    if (nsteps > 0) {
+        load_stage(kbeg);
+        store_stage(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nsteps)
+            load_stage(kbeg + (s + 1) * GK);
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 4) {
+            double afr[2], bfr[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                afr[x] = As[buf][wi + x * 16 + l16][kk + lk];
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                bfr[y] = Bs[buf][wj + y * 16 + l16][kk + lk];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[x], bfr[y], acc[x][y],
+                                                                      0, 0, 0);
+        }
+        if (s + 1 < nsteps)
+            store_stage(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int j = j0 + wj + y * 16 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + x * 16 + lk + 4 * r;
+                if (i < I && j < N)
+                    Cs[(long)i * N + j] = acc[x][y][r];
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void split_sum_kernel(const double *__restrict__ part,
+                                                        double *__restrict__ C, long count,
+                                                        int S)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count)
+        return;
+    double s = 0.0;
+    for (int z = 0; z < S; ++z)
+        s += part[(long)z * count + e];
+    C[e] = s;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// pseudo-random value in [-1, 1) from (salt, row, column): splitmix64
+__device__ __forceinline__ double hash_unit(unsigned long long salt, int i, int a)
+{
+    unsigned long long z = salt * 0x9E3779B97F4A7C15ull + ((unsigned long long)i << 32) +
+                           (unsigned long long)a + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+constexpr int OT = 1024;     // threads of the orthonormalisation workgroup
+constexpr int OW = OT / 64;  // its waves
+constexpr int OJ = 16;       // earlier rows per pass over the row
+
+// block-wide sum of one value per thread (every thread gets the result)
+__device__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < OW; ++w)
+        s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(OT) void orth_rows_kernel(double *__restrict__ X, int k, int n,
+                                                       unsigned long long salt)
+{
+    __shared__ double red[OW][OJ + 1];
+    __shared__ double dots[kTuckerMaxSub];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = 0; i < k; ++i) {
+        double *xi = X + (long)i * n;
+        for (int attempt = 0; attempt < 3; ++attempt) {
+            double ss = 0.0;
+            for (int a = tid; a < n; a += OT)
+                ss += xi[a] * xi[a];
+            const double nrm0 = block_sum(ss, &red[0][0]);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j0 = 0; j0 < i; j0 += OJ) {
+                    const int jc = min(OJ, i - j0);
+                    double acc[OJ];
+#pragma unroll
+                    for (int jj = 0; jj < OJ; ++jj)
+                        acc[jj] = 0.0;
+                    for (int a = tid; a < n; a += OT) {
+                        const double v = xi[a];
+#pragma unroll
+                        for (int jj = 0; jj < OJ; ++jj)
+                            if (jj < jc)
+                                acc[jj] += X[(long)(j0 + jj) * n + a] * v;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int jj = 0; jj < OJ; ++jj) {
+                        const double v = wave_sum(acc[jj]);
+                        if (lane == 0)
+                            red[wave][jj] = v;
+                    }
+                    __syncthreads();
+                    if (tid < jc) {
+                        double s = 0.0;
+                        for (int w = 0; w < OW; ++w)
+                            s += red[w][tid];
+                        dots[j0 + tid] = s;
+                    }
+                }
+                __syncthreads();
+                for (int a = tid; a < n; a += OT) {
+                    double v = xi[a];
+                    for (int j = 0; j < i; ++j)
+                        v -= dots[j] * X[(long)j * n + a];
+                    xi[a] = v;
+                }
+                __syncthreads();
+            }
+            ss = 0.0;
+            for (int a = tid; a < n; a += OT)
+                ss += xi[a] * xi[a];
+            const double nrm = block_sum(ss, &red[0][0]);
+            if ((nrm > 1e-20 * nrm0 && nrm > 0.0) || attempt == 2) {
+                const double sc = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+                for (int a = tid; a < n; a += OT)
+                    xi[a] *= sc;
+                __syncthreads();
+                break;
+            }
+            // the row lies (numerically) in the span of the earlier rows
+            for (int a = tid; a < n; a += OT)
+                xi[a] = hash_unit(salt + 7919ull * (attempt + 1), i, a);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void random_rows_kernel(double *__restrict__ X, int i0, int k,
+                                                          int n, unsigned long long salt)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const long count = (long)(k - i0) * n;
+    if (e >= count)
+        return;
+    const int i = i0 + (int)(e / n), a = (int)(e % n);
+    X[(long)i * n + a] = hash_unit(salt, i, a);
+}
+
+constexpr int JT = 256;
+
+__global__ __launch_bounds__(JT) void jacobi_eig_kernel(const double *__restrict__ Hin, int k,
+                                                        double *__restrict__ lam,
+                                                        double *__restrict__ Vt)
+{
+    __shared__ double H[kTuckerMaxSub][kTuckerMaxSub + 1];
+    __shared__ double V[kTuckerMaxSub][kTuckerMaxSub + 1];
+    __shared__ double cs[kTuckerMaxSub / 2], sn[kTuckerMaxSub / 2];
+    __shared__ int pp[kTuckerMaxSub / 2], qq[kTuckerMaxSub / 2];
+    __shared__ int rotated;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < k * k; e += JT) {
+        const int i = e / k, j = e % k;
+        H[i][j] = 0.5 * (Hin[(long)i * k + j] + Hin[(long)j * k + i]);
+        V[i][j] = i == j ? 1.0 : 0.0;
+    }
+    const int kk = k + (k & 1);
+    const int half = kk / 2;
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0)
+            rotated = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < kk - 1; ++rnd) {
+            if (tid < half) {
+                // round-robin pairing: position 0 fixed, the rest rotate
+                const int m1 = tid, m2 = kk - 1 - tid;
+                int p = m1 == 0 ? 0 : 1 + (m1 - 1 + rnd) % (kk - 1);
+                int q = 1 + (m2 - 1 + rnd) % (kk - 1);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                int live = 0;
+                if (q < k) {
+                    const double hpq = H[p][q], hpp = H[p][p], hqq = H[q][q];
+                    if (hpq != 0.0 && fabs(hpq) > 1e-17 * sqrt(fabs(hpp * hqq))) {
+                        const double th = (hqq - hpp) / (2.0 * hpq);
+                        const double t = th != 0.0
+                                             ? copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0))
+                                             : 1.0;
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                        live = 1;
+                        rotated = 1;
+                    }
+                }
+                pp[tid] = live ? p : -1;
+                qq[tid] = q;
+                cs[tid] = c;
+                sn[tid] = s;
+            }
+            __syncthreads();
+            for (int e = tid; e < half * k; e += JT) {
+                const int r = e / k, col = e % k;
+                const int p = pp[r];
+                if (p >= 0) {
+                    const int q = qq[r];
+                    const double c = cs[r], s = sn[r];
+                    const double hp = H[p][col], hq = H[q][col];
+                    H[p][col] = c * hp - s * hq;
+                    H[q][col] = s * hp + c * hq;
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < half * k; e += JT) {
+                const int r = e / k, row = e % k;
+                const int p = pp[r];
+                if (p >= 0) {
+                    const int q = qq[r];
+                    const double c = cs[r], s = sn[r];
+                    const double hp = H[row][p], hq = H[row][q];
+                    H[row][p] = c * hp - s * hq;
+                    H[row][q] = s * hp + c * hq;
+                    const double vp = V[row][p], vq = V[row][q];
+                    V[row][p] = c * vp - s * vq;
+                    V[row][q] = s * vp + c * vq;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rotated)
+            break;
+        __syncthreads();
+    }
+    // decreasing order: the rank of eigenvalue i among all (ties by index)
+    if (tid < k) {
+        const double li = H[tid][tid];
+        int rank = 0;
+        for (int j = 0; j < k; ++j) {
+            const double lj = H[j][j];
+            rank += (lj > li) || (lj == li && j < tid);
+        }
+        lam[rank] = li;
+        for (int j = 0; j < k; ++j)
+            Vt[(long)rank * k + j] = V[j][tid];
+    }
+}
+
+__global__ __launch_bounds__(256) void khatri_rao_kernel(const double *__restrict__ c,
+                                                         const double *__restrict__ Ua,
+                                                         const double *__restrict__ Ub, int ra,
+                                                         int rb, int R, double *__restrict__ K)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const long count = (long)ra * rb * R;
+    if (e >= count)
+        return;
+    const int t = (int)(e % R);
+    const long ij = e / R;
+    const int i = (int)(ij / rb), j = (int)(ij % rb);
+    K[e] = c[t] * Ua[(long)i * R + t] * Ub[(long)j * R + t];
+}
+
+__global__ __launch_bounds__(256) void sign_rows_kernel(double *__restrict__ Z, int n,
+                                                        const double *__restrict__ lam,
+                                                        double *__restrict__ sv, int r)
+{
+    __shared__ double bv[256];
+    __shared__ int bi[256];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    double *z = Z + (long)i * n;
+    double best = -1.0;
+    int idx = n;
+    for (int a = tid; a < n; a += 256) {
+        const double v = fabs(z[a]);
+        if (v > best) {
+            best = v;
+            idx = a;
+        }
+    }
+    bv[tid] = best;
+    bi[tid] = idx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double v2 = bv[tid + w];
+            const int i2 = bi[tid + w];
+            if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
+                bv[tid] = v2;
+                bi[tid] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    const double sg = (bi[0] < n && z[bi[0]] < 0.0) ? -1.0 : 1.0;
+    __syncthreads();
+    if (sg < 0.0)
+        for (int a = tid; a < n; a += 256)
+            z[a] = -z[a];
+    if (tid == 0 && sv)
+        sv[i] = sqrt(fmax(lam[i], 0.0));
+}
+
+}  // namespace
+
+int gemm_splits(int I, int N, int K)
+{
+    const long tiles = (long)((I + GT - 1) / GT) * ((N + GT - 1) / GT);
+    int S = (int)((512 + tiles - 1) / tiles);
+    const int kmax = (K + 63) / 64;
+    S = std::min(S, std::min(kGemmMaxSplit, kmax));
+    return std::max(S, 1);
+}
+
+hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C, int I, int N,
+                           int K, double *part, hipStream_t st)
+{
+    const int S = part ? gemm_splits(I, N, K) : 1;
+    int kchunk = (K + S - 1) / S;
+    kchunk = (kchunk + GK - 1) / GK * GK;
+    const int Sused = (K + kchunk - 1) / kchunk > 0 ? (K + kchunk - 1) / kchunk : 1;
+    dim3 grid((N + GT - 1) / GT, (I + GT - 1) / GT, Sused);
+    double *out = Sused > 1 ? part : C;
+    if (nn)
+        hipLaunchKernelGGL(gemm_f64_kernel<true>, grid, dim3(256), 0, st, A, B, out, I, N, K,
+                           kchunk);
+    else
+        hipLaunchKernelGGL(gemm_f64_kernel<false>, grid, dim3(256), 0, st, A, B, out, I, N, K,
+                           kchunk);
+    if (Sused > 1) {
+        const long count = (long)I * N;
+        hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256),
+                           0, st, part, C, count, Sused);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_orth_rows(double *X, int k, int n, unsigned long long salt, hipStream_t st)
+{
+    hipLaunchKernelGGL(orth_rows_kernel, dim3(1), dim3(OT), 0, st, X, k, n, salt);
+    return hipGetLastError();
+}
+
+hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
+                              hipStream_t st)
+{
+    const long count = (long)(k - i0) * n;
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(random_rows_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       st, X, i0, k, n, salt);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_eig(const double *H, int k, double *lam, double *Vt, hipStream_t st)
+{
+    hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(JT), 0, st, H, k, lam, Vt);
+    return hipGetLastError();
+}
+
+hipError_t launch_khatri_rao(const double *c, const double *Ua, const double *Ub, int ra, int rb,
+                             int R, double *K, hipStream_t st)
+{
+    const long count = (long)ra * rb * R;
+    hipLaunchKernelGGL(khatri_rao_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       st, c, Ua, Ub, ra, rb, R, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_sign_rows(double *Z, int r, int n, const double *lam, double *sv,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(sign_rows_kernel, dim3(r), dim3(256), 0, st, Z, n, lam, sv, r);
+    return hipGetLastError();
+}
+
+}  // namespace tc

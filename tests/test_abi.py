@@ -324,3 +324,29 @@ def test_nuclear_workspace_and_rejects(L):
     P.h[1] = 0.0
     assert L.tc_nuclear(ctypes.byref(P), ctypes.c_void_p(0x1000), 1 << 30, None) == \
         _lib.TC_ERR_INVALID_ARG
+
+
+def test_canonical_to_tucker_rejects(L):
+    n = (ctypes.c_int * 3)(50, 40, 30)
+    r = (ctypes.c_int * 3)(5, 6, 7)
+    big = (ctypes.c_int * 3)(5, 49, 7)
+    over_n = (ctypes.c_int * 3)(5, 6, 31)
+    assert L.tc_canonical_to_tucker_workspace_bytes(n, 20, r) > 0
+    assert L.tc_canonical_to_tucker_workspace_bytes(n, 20, big) == ctypes.c_size_t(-1).value
+    assert L.tc_canonical_to_tucker_workspace_bytes(n, 20, over_n) == ctypes.c_size_t(-1).value
+    assert L.tc_canonical_to_tucker_workspace_bytes(n, 4, r) == ctypes.c_size_t(-1).value
+    v = ctypes.c_void_p(0x1000)
+    vp3 = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    nul3 = (ctypes.c_void_p * 3)(0x1000, None, 0x1000)
+    args = lambda **kw: dict(dict(n=n, R=20, c=v, A=vp3, r=r, m_max=1, its=10, Z=vp3, beta=v), **kw)
+    def call(a, ws=v, ws_bytes=1 << 40):
+        return L.tc_canonical_to_tucker(a["n"], a["R"], a["c"], a["A"], a["r"], a["m_max"],
+                                        a["its"], a["Z"], a["beta"], None, ws, ws_bytes, None)
+    assert call(args(), ws=None, ws_bytes=0) == _lib.TC_ERR_WORKSPACE
+    assert call(args(its=0)) == _lib.TC_ERR_INVALID_ARG
+    assert call(args(m_max=-1)) == _lib.TC_ERR_INVALID_ARG
+    assert call(args(A=nul3)) == _lib.TC_ERR_INVALID_ARG
+    assert call(args(Z=nul3)) == _lib.TC_ERR_INVALID_ARG
+    # a sweep needs r_l <= r_m1 r_m2
+    skew = (ctypes.c_int * 3)(1, 2, 7)
+    assert call(args(r=skew)) == _lib.TC_ERR_INVALID_ARG

@@ -1,0 +1,80 @@
+"""Parity of the canonical-to-Tucker transform (tc_canonical_to_tucker,
+Appendix part 1) with the oracle, through the C ABI, binary64.
+
+The oracle takes every dominant subspace from a full SVD; the GPU from
+orthogonal iteration and a Rayleigh-Ritz step.  Both fix each basis
+vector's sign the same way, so where the leading singular values are apart
+(relative gaps down to 3e-5 here) the bases agree entry by entry: a singular
+vector moves by about u sigma_1^2 / (sigma_i^2 - sigma_{i+1}^2).  The tests
+assert |dZ| <= 1e-9 per entry, |dbeta| <= 1e-9 max|beta|, the singular values
+to 1e-10 relative, and orthonormal rows."""
+import numpy as np
+import pytest
+
+from paper_1504_06289_amd import workloads as wl
+from tests.gpu_common import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def compare(tc, orc, c, A3, ranks, m_max, its=20):
+    Zg, bg, svg = tc.canonical_to_tucker(dev(c), [dev(a) for a in A3], ranks, m_max, its)
+    Zg = [host(z) for z in Zg]
+    bg = host(bg)
+    Zo, bo, svo = orc.canonical_to_tucker(c, A3, ranks, m_max)
+    for l in range(3):
+        s = svo[l]
+        r = ranks[l]
+        gaps = (s[:r] - s[1:r + 1]) / s[0] if len(s) > r else (s[:r - 1] - s[1:r]) / s[0]
+        dz = np.max(np.abs(Zg[l] - Zo[l]))
+        orth = np.max(np.abs(Zg[l] @ Zg[l].T - np.eye(r)))
+        dsv = np.max(np.abs(svg[l] - s[:r]) / s[0])
+        say(f"   mode {l}: min gap {gaps.min():.1e}  |dZ| {dz:.1e}  orth {orth:.1e}  "
+            f"dsv {dsv:.1e}")
+        assert orth <= 1e-13
+        assert dsv <= 1e-10
+        assert dz <= 1e-9
+    db = np.max(np.abs(bg - bo)) / np.max(np.abs(bo))
+    say(f"   |dbeta| / max|beta| = {db:.1e}")
+    assert db <= 1e-9
+    return Zg, bg
+
+
+@pytest.mark.parametrize("n,R,ranks,m_max", [((128, 96, 80), 60, (8, 6, 7), 2),
+                                              ((256, 256, 256), 200, (16, 16, 16), 2),
+                                              ((300, 200, 100), 150, (12, 10, 9), 1),
+                                              ((200, 150, 120), 90, (10, 10, 10), 0),
+                                              ((20, 12, 30), 40, (6, 5, 7), 2),
+                                              ((512, 512, 512), 400, (24, 20, 22), 1)])
+def test_c2t_density(tc, orc, n, R, ranks, m_max):
+    """A density in canonical format (Gaussian-product factors, weights in
+    [0.1, 1]): the rank reduction the transform is there for."""
+    say(f"c2t density n={n} R={R} ranks={ranks} m_max={m_max}")
+    V, d = wl.density(n, 7.0, R, seed=R)
+    compare(tc, orc, d, V, ranks, m_max)
+
+
+def test_c2t_exact_low_multilinear_rank(tc, orc):
+    """Side matrices spanning r_l-dimensional subspaces: the Tucker form
+    reproduces the tensor (checked on the full 3D grid)."""
+    rng = np.random.default_rng(3)
+    n3, r3, R = (40, 33, 27), (5, 4, 6), 70
+    A3 = [rng.standard_normal((R, r3[l])) @ rng.standard_normal((r3[l], n3[l])) for l in range(3)]
+    c = rng.uniform(0.5, 2.0, R)
+    say("c2t exact multilinear rank")
+    Zg, bg = compare(tc, orc, c, A3, r3, 2)
+    T = orc.canonical_full(c, A3)
+    assert np.max(np.abs(orc.tucker_full(Zg, bg) - T)) <= 1e-11 * np.max(np.abs(T))
+
+
+def test_c2t_few_terms_and_determinism(tc, orc):
+    """Fewer terms than the iterated subspace (R < k: the subspace is filled
+    with pseudo-random rows) and bitwise repeatable results."""
+    V, d = wl.density((90, 70, 60), 6.0, 10, seed=2)
+    say("c2t R=10 < k")
+    compare(tc, orc, d, V, (4, 4, 4), 1)
+    A = [dev(v) for v in V]
+    Z1, b1, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
+    Z2, b2, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
+    assert np.array_equal(host(b1), host(b2))
+    assert all(np.array_equal(host(x), host(y)) for x, y in zip(Z1, Z2))
