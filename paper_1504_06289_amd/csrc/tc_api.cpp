@@ -973,7 +973,8 @@ static int tucker_sub(int n, int r)
 // Workspace: [X: 64 x nmax][P: 64 x mmax][part: slices x 64 x max(nmax, mmax)]
 // [H: 64 x 64][lam: 64][Vt: 64 x 64][Ut: 3 x 48 x R][K: 48^2 x R][Mt: 48^2 x nmax]
 struct TuckerPlan {
-    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt;
+    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt, *D, *nrm, *Linv;
+    int *flag;
     size_t bytes;
 };
 
@@ -1006,6 +1007,14 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         need(r[l], n[l], k);
         need(r[l], R, n[l]);
         need(q, n[l], R);
+        for (int b0 = 0; b0 < k; b0 += kOrthBlock) {
+            const int bk = std::min(kOrthBlock, k - b0);
+            need(bk, bk, n[l]);
+            if (b0 > 0) {
+                need(bk, b0, n[l]);
+                need(bk, n[l], b0);
+            }
+        }
     }
     need(r[0], (long)r[1] * r[2], R);
     T.part = c.take<double>(part);
@@ -1016,6 +1025,10 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         T.Ut[l] = c.take<double>((size_t)r[l] * R);
     T.K = c.take<double>((size_t)rr * R);
     T.Mt = c.take<double>((size_t)rr * nmax);
+    T.D = c.take<double>((size_t)kOrthBlock * kTuckerMaxSub);
+    T.nrm = c.take<double>(kOrthBlock);
+    T.Linv = c.take<double>((size_t)kOrthBlock * kOrthBlock);
+    T.flag = c.take<int>(1);
     T.bytes = c.used;
     return T;
 }
@@ -1032,11 +1045,12 @@ static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int 
                                st) != hipSuccess)
         return TC_ERR_HIP;
     TRYK("random_rows", launch_random_rows(T.X, warm ? r : 0, k, n, salt, st));
-    TRYK("orth_rows", launch_orth_rows(T.X, k, n, salt + 1, st));
+    TRYK("orth_rows", launch_orth_rows(T.X, k, n, T.D, T.nrm, T.Linv, T.flag, T.part, salt + 1, st));
     for (int it = 0; it < its; ++it) {
         TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));  // X B^T
         TRYK("gemm_f64", launch_gemm_f64(true, T.P, B, T.X, k, n, m, T.part, st));   // (X B^T) B
-        TRYK("orth_rows", launch_orth_rows(T.X, k, n, salt + 2 + it, st));
+        TRYK("orth_rows", launch_orth_rows(T.X, k, n, T.D, T.nrm, T.Linv, T.flag, T.part,
+                                           salt + 2 + it, st));
     }
     TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));
     TRYK("gemm_f64", launch_gemm_f64(false, T.P, T.P, T.H, k, k, m, T.part, st));

@@ -189,10 +189,16 @@ int gemm_splits(int I, int N, int K);
 // nn: C[i][j] = sum_t A[i][t] B[t][j] (A [I][K], B [K][N]); otherwise
 // C[i][j] = sum_t A[i][t] B[j][t] (B [N][K]).  part: split-slice scratch, or
 // NULL for one slice.
+// sub: C -= the product instead of C = it.
 hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C, int I, int N,
-                           int K, double *part, hipStream_t st);
-// orthonormal rows of X [k][n] (k <= kTuckerMaxSub <= n), in place
-hipError_t launch_orth_rows(double *X, int k, int n, unsigned long long salt, hipStream_t st);
+                           int K, double *part, hipStream_t st, bool sub = false);
+// orthonormal rows of X [k][n] (k <= kTuckerMaxSub <= n), in place, in blocks
+// of kOrthBlock rows; scratch D [kOrthBlock][k], nrm [kOrthBlock],
+// Linv [kOrthBlock]^2, flag [1]; part as for launch_gemm_f64 (products
+// bk x b0 over n, bk x n over b0 and bk x bk over n)
+constexpr int kOrthBlock = 16;
+hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, double *Linv,
+                            int *flag, double *part, unsigned long long salt, hipStream_t st);
 // rows i0..k-1 of X [k][n] pseudo-random in [-1, 1)
 hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
                               hipStream_t st);

@@ -13,9 +13,15 @@
 //                 column), 64 x 64 tiles on binary64 matrix cores, the
 //                 contraction split over blockIdx.z into fixed slices whose
 //                 partial tiles are summed in order (bitwise reproducible);
-//   orth_rows     classical Gram-Schmidt applied twice to the rows of X in one
-//                 workgroup; a row that loses all but 1e-10 of its norm is
-//                 replaced by pseudo-random values and orthogonalised again;
+//   orth_rows     block Gram-Schmidt: each block of 16 rows is projected
+//                 against the earlier rows twice by matrix-core products, then
+//                 orthonormalised within the block by two Cholesky-QR passes
+//                 (block Gram, 16 x 16 Cholesky, column-parallel triangular
+//                 apply); where a row keeps less than 1e-4 of its norm the
+//                 block falls back, on the device, to classical Gram-Schmidt
+//                 applied twice in one workgroup, and a row that keeps less
+//                 than 1e-10 is replaced by pseudo-random values and
+//                 orthogonalised against every earlier row;
 //   jacobi_eig    cyclic Jacobi on a symmetric k x k matrix (k <= 64) held in
 //                 LDS, the k/2 disjoint rotations of a round-robin round at
 //                 once; eigenvalues sorted in decreasing order, eigenvectors
@@ -38,7 +44,7 @@ template <bool NN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict__ A,
                                                        const double *__restrict__ B,
                                                        double *__restrict__ C, int I, int N,
-                                                       int K, int kchunk)
+                                                       int K, int kchunk, int sub)
 {
     __shared__ double As[2][GT][GK + GPAD];
     __shared__ double Bs[2][GT][GK + GPAD];
@@ -148,15 +154,19 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double *__restrict_
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wi + x * 16 + lk + 4 * r;
-                if (i < I && j < N)
-                    Cs[(long)i * N + j] = acc[x][y][r];
+                if (i < I && j < N) {
+                    if (sub)
+                        Cs[(long)i * N + j] -= acc[x][y][r];
+                    else
+                        Cs[(long)i * N + j] = acc[x][y][r];
+                }
             }
         }
 }
 
 __global__ __launch_bounds__(256) void split_sum_kernel(const double *__restrict__ part,
                                                         double *__restrict__ C, long count,
-                                                        int S)
+                                                        int S, int sub)
 {
     const long e = (long)blockIdx.x * 256 + threadIdx.x;
     if (e >= count)
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const double *__restrict
     double s = 0.0;
     for (int z = 0; z < S; ++z)
         s += part[(long)z * count + e];
-    C[e] = s;
+    C[e] = sub ? C[e] - s : s;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -205,21 +215,30 @@ __device__ double block_sum(double v, double *red)
     return s;
 }
 
-__global__ __launch_bounds__(OT) void orth_rows_kernel(double *__restrict__ X, int k, int n,
-                                                       unsigned long long salt)
+// Rows b0 .. b0+bk-1 of X, already projected against the rows before b0:
+// two-pass classical Gram-Schmidt within the block.  A row left with less
+// than 1e-10 of its norm before any projection (nrm_pre, squared) lies in the
+// span of the rows before it: it is refilled with pseudo-random values and
+// orthogonalised against every earlier row of X.
+__global__ __launch_bounds__(OT) void orth_block_kernel(double *__restrict__ X, int b0, int bk,
+                                                        int n,
+                                                        const double *__restrict__ nrm_pre,
+                                                        const int *__restrict__ flag,
+                                                        unsigned long long salt)
 {
     __shared__ double red[OW][OJ + 1];
     __shared__ double dots[kTuckerMaxSub];
+    if (*flag == 0)
+        return;  // the Cholesky passes have orthonormalised the block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = 0; i < k; ++i) {
+    for (int il = 0; il < bk; ++il) {
+        const int i = b0 + il;
         double *xi = X + (long)i * n;
+        double ref = nrm_pre[il];
+        int jlo = b0;  // earlier rows still to project against
         for (int attempt = 0; attempt < 3; ++attempt) {
-            double ss = 0.0;
-            for (int a = tid; a < n; a += OT)
-                ss += xi[a] * xi[a];
-            const double nrm0 = block_sum(ss, &red[0][0]);
             for (int pass = 0; pass < 2; ++pass) {
-                for (int j0 = 0; j0 < i; j0 += OJ) {
+                for (int j0 = jlo; j0 < i; j0 += OJ) {
                     const int jc = min(OJ, i - j0);
                     double acc[OJ];
 #pragma unroll
@@ -241,38 +260,153 @@ __global__ __launch_bounds__(OT) void orth_rows_kernel(double *__restrict__ X, i
                     }
                     __syncthreads();
                     if (tid < jc) {
-                        double s = 0.0;
+                        double sum = 0.0;
                         for (int w = 0; w < OW; ++w)
-                            s += red[w][tid];
-                        dots[j0 + tid] = s;
+                            sum += red[w][tid];
+                        dots[j0 - jlo + tid] = sum;
                     }
                 }
                 __syncthreads();
                 for (int a = tid; a < n; a += OT) {
                     double v = xi[a];
-                    for (int j = 0; j < i; ++j)
-                        v -= dots[j] * X[(long)j * n + a];
+                    for (int j = jlo; j < i; ++j)
+                        v -= dots[j - jlo] * X[(long)j * n + a];
                     xi[a] = v;
                 }
                 __syncthreads();
             }
-            ss = 0.0;
+            double ss = 0.0;
             for (int a = tid; a < n; a += OT)
                 ss += xi[a] * xi[a];
             const double nrm = block_sum(ss, &red[0][0]);
-            if ((nrm > 1e-20 * nrm0 && nrm > 0.0) || attempt == 2) {
+            if ((nrm > 1e-20 * ref && nrm > 0.0) || attempt == 2) {
                 const double sc = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
                 for (int a = tid; a < n; a += OT)
                     xi[a] *= sc;
                 __syncthreads();
                 break;
             }
-            // the row lies (numerically) in the span of the earlier rows
-            for (int a = tid; a < n; a += OT)
-                xi[a] = hash_unit(salt + 7919ull * (attempt + 1), i, a);
-            __syncthreads();
+            // numerically in the span of the earlier rows: a fresh row,
+            // projected against all of them
+            ss = 0.0;
+            for (int a = tid; a < n; a += OT) {
+                const double v = hash_unit(salt + 7919ull * (attempt + 1), i, a);
+                xi[a] = v;
+                ss += v * v;
+            }
+            ref = block_sum(ss, &red[0][0]);
+            jlo = 0;
         }
     }
+}
+
+// Cholesky of the block Gram W [bk][bk] (bk <= kOrthBlock) and the inverse
+// of its factor.  First pass (ref = the squared row norms before any
+// projection): flag = 1 when a pivot keeps less than 1e-8 of its reference
+// (a row within 1e-4 of the span of the rows before it), and the Cholesky
+// passes are then skipped for the Gram-Schmidt fallback.  Second pass (ref
+// NULL): runs only where the first did not flag, and flags a non-positive
+// pivot the same way.
+__global__ __launch_bounds__(64) void chol_small_kernel(const double *__restrict__ W, int bk,
+                                                        const double *__restrict__ ref,
+                                                        int *__restrict__ flag,
+                                                        double *__restrict__ Linv)
+{
+    __shared__ double L[kOrthBlock][kOrthBlock + 1];
+    __shared__ double Li[kOrthBlock][kOrthBlock + 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (!ref && *flag)
+        return;
+    if (tid == 0) {
+        bad = 0;
+        for (int j = 0; j < bk; ++j) {
+            double d = W[j * bk + j];
+            for (int p = 0; p < j; ++p)
+                d -= L[j][p] * L[j][p];
+            const double lim = ref ? 1e-8 * ref[j] : 0.0;
+            if (!(d > lim) || !(d > 0.0)) {
+                bad = 1;
+                break;
+            }
+            const double ljj = sqrt(d);
+            L[j][j] = ljj;
+            for (int i = j + 1; i < bk; ++i) {
+                double v = 0.5 * (W[i * bk + j] + W[j * bk + i]);
+                for (int p = 0; p < j; ++p)
+                    v -= L[i][p] * L[j][p];
+                L[i][j] = v / ljj;
+            }
+        }
+        if (ref || bad)
+            *flag = bad;  // a failed second pass also hands the block to the fallback
+    }
+    __syncthreads();
+    if (bad)
+        return;
+    // columns of L^{-1} by forward substitution, one thread per column
+    if (tid < bk) {
+        const int c = tid;
+        for (int i = 0; i < bk; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int p = c; p < i; ++p)
+                v -= L[i][p] * Li[p][c];
+            Li[i][c] = i >= c ? v / L[i][i] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < bk * bk; e += 64)
+        Linv[e] = Li[e / bk][e % bk];
+}
+
+// X_B <- L^{-1} X_B, one thread per column (skipped when flagged)
+__global__ __launch_bounds__(256) void apply_linv_kernel(double *__restrict__ XB, int bk, int n,
+                                                         const double *__restrict__ Linv,
+                                                         const int *__restrict__ flag)
+{
+    __shared__ double Ls[kOrthBlock * kOrthBlock];
+    if (*flag)
+        return;
+    for (int e = threadIdx.x; e < bk * bk; e += 256)
+        Ls[e] = Linv[e];
+    __syncthreads();
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= n)
+        return;
+    double x[kOrthBlock];
+#pragma unroll
+    for (int i = 0; i < kOrthBlock; ++i)
+        x[i] = i < bk ? XB[(long)i * n + a] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kOrthBlock; ++i) {
+        if (i < bk) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < kOrthBlock; ++j)
+                if (j <= i)
+                    v += Ls[i * bk + j] * x[j];
+            XB[(long)i * n + a] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void row_norms_kernel(const double *__restrict__ X, int n,
+                                                        double *__restrict__ nrm)
+{
+    __shared__ double red[256];
+    const double *x = X + (long)blockIdx.x * n;
+    double s = 0.0;
+    for (int a = threadIdx.x; a < n; a += 256)
+        s += x[a] * x[a];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        nrm[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void random_rows_kernel(double *__restrict__ X, int i0, int k,
@@ -455,7 +589,7 @@ int gemm_splits(int I, int N, int K)
 }
 
 hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C, int I, int N,
-                           int K, double *part, hipStream_t st)
+                           int K, double *part, hipStream_t st, bool sub)
 {
     const int S = part ? gemm_splits(I, N, K) : 1;
     int kchunk = (K + S - 1) / S;
@@ -463,24 +597,54 @@ hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C,
     const int Sused = (K + kchunk - 1) / kchunk > 0 ? (K + kchunk - 1) / kchunk : 1;
     dim3 grid((N + GT - 1) / GT, (I + GT - 1) / GT, Sused);
     double *out = Sused > 1 ? part : C;
+    const int sub_here = Sused > 1 ? 0 : (int)sub;
     if (nn)
         hipLaunchKernelGGL(gemm_f64_kernel<true>, grid, dim3(256), 0, st, A, B, out, I, N, K,
-                           kchunk);
+                           kchunk, sub_here);
     else
         hipLaunchKernelGGL(gemm_f64_kernel<false>, grid, dim3(256), 0, st, A, B, out, I, N, K,
-                           kchunk);
+                           kchunk, sub_here);
     if (Sused > 1) {
         const long count = (long)I * N;
         hipLaunchKernelGGL(split_sum_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256),
-                           0, st, part, C, count, Sused);
+                           0, st, part, C, count, Sused, (int)sub);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_orth_rows(double *X, int k, int n, unsigned long long salt, hipStream_t st)
+hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, double *Linv,
+                            int *flag, double *part, unsigned long long salt, hipStream_t st)
 {
-    hipLaunchKernelGGL(orth_rows_kernel, dim3(1), dim3(OT), 0, st, X, k, n, salt);
-    return hipGetLastError();
+    for (int b0 = 0; b0 < k; b0 += kOrthBlock) {
+        const int bk = std::min(kOrthBlock, k - b0);
+        double *XB = X + (long)b0 * n;
+        hipLaunchKernelGGL(row_norms_kernel, dim3(bk), dim3(256), 0, st, XB, n, nrm);
+        for (int pass = 0; pass < 2 && b0 > 0; ++pass) {
+            // D = X_B X_prev^T, X_B -= D X_prev
+            hipError_t e = launch_gemm_f64(false, XB, X, D, bk, b0, n, part, st, false);
+            if (e != hipSuccess)
+                return e;
+            e = launch_gemm_f64(true, D, X, XB, bk, n, b0, part, st, true);
+            if (e != hipSuccess)
+                return e;
+        }
+        // two Cholesky passes within the block (W in D)
+        for (int pass = 0; pass < 2; ++pass) {
+            hipError_t e = launch_gemm_f64(false, XB, XB, D, bk, bk, n, part, st, false);
+            if (e != hipSuccess)
+                return e;
+            hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, st, D, bk,
+                               pass == 0 ? nrm : nullptr, flag, Linv);
+            hipLaunchKernelGGL(apply_linv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, XB,
+                               bk, n, Linv, flag);
+        }
+        hipLaunchKernelGGL(orth_block_kernel, dim3(1), dim3(OT), 0, st, X, b0, bk, n, nrm, flag,
+                           salt + 104729ull * b0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
