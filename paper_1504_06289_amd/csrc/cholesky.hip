@@ -73,26 +73,38 @@ __global__ __launch_bounds__(CT) void fit_column_reduce(const double *__restrict
 
 // y[l][k][s] = sum_t M^l_k[s][t] V^l[j][t] for the pivot j (one workgroup per
 // (l, k), threads over s)
-__global__ __launch_bounds__(CT) void tei_y_kernel(const double *__restrict__ V0,
-                                                   const double *__restrict__ V1,
-                                                   const double *__restrict__ V2,
-                                                   const double *__restrict__ M0,
-                                                   const double *__restrict__ M1,
-                                                   const double *__restrict__ M2, int R,
-                                                   int R_N, const int *__restrict__ state,
-                                                   double *__restrict__ y)
+// y^l_k = M^l_k v_j (v_j the pivot's row of V^l): workgroup (l k, row block)
+// takes 64 rows s, its 4 waves the t = g mod 4 terms of each, summed in a
+// fixed order.  M is symmetric: row s is read as column s, so that the
+// lanes' loads are contiguous.
+constexpr int kYRows = 64;
+constexpr int kYGroups = 4;
+
+__global__ __launch_bounds__(kYRows * kYGroups) void tei_y_kernel(
+    const double *__restrict__ V0, const double *__restrict__ V1, const double *__restrict__ V2,
+    const double *__restrict__ M0, const double *__restrict__ M1, const double *__restrict__ M2,
+    int R, int R_N, const int *__restrict__ state, double *__restrict__ y)
 {
+    __shared__ double red[kYGroups][kYRows + 1];
     if (state[1])
         return;
     const int l = blockIdx.x / R_N, k = blockIdx.x % R_N;
     const double *V = l == 0 ? V0 : (l == 1 ? V1 : V2);
     const double *M = (l == 0 ? M0 : (l == 1 ? M1 : M2)) + (long)k * R * R;
     const double *vj = V + (long)state[0] * R;
-    for (int s = threadIdx.x; s < R; s += CT) {
-        double acc = 0.0;
-        for (int t = 0; t < R; ++t)
-            acc = fma(M[(long)s * R + t], vj[t], acc);
-        y[((long)l * R_N + k) * R + s] = acc;
+    const int sl = threadIdx.x % kYRows, g = threadIdx.x / kYRows;
+    const int s = blockIdx.y * kYRows + sl;
+    double acc = 0.0;
+    if (s < R)
+        for (int t = g; t < R; t += kYGroups)
+            acc = fma(M[(long)t * R + s], vj[t], acc);
+    red[g][sl] = acc;
+    __syncthreads();
+    if (g == 0 && s < R) {
+        double v = red[0][sl];
+        for (int h = 1; h < kYGroups; ++h)
+            v += red[h][sl];
+        y[((long)l * R_N + k) * R + s] = v;
     }
 }
 
@@ -148,28 +160,42 @@ __global__ __launch_bounds__(CT) void tei_diag_kernel(const double *__restrict__
 
 // step r: L_r = (col - sum_{s<r} L_s L_s[p]) / sqrt(d[p]), zero on the
 // earlier pivots; d -= L_r^2; d[p] = 0
-__global__ __launch_bounds__(CT) void chol_step_kernel(const double *__restrict__ col,
-                                                       double *__restrict__ L, int N, int r,
-                                                       const int *__restrict__ piv,
-                                                       const int *__restrict__ state,
-                                                       double *__restrict__ d)
+// One step: column r of L at every index a, with the sum over the earlier
+// columns split over 16 waves (64 indices per workgroup) and added in a fixed
+// order; the earlier pivots (ispiv) get zero; the residual diagonal drops by
+// l^2 except at the pivot itself.
+constexpr int kStepA = 64;
+constexpr int kStepG = 16;
+
+__global__ __launch_bounds__(kStepA * kStepG) void chol_step_kernel(
+    const double *__restrict__ col, double *__restrict__ L, int N, int r,
+    const int *__restrict__ ispiv, const int *__restrict__ state, double *__restrict__ d)
 {
-    const int a = blockIdx.x * CT + threadIdx.x;
-    if (a >= N || state[1])
+    __shared__ double red[kStepG][kStepA + 1];
+    if (state[1])
         return;
+    const int al = threadIdx.x & (kStepA - 1), g = threadIdx.x / kStepA;
+    const int a = blockIdx.x * kStepA + al;
     const int p = state[0];
-    double v = col[a];
-    for (int s = 0; s < r; ++s)
-        v -= L[(long)s * N + a] * L[(long)s * N + p];
-    double l = v / sqrt(d[p]);
-    for (int s = 0; s < r; ++s)
-        if (piv[s] == a)
+    double sum = 0.0;
+    if (a < N)
+        for (int q = g; q < r; q += kStepG)
+            sum = fma(L[(long)q * N + a], L[(long)q * N + p], sum);
+    red[g][al] = sum;
+    __syncthreads();
+    if (g == 0 && a < N) {
+        double v = col[a];
+        for (int h = 0; h < kStepG; ++h)
+            v -= red[h][al];
+        double l = v / sqrt(d[p]);
+        if (ispiv[a] && a != p)
             l = 0.0;
-    L[(long)r * N + a] = l;
-    // every thread reads d[p], so the pivot's own entry is cleared by the
-    // next kernel (chol_select), not here
-    if (a != p)
-        d[a] -= l * l;
+        L[(long)r * N + a] = l;
+        // every thread reads d[p], so the pivot's own entry is cleared by the
+        // next kernel (chol_select), not here
+        if (a != p)
+            d[a] -= l * l;
+    }
 }
 
 // The largest residual diagonal entry (first index among equals) and the
@@ -240,27 +266,47 @@ __global__ void fill_int_kernel(int *__restrict__ x, int count, int value)
 }
 
 // piv[r] = the current pivot (unless done)
-__global__ void chol_record_kernel(int r, const int *__restrict__ state, int *__restrict__ piv)
+__global__ void chol_record_kernel(int r, const int *__restrict__ state, int *__restrict__ piv,
+                                   int *__restrict__ ispiv)
 {
-    if (threadIdx.x == 0 && !state[1])
+    if (threadIdx.x == 0 && !state[1]) {
         piv[r] = state[0];
+        ispiv[state[0]] = 1;
+    }
 }
 
 // fit result: T[r][s] = L_s[P[r]] is lower triangular (pivot order); for each
 // grid point a solve T^T u_a = (L_0[a], ..., L_{R-1}[a]) by back substitution
-// and store U[s][a] = u_a[s] (rows s >= R of U zero)
-__global__ __launch_bounds__(CT) void fit_u_kernel(const double *__restrict__ L, int n, int R,
-                                                   int R_max, const int *__restrict__ piv,
-                                                   double *__restrict__ U)
+// and store U[s][a] = u_a[s] (rows s >= R of U zero).  fit_t gathers T into
+// Tg[s][r] first, so that the substitution reads it at addresses common to
+// the whole wave; one thread per grid point, 64 per workgroup.
+__global__ __launch_bounds__(CT) void fit_t_kernel(const double *__restrict__ L, int n, int R,
+                                                   const int *__restrict__ piv,
+                                                   double *__restrict__ Tg)
 {
-    const int a = blockIdx.x * CT + threadIdx.x;
+    const long e = (long)blockIdx.x * CT + threadIdx.x;
+    if (e >= (long)R * R)
+        return;
+    const int s = (int)(e / R), r = (int)(e % R);
+    Tg[e] = L[(long)s * n + piv[r]];
+}
+
+constexpr int kFitUThreads = 64;
+
+__global__ __launch_bounds__(kFitUThreads) void fit_u_kernel(const double *__restrict__ L, int n,
+                                                             int R, int R_max,
+                                                             const double *__restrict__ Tg,
+                                                             double *__restrict__ U)
+{
+    const int a = blockIdx.x * kFitUThreads + threadIdx.x;
     if (a >= n)
         return;
     for (int s = R - 1; s >= 0; --s) {
+        const double *ts = Tg + (long)s * R;
         double v = L[(long)s * n + a];
         for (int r = s + 1; r < R; ++r)
-            v -= L[(long)s * n + piv[r]] * U[(long)r * n + a];  // T[r][s] u[r]
-        U[(long)s * n + a] = v / L[(long)s * n + piv[s]];        // T[s][s]
+            v -= ts[r] * U[(long)r * n + a];  // T[r][s] u[r]
+        U[(long)s * n + a] = v / ts[s];       // T[s][s]
     }
     for (int s = R; s < R_max; ++s)
         U[(long)s * n + a] = 0.0;
@@ -321,7 +367,8 @@ hipError_t launch_tei_column(const double *c, const double *const *V, const doub
                              int R, int R_N, int N_pair, const int *state, double *y, double *Z,
                              double *col, hipStream_t st)
 {
-    hipLaunchKernelGGL(tei_y_kernel, dim3(3 * R_N), dim3(CT), 0, st, V[0], V[1], V[2], M[0],
+    hipLaunchKernelGGL(tei_y_kernel, dim3(3 * R_N, (R + kYRows - 1) / kYRows),
+                       dim3(kYRows * kYGroups), 0, st, V[0], V[1], V[2], M[0],
                        M[1], M[2], R, R_N, state, y);
     const long plane = (long)N_pair * R_N;
     for (int l = 0; l < 3; ++l) {
@@ -336,11 +383,11 @@ hipError_t launch_tei_column(const double *c, const double *const *V, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
+hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *ispiv,
                             const int *state, double *d, hipStream_t st)
 {
-    hipLaunchKernelGGL(chol_step_kernel, dim3((N + CT - 1) / CT), dim3(CT), 0, st, col, L, N, r,
-                       piv, state, d);
+    hipLaunchKernelGGL(chol_step_kernel, dim3((N + kStepA - 1) / kStepA), dim3(kStepA * kStepG),
+                       0, st, col, L, N, r, ispiv, state, d);
     return hipGetLastError();
 }
 
@@ -359,17 +406,23 @@ hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_chol_record(int r, const int *state, int *piv, hipStream_t st)
+hipError_t launch_chol_record(int r, const int *state, int *piv, int *ispiv, hipStream_t st)
 {
-    hipLaunchKernelGGL(chol_record_kernel, dim3(1), dim3(64), 0, st, r, state, piv);
+    hipLaunchKernelGGL(chol_record_kernel, dim3(1), dim3(64), 0, st, r, state, piv, ispiv);
     return hipGetLastError();
 }
 
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
-                             int R_max, const int *piv, double *U, double *V, hipStream_t st)
+                             int R_max, const int *piv, double *Tg, double *U, double *V,
+                             hipStream_t st)
 {
-    hipLaunchKernelGGL(fit_u_kernel, dim3((n + CT - 1) / CT), dim3(CT), 0, st, L, n, R, R_max,
-                       piv, U);
+    if (R > 0) {
+        const long e = (long)R * R;
+        hipLaunchKernelGGL(fit_t_kernel, dim3((unsigned)((e + CT - 1) / CT)), dim3(CT), 0, st, L,
+                           n, R, piv, Tg);
+    }
+    hipLaunchKernelGGL(fit_u_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
+                       dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
     const long e = (long)N_pair * R_max;
     hipLaunchKernelGGL(fit_v_kernel, dim3((unsigned)((e + CT - 1) / CT)), dim3(CT), 0, st, F, n,
                        N_pair, R, R_max, piv, V);

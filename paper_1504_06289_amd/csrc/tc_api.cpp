@@ -684,7 +684,7 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
 // pivots, pivot state and statistics, and (fit only) the factor L.
 struct CholScratch {
     double *d, *col, *L, *y, *Yd, *stats;
-    int *piv, *state;
+    int *piv, *state, *ispiv;
 };
 
 CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
@@ -699,6 +699,7 @@ CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
     s.stats = c.take<double>(2);
     s.piv = c.take<int>(R_max);
     s.state = c.take<int>(3);
+    s.ispiv = c.take<int>(N);
     return s;
 }
 
@@ -724,6 +725,7 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
                hipStreamSynchronize(st) == hipSuccess;
     };
     TRYK("chol_init", launch_fill_int(s.state, 3, 0, st));
+    TRYK("chol_init", launch_fill_int(s.ispiv, N, 0, st));
     TRYK("chol_select", launch_chol_select(s.d, N, 0, 0, -1.0, R_max, s.state, s.stats, st));
     if (!fetch())
         return TC_ERR_HIP;
@@ -735,11 +737,11 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
     int r = 0;
     while (!state[1]) {
         for (int g = 0; g < kCholGroup && r < R_max; ++g, ++r) {
-            TRYK("chol_record", launch_chol_record(r, s.state, s.piv, st));
+            TRYK("chol_record", launch_chol_record(r, s.state, s.piv, s.ispiv, st));
             const tc_status cs = column(st);
             if (cs != TC_OK)
                 return cs;
-            TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.piv, s.state, s.d, st));
+            TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.ispiv, s.state, s.d, st));
             TRYK("chol_select", launch_chol_select(s.d, N, 1, r + 1, thr, R_max, s.state,
                                                    s.stats, st));
         }
@@ -761,7 +763,7 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
 size_t fit_ws(int n, int R_max)
 {
     Carver c(nullptr);
-    carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n);
+    carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n, (size_t)R_max * R_max);
     return c.used;
 }
 
@@ -918,7 +920,8 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
-    const CholScratch s = carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n);
+    const CholScratch s =
+        carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n, (size_t)R_max * R_max);
     TRYK("fit_diag", launch_fit_diag(F_dev, n, N_pair, s.d, st));
     auto column = [&](hipStream_t cst) -> tc_status {
         if (launch_fit_column(F_dev, n, N_pair, s.state, s.y, s.col, cst) != hipSuccess)
@@ -929,8 +932,8 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
                                          R_out, residual_out, st);
     if (r != TC_OK)
         return r;
-    TRYK("fit_finish", launch_fit_finish(F_dev, s.L, n, N_pair, *R_out, R_max, s.piv, U_dev,
-                                         V_dev, st));
+    TRYK("fit_finish", launch_fit_finish(F_dev, s.L, n, N_pair, *R_out, R_max, s.piv, s.Yd,
+                                         U_dev, V_dev, st));
     return hipStreamSynchronize(st) == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 

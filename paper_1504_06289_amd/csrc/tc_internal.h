@@ -169,20 +169,23 @@ hipError_t launch_tei_diag(const double *c, const double *const *V, const double
 hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
                              int R, int R_N, int N_pair, const int *state, double *y, double *Z,
                              double *col, hipStream_t st);
-hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *piv,
+// ispiv [N]: 1 at the pivots recorded so far (launch_chol_record sets them)
+hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *ispiv,
                             const int *state, double *d, hipStream_t st);
 // state = {pivot, done, steps}; see cholesky.hip
 hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
                               int *state, double *stats, hipStream_t st);
-hipError_t launch_chol_record(int r, const int *state, int *piv, hipStream_t st);
+hipError_t launch_chol_record(int r, const int *state, int *piv, int *ispiv, hipStream_t st);
 hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st);
+// Tg: scratch [R_max][R_max]
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
-                             int R_max, const int *piv, double *U, double *V, hipStream_t st);
+                             int R_max, const int *piv, double *Tg, double *U, double *V,
+                             hipStream_t st);
 
 // ---- canonical-to-Tucker pieces (tucker.hip) -------------------------------
 constexpr int kTuckerMaxSub = 64;   // rows of the iterated subspace
 constexpr int kTuckerMaxRank = 48;  // Tucker rank per mode
-constexpr int kGemmMaxSplit = 16;   // contraction slices of launch_gemm_f64
+constexpr int kGemmMaxSplit = 64;   // contraction slices of launch_gemm_f64
 // Slices launch_gemm_f64 uses for C [I][N] over K (part then holds
 // slices x I x N doubles).
 int gemm_splits(int I, int N, int K);

@@ -16,8 +16,8 @@
 //   orth_rows     block Gram-Schmidt: each block of 16 rows is projected
 //                 against the earlier rows twice by matrix-core products, then
 //                 orthonormalised within the block by two Cholesky-QR passes
-//                 (block Gram, 16 x 16 Cholesky, column-parallel triangular
-//                 apply); where a row keeps less than 1e-4 of its norm the
+//                 (block Gram, 16 x 16 Cholesky, column-parallel forward
+//                 substitution); where a row keeps less than 1e-4 of its norm the
 //                 block falls back, on the device, to classical Gram-Schmidt
 //                 applied twice in one workgroup, and a row that keeps less
 //                 than 1e-10 is replaced by pseudo-random values and
@@ -171,9 +171,16 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const double *__restrict
     const long e = (long)blockIdx.x * 256 + threadIdx.x;
     if (e >= count)
         return;
-    double s = 0.0;
-    for (int z = 0; z < S; ++z)
-        s += part[(long)z * count + e];
+    // eight interleaved sums (eight loads in flight), combined in a fixed order
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int z = 0;
+    for (; z + 8 <= S; z += 8)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            a[q] += part[(long)(z + q) * count + e];
+    for (; z < S; ++z)
+        a[0] += part[(long)z * count + e];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     C[e] = sub ? C[e] - s : s;
 }
 
@@ -300,75 +307,65 @@ __global__ __launch_bounds__(OT) void orth_block_kernel(double *__restrict__ X, 
     }
 }
 
-// Cholesky of the block Gram W [bk][bk] (bk <= kOrthBlock) and the inverse
-// of its factor.  First pass (ref = the squared row norms before any
+// Cholesky factor L of the block Gram W [bk][bk] (bk <= kOrthBlock),
+// right-looking, one column per barrier step (thread (i, k) updates the
+// trailing entry (i, k)).  First pass (ref = the squared row norms before any
 // projection): flag = 1 when a pivot keeps less than 1e-8 of its reference
 // (a row within 1e-4 of the span of the rows before it), and the Cholesky
 // passes are then skipped for the Gram-Schmidt fallback.  Second pass (ref
 // NULL): runs only where the first did not flag, and flags a non-positive
-// pivot the same way.
-__global__ __launch_bounds__(64) void chol_small_kernel(const double *__restrict__ W, int bk,
-                                                        const double *__restrict__ ref,
-                                                        int *__restrict__ flag,
-                                                        double *__restrict__ Linv)
+// pivot the same way.  Lout [bk][bk]: L (lower triangle).
+__global__ __launch_bounds__(kOrthBlock * kOrthBlock) void chol_small_kernel(
+    const double *__restrict__ W, int bk, const double *__restrict__ ref, int *__restrict__ flag,
+    double *__restrict__ Lout)
 {
-    __shared__ double L[kOrthBlock][kOrthBlock + 1];
-    __shared__ double Li[kOrthBlock][kOrthBlock + 1];
+    __shared__ double A[kOrthBlock][kOrthBlock + 1];
     __shared__ int bad;
     const int tid = threadIdx.x;
+    const int i = tid / kOrthBlock, k = tid % kOrthBlock;
     if (!ref && *flag)
         return;
-    if (tid == 0) {
+    if (i < bk && k < bk)
+        A[i][k] = 0.5 * (W[i * bk + k] + W[k * bk + i]);
+    if (tid == 0)
         bad = 0;
-        for (int j = 0; j < bk; ++j) {
-            double d = W[j * bk + j];
-            for (int p = 0; p < j; ++p)
-                d -= L[j][p] * L[j][p];
+    __syncthreads();
+    for (int j = 0; j < bk; ++j) {
+        if (tid == 0) {
+            const double d = A[j][j];
             const double lim = ref ? 1e-8 * ref[j] : 0.0;
-            if (!(d > lim) || !(d > 0.0)) {
+            if (!(d > lim) || !(d > 0.0))
                 bad = 1;
-                break;
-            }
-            const double ljj = sqrt(d);
-            L[j][j] = ljj;
-            for (int i = j + 1; i < bk; ++i) {
-                double v = 0.5 * (W[i * bk + j] + W[j * bk + i]);
-                for (int p = 0; p < j; ++p)
-                    v -= L[i][p] * L[j][p];
-                L[i][j] = v / ljj;
-            }
+            else
+                A[j][j] = sqrt(d);
         }
-        if (ref || bad)
-            *flag = bad;  // a failed second pass also hands the block to the fallback
+        __syncthreads();
+        if (bad)
+            break;
+        if (tid > j && tid < bk)
+            A[tid][j] /= A[j][j];
+        __syncthreads();
+        if (i > j && k > j && k <= i && i < bk)
+            A[i][k] -= A[i][j] * A[k][j];
+        __syncthreads();
     }
-    __syncthreads();
-    if (bad)
-        return;
-    // columns of L^{-1} by forward substitution, one thread per column
-    if (tid < bk) {
-        const int c = tid;
-        for (int i = 0; i < bk; ++i) {
-            double v = i == c ? 1.0 : 0.0;
-            for (int p = c; p < i; ++p)
-                v -= L[i][p] * Li[p][c];
-            Li[i][c] = i >= c ? v / L[i][i] : 0.0;
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < bk * bk; e += 64)
-        Linv[e] = Li[e / bk][e % bk];
+    if (tid == 0 && (ref || bad))
+        *flag = bad;  // a failed second pass also hands the block to the fallback
+    if (!bad && i < bk && k < bk)
+        Lout[i * bk + k] = k <= i ? A[i][k] : 0.0;
 }
 
-// X_B <- L^{-1} X_B, one thread per column (skipped when flagged)
+// X_B <- L^{-1} X_B by forward substitution, one thread per column (skipped
+// when flagged)
 __global__ __launch_bounds__(256) void apply_linv_kernel(double *__restrict__ XB, int bk, int n,
-                                                         const double *__restrict__ Linv,
+                                                         const double *__restrict__ L,
                                                          const int *__restrict__ flag)
 {
     __shared__ double Ls[kOrthBlock * kOrthBlock];
     if (*flag)
         return;
     for (int e = threadIdx.x; e < bk * bk; e += 256)
-        Ls[e] = Linv[e];
+        Ls[e] = L[e];
     __syncthreads();
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= n)
@@ -380,12 +377,13 @@ __global__ __launch_bounds__(256) void apply_linv_kernel(double *__restrict__ XB
 #pragma unroll
     for (int i = 0; i < kOrthBlock; ++i) {
         if (i < bk) {
-            double v = 0.0;
+            double v = x[i];
 #pragma unroll
             for (int j = 0; j < kOrthBlock; ++j)
-                if (j <= i)
-                    v += Ls[i * bk + j] * x[j];
-            XB[(long)i * n + a] = v;
+                if (j < i)
+                    v -= Ls[i * bk + j] * x[j];
+            x[i] = v / Ls[i * bk + i];
+            XB[(long)i * n + a] = x[i];
         }
     }
 }
@@ -633,8 +631,8 @@ hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, dou
             hipError_t e = launch_gemm_f64(false, XB, XB, D, bk, bk, n, part, st, false);
             if (e != hipSuccess)
                 return e;
-            hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, st, D, bk,
-                               pass == 0 ? nrm : nullptr, flag, Linv);
+            hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(kOrthBlock * kOrthBlock), 0, st,
+                               D, bk, pass == 0 ? nrm : nullptr, flag, Linv);
             hipLaunchKernelGGL(apply_linv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, XB,
                                bk, n, Linv, flag);
         }
