@@ -399,6 +399,12 @@ tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, 
  * the r_l-th and the (k+1)-th singular value the basis converges like
  * (sigma_{k+1}/sigma_{r_l})^{2 its}.  Each basis vector's entry of largest
  * magnitude is positive.
+ *   eps > 0 selects the epsilon truncation of step (A): mode l keeps the
+ *   singular vectors whose singular value is at least eps times the largest
+ *   (at least 1, at most r_l), each rank then clamped to the product of the
+ *   other two; basis rows and core entries beyond the chosen ranks are zero,
+ *   and the call synchronises `stream` once to read the singular values.
+ *   eps <= 0 keeps the ranks r.  r_out host [3] (or NULL): the ranks used.
  *   n host [3], 1 <= n_l <= TC_MAX_N; R >= 1 terms; c [R] device;
  *   A_dev host array [3] of device [R][n_l] (row k = the mode-l vector of
  *   term k); r host [3], 1 <= r_l <= min(48, n_l, R), and with m_max > 0
@@ -408,13 +414,14 @@ tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, 
  *   (the singular values of the last step of each mode) or NULL.
  *   ws    tc_canonical_to_tucker_workspace_bytes(n, R, r) bytes of device
  *         memory ((size_t)-1 for invalid sizes).
- * Runs on `stream`, stream-ordered, no synchronisation.
+ * Runs on `stream`, stream-ordered; no synchronisation unless eps > 0.
  */
 size_t tc_canonical_to_tucker_workspace_bytes(const int *n, int R, const int *r);
 tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
                                  const double *const *A_dev, const int *r, int m_max, int its,
-                                 double *const *Z_dev, double *beta_dev, double *sv_dev,
-                                 void *ws, size_t ws_bytes, void *stream);
+                                 double eps, double *const *Z_dev, double *beta_dev,
+                                 double *sv_dev, int *r_out, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /*
  * tc_lattice_sum -- assembled canonical vectors of the Newton kernel summed

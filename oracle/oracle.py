@@ -440,9 +440,25 @@ def _leading_left(Mt: np.ndarray, r: int):
     return _sign_rows(Z), s
 
 
-def canonical_to_tucker(c, A3, ranks, m_max: int):
+def tucker_ranks(sv3, ranks, eps: float):
+    """The epsilon truncation of step (A): per mode the number of singular
+    values of the side matrix at least eps times the largest (at least 1, at
+    most ranks[l]), then each clamped to the product of the other two so that
+    the alternating sweeps stay defined.  eps <= 0 keeps the given ranks."""
+    if eps <= 0:
+        return list(ranks)
+    r = [max(1, min(int(ranks[l]), int(np.sum(sv3[l] >= eps * sv3[l][0])))) for l in range(3)]
+    for l in range(3):
+        m1, m2 = [x for x in range(3) if x != l]
+        r[l] = min(r[l], r[m1] * r[m2])
+    return r
+
+
+def canonical_to_tucker(c, A3, ranks, m_max: int, eps: float = 0.0):
     """Returns (Z3 [r_l][n_l] each, beta [r1][r2][r3], sv3: singular values of
-    the last SVD of each mode)."""
+    the last SVD of each mode).  With eps > 0 the ranks are the epsilon
+    truncation of step (A) (tucker_ranks) and the outputs keep the shapes of
+    `ranks`, zero beyond the chosen ranks."""
     c = _f64(c)
     A3 = [_f64(a) for a in A3]
     # (A) dominant subspace of each side matrix; (B) projection
@@ -451,6 +467,9 @@ def canonical_to_tucker(c, A3, ranks, m_max: int):
         Z, s = _leading_left(A3[l], ranks[l])
         Z3.append(Z)
         sv3.append(s)
+    rk = tucker_ranks(sv3, ranks, eps)
+    for l in range(3):
+        Z3[l][rk[l]:] = 0.0
     Ut = [Z3[l] @ A3[l].T for l in range(3)]            # [r_l][R]
     # (C, D) alternating sweeps over the modes
     for _ in range(m_max):
@@ -461,6 +480,7 @@ def canonical_to_tucker(c, A3, ranks, m_max: int):
             K = (c[None, None, :] * Ut[m1][:, None, :] * Ut[m2][None, :, :]).reshape(-1, c.shape[0])
             Mt = K @ A3[l]                                # [r_m1 r_m2][n_l] = M^T
             Z3[l], sv3[l] = _leading_left(Mt, ranks[l])
+            Z3[l][rk[l]:] = 0.0
             Ut[l] = Z3[l] @ A3[l].T
     # (E) core
     beta = np.einsum("k,ik,jk,mk->ijm", c, Ut[0], Ut[1], Ut[2])

@@ -162,8 +162,9 @@ def lib() -> ctypes.CDLL:
         L.tc_canonical_to_tucker_workspace_bytes.argtypes = [pi, ctypes.c_int, pi]
         L.tc_canonical_to_tucker_workspace_bytes.restype = ctypes.c_size_t
         L.tc_canonical_to_tucker.argtypes = [pi, ctypes.c_int, vp, ctypes.POINTER(vp), pi,
-                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), vp,
-                                             vp, vp, ctypes.c_size_t, vp]
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                             ctypes.POINTER(vp), vp, vp, pi, vp, ctypes.c_size_t,
+                                             vp]
         L.tc_canonical_to_tucker.restype = ctypes.c_int
         L.tc_nuclear_workspace_bytes.argtypes = [ctypes.POINTER(TcNuclear)]
         L.tc_nuclear_workspace_bytes.restype = ctypes.c_size_t

@@ -114,10 +114,12 @@ def coulomb(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tens
 
 
 def canonical_to_tucker(c: torch.Tensor, A3: Sequence[torch.Tensor], ranks: Sequence[int],
-                        m_max: int = 2, its: int = 20):
+                        m_max: int = 2, its: int = 20, eps: float = 0.0):
     """tc_canonical_to_tucker: Tucker form of sum_k c_k a^1_k x a^2_k x a^3_k
     (A3[l] [R][n_l]).  Returns (Z3: [r_l][n_l] orthonormal rows, beta
-    [r1][r2][r3], sv: numpy singular values of the last step of each mode)."""
+    [r1][r2][r3], sv: numpy singular values of the last step of each mode,
+    the ranks used: `ranks`, or with eps > 0 the epsilon truncation, rows and
+    core entries beyond them zero)."""
     _dev_f64(c, "c")
     R = c.shape[0]
     dev = c.device
@@ -139,11 +141,12 @@ def canonical_to_tucker(c: torch.Tensor, A3: Sequence[torch.Tensor], ranks: Sequ
     ws = _workspace(ws_bytes, dev)
     av = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in A3])
     zv = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in Z3])
-    check(L.tc_canonical_to_tucker(ni, R, _ptr(c), av, ri, int(m_max), int(its), zv,
-                                   _ptr(beta), _ptr(sv), _ptr(ws), ws_bytes, _stream(dev)),
+    ro = (ctypes.c_int * 3)(0, 0, 0)
+    check(L.tc_canonical_to_tucker(ni, R, _ptr(c), av, ri, int(m_max), int(its), float(eps), zv,
+                                   _ptr(beta), _ptr(sv), ro, _ptr(ws), ws_bytes, _stream(dev)),
           "tc_canonical_to_tucker")
     s = sv.cpu().numpy()
-    return Z3, beta, [s[:r[0]], s[r[0]:r[0] + r[1]], s[r[0] + r[1]:]]
+    return Z3, beta, [s[:r[0]], s[r[0]:r[0] + r[1]], s[r[0] + r[1]:]], [int(x) for x in ro]
 
 
 def nuclear(c: torch.Tensor, p3: Sequence[torch.Tensor], U3: Sequence[torch.Tensor],

@@ -994,7 +994,7 @@ static int tucker_sub(int n, int r)
 // Workspace: [X: 64 x nmax][P: 64 x mmax][part: slices x 64 x max(nmax, mmax)]
 // [H: 64 x 64][lam: 64][Vt: 64 x 64][Ut: 3 x 48 x R][K: 48^2 x R][Mt: 48^2 x nmax]
 struct TuckerPlan {
-    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt, *D, *nrm, *Linv;
+    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt, *D, *nrm, *Linv, *lamA;
     int *flag;
     size_t bytes;
 };
@@ -1050,6 +1050,7 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
     T.nrm = c.take<double>(kOrthBlock);
     T.Linv = c.take<double>((size_t)kOrthBlock * kOrthBlock);
     T.flag = c.take<int>(1);
+    T.lamA = c.take<double>(3 * (size_t)kTuckerMaxSub);
     T.bytes = c.used;
     return T;
 }
@@ -1090,11 +1091,12 @@ size_t tc_canonical_to_tucker_workspace_bytes(const int *n, int R, const int *r)
 
 tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
                                  const double *const *A_dev, const int *r, int m_max, int its,
-                                 double *const *Z_dev, double *beta_dev, double *sv_dev,
-                                 void *ws, size_t ws_bytes, void *stream)
+                                 double eps, double *const *Z_dev, double *beta_dev,
+                                 double *sv_dev, int *r_out, void *ws, size_t ws_bytes,
+                                 void *stream)
 {
     if (!tucker_sizes_ok(n, R, r) || !c_dev || !A_dev || !Z_dev || !beta_dev || m_max < 0 ||
-        m_max > 100 || its < 1 || its > 1000)
+        m_max > 100 || its < 1 || its > 1000 || !std::isfinite(eps) || eps >= 1.0)
         return TC_ERR_INVALID_ARG;
     for (int l = 0; l < 3; ++l) {
         if (!A_dev[l] || !Z_dev[l])
@@ -1109,12 +1111,42 @@ tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
     hipStream_t st = (hipStream_t)stream;
     double *sv3[3] = {sv_dev, sv_dev ? sv_dev + r[0] : nullptr,
                       sv_dev ? sv_dev + r[0] + r[1] : nullptr};
-    // (A) dominant subspaces of the side matrices, (B) projections
+    // (A) dominant subspaces of the side matrices
+    int rk[3] = {r[0], r[1], r[2]};
     for (int l = 0; l < 3; ++l) {
         const tc_status s = dominant_rows(T, A_dev[l], R, n[l], r[l], its, false, Z_dev[l],
                                           sv3[l], 1000ull * (l + 1), st);
         if (s != TC_OK)
             return s;
+        if (eps > 0.0 && hipMemcpyAsync(T.lamA + l * kTuckerMaxSub, T.lam, sizeof(double) * r[l],
+                                        hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return TC_ERR_HIP;
+    }
+    if (eps > 0.0) {
+        // epsilon truncation: singular values sqrt(lam) against eps times the largest
+        double lam[3 * kTuckerMaxSub];
+        if (hipMemcpyAsync(lam, T.lamA, sizeof lam, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return TC_ERR_HIP;
+        for (int l = 0; l < 3; ++l) {
+            const double *ll = lam + l * kTuckerMaxSub;
+            const double s0 = std::sqrt(std::max(ll[0], 0.0));
+            int cnt = 0;
+            for (int i = 0; i < r[l]; ++i)
+                cnt += std::sqrt(std::max(ll[i], 0.0)) >= eps * s0;
+            rk[l] = std::max(1, std::min(r[l], cnt));
+        }
+        for (int l = 0; l < 3; ++l) {
+            const int m1 = l == 0 ? 1 : 0, m2 = l == 2 ? 1 : 2;
+            rk[l] = std::min(rk[l], rk[m1] * rk[m2]);
+        }
+    }
+    if (r_out)
+        for (int l = 0; l < 3; ++l)
+            r_out[l] = rk[l];
+    // (B) projections (basis rows beyond the chosen ranks zero)
+    for (int l = 0; l < 3; ++l) {
+        TRYK("zero_rows", launch_zero_rows(Z_dev[l], rk[l], r[l], n[l], st));
         TRYK("gemm_f64", launch_gemm_f64(false, Z_dev[l], A_dev[l], T.Ut[l], r[l], R, n[l],
                                          T.part, st));
     }
@@ -1131,6 +1163,7 @@ tc_status tc_canonical_to_tucker(const int *n, int R, const double *c_dev,
                               1000000ull + 1000ull * (3 * sweep + l), st);
             if (s != TC_OK)
                 return s;
+            TRYK("zero_rows", launch_zero_rows(Z_dev[l], rk[l], r[l], n[l], st));
             TRYK("gemm_f64", launch_gemm_f64(false, Z_dev[l], A_dev[l], T.Ut[l], r[l], R, n[l],
                                              T.part, st));
         }

@@ -205,6 +205,8 @@ hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, dou
 // rows i0..k-1 of X [k][n] pseudo-random in [-1, 1)
 hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
                               hipStream_t st);
+// rows i0..k-1 of X [k][n] set to zero
+hipError_t launch_zero_rows(double *X, int i0, int k, int n, hipStream_t st);
 // eigenpairs of the symmetric H [k][k] (k <= kTuckerMaxSub): lam decreasing,
 // Vt [k][k] rows the eigenvectors
 hipError_t launch_jacobi_eig(const double *H, int k, double *lam, double *Vt, hipStream_t st);

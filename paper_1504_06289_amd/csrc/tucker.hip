@@ -407,6 +407,14 @@ __global__ __launch_bounds__(256) void row_norms_kernel(const double *__restrict
         nrm[blockIdx.x] = red[0];
 }
 
+__global__ __launch_bounds__(256) void zero_rows_kernel(double *__restrict__ X, int i0, int k,
+                                                        int n)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e < (long)(k - i0) * n)
+        X[(long)i0 * n + e] = 0.0;
+}
+
 __global__ __launch_bounds__(256) void random_rows_kernel(double *__restrict__ X, int i0, int k,
                                                           int n, unsigned long long salt)
 {
@@ -653,6 +661,16 @@ hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long lon
         return hipSuccess;
     hipLaunchKernelGGL(random_rows_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
                        st, X, i0, k, n, salt);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(double *X, int i0, int k, int n, hipStream_t st)
+{
+    const long count = (long)(k - i0) * n;
+    if (count <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(zero_rows_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       X, i0, k, n);
     return hipGetLastError();
 }
 

@@ -338,14 +338,19 @@ def test_canonical_to_tucker_rejects(L):
     v = ctypes.c_void_p(0x1000)
     vp3 = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
     nul3 = (ctypes.c_void_p * 3)(0x1000, None, 0x1000)
-    args = lambda **kw: dict(dict(n=n, R=20, c=v, A=vp3, r=r, m_max=1, its=10, Z=vp3, beta=v), **kw)
+    args = lambda **kw: dict(dict(n=n, R=20, c=v, A=vp3, r=r, m_max=1, its=10, eps=0.0, Z=vp3,
+                                  beta=v), **kw)
+
     def call(a, ws=v, ws_bytes=1 << 40):
         return L.tc_canonical_to_tucker(a["n"], a["R"], a["c"], a["A"], a["r"], a["m_max"],
-                                        a["its"], a["Z"], a["beta"], None, ws, ws_bytes, None)
+                                        a["its"], a["eps"], a["Z"], a["beta"], None, None, ws,
+                                        ws_bytes, None)
     assert call(args(), ws=None, ws_bytes=0) == _lib.TC_ERR_WORKSPACE
     assert call(args(its=0)) == _lib.TC_ERR_INVALID_ARG
     assert call(args(m_max=-1)) == _lib.TC_ERR_INVALID_ARG
     assert call(args(A=nul3)) == _lib.TC_ERR_INVALID_ARG
+    assert call(args(eps=float("nan"))) == _lib.TC_ERR_INVALID_ARG
+    assert call(args(eps=1.0)) == _lib.TC_ERR_INVALID_ARG
     assert call(args(Z=nul3)) == _lib.TC_ERR_INVALID_ARG
     # a sweep needs r_l <= r_m1 r_m2
     skew = (ctypes.c_int * 3)(1, 2, 7)

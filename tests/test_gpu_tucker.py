@@ -17,18 +17,29 @@ from tests.gpu_common import dev, host, say
 pytestmark = pytest.mark.gpu
 
 
-def compare(tc, orc, c, A3, ranks, m_max, its=20):
-    Zg, bg, svg = tc.canonical_to_tucker(dev(c), [dev(a) for a in A3], ranks, m_max, its)
+def compare(tc, orc, c, A3, ranks, m_max, its=20, eps=0.0):
+    Zg, bg, svg, rg = tc.canonical_to_tucker(dev(c), [dev(a) for a in A3], ranks, m_max, its,
+                                             eps)
     Zg = [host(z) for z in Zg]
     bg = host(bg)
-    Zo, bo, svo = orc.canonical_to_tucker(c, A3, ranks, m_max)
+    Zo, bo, svo = orc.canonical_to_tucker(c, A3, ranks, m_max, eps)
+    if eps > 0:
+        # step (A)'s singular values, not too close to the threshold
+        sA = [np.linalg.svd(A3[l].T, compute_uv=False) for l in range(3)]
+        ro = orc.tucker_ranks(sA, ranks, eps)
+        say(f"   ranks: GPU {rg}, oracle {ro}")
+        assert rg == ro
+        for l in range(3):
+            rat = np.maximum(sA[l][:ranks[l]] / sA[l][0], 1e-300)
+            assert np.min(np.abs(np.log(rat / eps))) > 0.05
     for l in range(3):
         s = svo[l]
-        r = ranks[l]
+        r = rg[l] if eps > 0 else ranks[l]
         gaps = (s[:r] - s[1:r + 1]) / s[0] if len(s) > r else (s[:r - 1] - s[1:r]) / s[0]
         dz = np.max(np.abs(Zg[l] - Zo[l]))
-        orth = np.max(np.abs(Zg[l] @ Zg[l].T - np.eye(r)))
-        dsv = np.max(np.abs(svg[l] - s[:r]) / s[0])
+        orth = np.max(np.abs(Zg[l][:r] @ Zg[l][:r].T - np.eye(r)))
+        assert np.all(Zg[l][r:] == 0.0)
+        dsv = np.max(np.abs(svg[l][:r] - s[:r]) / s[0])
         say(f"   mode {l}: min gap {gaps.min():.1e}  |dZ| {dz:.1e}  orth {orth:.1e}  "
             f"dsv {dsv:.1e}")
         assert orth <= 1e-13
@@ -74,7 +85,25 @@ def test_c2t_few_terms_and_determinism(tc, orc):
     say("c2t R=10 < k")
     compare(tc, orc, d, V, (4, 4, 4), 1)
     A = [dev(v) for v in V]
-    Z1, b1, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
-    Z2, b2, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
+    Z1, b1, _, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
+    Z2, b2, _, _ = tc.canonical_to_tucker(dev(d), A, (4, 4, 4), 1)
     assert np.array_equal(host(b1), host(b2))
     assert all(np.array_equal(host(x), host(y)) for x, y in zip(Z1, Z2))
+
+
+def test_c2t_epsilon_truncation(tc, orc):
+    """The epsilon truncation of step (A): the true ranks of a tensor of low
+    multilinear rank from larger maximal ranks (full tensor reproduced), and
+    a density truncated at 0.29 of the largest singular value, against the
+    oracle's ranks, bases and core."""
+    rng = np.random.default_rng(4)
+    n3, r3, R = (40, 33, 27), (5, 4, 6), 70
+    A3 = [rng.standard_normal((R, r3[l])) @ rng.standard_normal((r3[l], n3[l])) for l in range(3)]
+    c = rng.uniform(0.5, 2.0, R)
+    say("c2t eps exact")
+    Zg, bg = compare(tc, orc, c, A3, (9, 8, 10), 1, eps=1e-9)
+    T = orc.canonical_full(c, A3)
+    assert np.max(np.abs(orc.tucker_full(Zg, bg) - T)) <= 1e-11 * np.max(np.abs(T))
+    V, d = wl.density((160, 120, 100), 7.0, 80, seed=6)
+    say("c2t eps density")
+    compare(tc, orc, d, V, (16, 16, 16), 1, eps=0.29)

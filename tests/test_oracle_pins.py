@@ -711,6 +711,10 @@ def test_canonical_to_tucker_recovers_low_multilinear_rank(orc):
         assert np.max(np.abs(orc.tucker_full(Z3, beta) - T)) <= 1e-12 * np.max(np.abs(T))
     Z3, beta, sv = orc.canonical_to_tucker(c, A3, n3, 1)
     assert np.max(np.abs(orc.tucker_full(Z3, beta) - T)) <= 1e-12 * np.max(np.abs(T))
+    # the epsilon truncation finds the multilinear rank from larger maximal ranks
+    Z3, beta, sv = orc.canonical_to_tucker(c, A3, (7, 8, 9), 2, eps=1e-10)
+    assert [int(np.sum(np.linalg.norm(z, axis=1) > 0.5)) for z in Z3] == list(r3)
+    assert np.max(np.abs(orc.tucker_full(Z3, beta) - T)) <= 1e-12 * np.max(np.abs(T))
 
 
 def test_canonical_to_tucker_sweep_is_the_unfolding_svd(orc):
