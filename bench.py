@@ -235,7 +235,7 @@ def mfma_pct(prof, w, prec, cls=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
