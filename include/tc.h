@@ -61,7 +61,7 @@ typedef enum {
     TC_OK = 0,
     TC_ERR_INVALID_ARG = 1, /* null pointer, size out of range, non-finite parameter */
     TC_ERR_WORKSPACE = 2,   /* workspace missing or smaller than tc_workspace_bytes */
-    TC_ERR_UNSUPPORTED = 3, /* precision or size this build does not implement */
+    TC_ERR_UNSUPPORTED = 3, /* precision or size the library does not implement */
     TC_ERR_HIP = 4          /* a HIP launch or runtime call failed */
 } tc_status;
 
