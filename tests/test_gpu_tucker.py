@@ -107,3 +107,26 @@ def test_c2t_epsilon_truncation(tc, orc):
     V, d = wl.density((160, 120, 100), 7.0, 80, seed=6)
     say("c2t eps density")
     compare(tc, orc, d, V, (16, 16, 16), 1, eps=0.29)
+
+
+@pytest.mark.parametrize("n3,R,ranks,m_max", [((1, 2, 3), 5, (1, 1, 1), 2),
+                                              ((1, 1, 1), 1, (1, 1, 1), 1),
+                                              ((7, 3, 9), 2, (2, 2, 2), 1)])
+def test_c2t_degenerate_sizes(tc, orc, n3, R, ranks, m_max):
+    """One cell in a mode (a subspace of k = n rows), a single term, and fewer
+    terms than the ranks' images: the full tensor is reproduced whenever the
+    ranks reach the multilinear rank."""
+    rng = np.random.default_rng(sum(n3) + R)
+    A3 = [rng.standard_normal((R, nl)) for nl in n3]
+    c = rng.uniform(0.5, 1.5, R)
+    say(f"c2t degenerate n={n3} R={R} ranks={ranks}")
+    Zg, bg, _, rg = tc.canonical_to_tucker(dev(c), [dev(a) for a in A3], ranks, m_max)
+    Zg = [host(z) for z in Zg]
+    bg = host(bg)
+    for l in range(3):
+        np.testing.assert_allclose(Zg[l] @ Zg[l].T, np.eye(ranks[l]), atol=1e-13)
+    T = orc.canonical_full(c, A3)
+    Zo, bo, _ = orc.canonical_to_tucker(c, A3, ranks, m_max)
+    To = orc.tucker_full(Zo, bo)
+    Tg = orc.tucker_full(Zg, bg)
+    assert np.max(np.abs(Tg - To)) <= 1e-12 * max(np.max(np.abs(T)), 1e-300)
