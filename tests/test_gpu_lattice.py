@@ -147,3 +147,27 @@ def test_lattice_energy_printed_table(tc, orc, row):
     say(f"   E = {E:.12e}  exact {Ee:.12e}  rel {abs(E - Ee) / Ee:.2e}  printed {printed:g}")
     assert abs(E - Ee) <= 1e-9 * Ee
     assert printed_value_holds(E, printed, digits, reading)
+
+
+def test_lattice_at_the_largest_grid(tc, orc):
+    """n0 L = 65536 cells per direction (the largest grid of the ABI), both
+    forms of the sum, and the energy against the oracle's weighted lags."""
+    for n0, L3, R_N in [(256, (256, 2, 1), 8), (4096, (16, 1, 3), 2)]:
+        say(f"lattice at the largest grid: n0={n0} L={L3} R_N={R_N}")
+        h = 2.0 / n0
+        c, p3 = kernel3(orc, n0, L3, h, R_N)
+        A3 = tc.lattice_sum([dev(p) for p in p3], n0, L3)
+        for l in range(3):
+            Ar = orc.lattice_sum(p3[l], n0, L3[l])
+            assert np.max(np.abs(host(A3[l]) - Ar)) <= 4 * L3[l] ** 2 * 2.0 ** -53 * np.abs(p3[l]).max()
+        E = tc.lattice_energy(dev(c), [dev(p) for p in p3], [h, h, h], n0, L3, 1.0)
+        w = c / h ** 6
+        T = np.ones(R_N)
+        for l in range(3):
+            T = T * orc.lattice_sum(p3[l], n0, L3[l])[:, np.arange(L3[l]) * n0 + n0 // 2].sum(1)
+        z = np.prod([p3[l][:, n0 * L3[l] - 1] for l in range(3)], axis=0)
+        Er = 0.5 * np.sum(w * (T - np.prod(L3) * z))
+        if np.prod(L3) == 1:
+            assert E == 0.0
+        else:
+            assert abs(E - Er) <= 1e-12 * abs(Er)

@@ -83,3 +83,21 @@ def test_nuclear_determinism_and_device_kernel(tc, orc):
     sc = scale(c_o, ps_o, w.h, w.U, Z, pos)
     # kernel vectors within 1e-12 relative of the oracle's
     assert worst(V1, Vr, sc) <= 5e-12
+
+
+def test_nuclear_largest_pair_count(tc, orc):
+    """2047 nuclei x 32 terms = 65504 (nucleus, term) pairs, the most the grid
+    of the diagonal Gram takes (the ABI limit is 65535), in 32 argument
+    chunks."""
+    w = wl.small_products((64, 48, 40), 8, R_N=32, b=5.0, seed=9)
+    c, ps = oracle_setup(orc, w)
+    rng = np.random.default_rng(2047)
+    M = 2047
+    Z = rng.uniform(0.5, 3.0, M)
+    pos = [[int(rng.integers(0, nl)) for nl in w.n] for _ in range(M)]
+    say(f"nuclear M={M} pairs={M * 32}")
+    V = run(tc, c, ps, w.U, w.h, Z, pos)
+    Vr = orc.nuclear(c, ps, w.h, w.U, Z, pos)
+    ratio = worst(V, Vr, scale(c, ps, w.h, w.U, Z, pos))
+    say(f"   max |dV| / scale = {ratio:.2e}")
+    assert ratio <= 1e-12
