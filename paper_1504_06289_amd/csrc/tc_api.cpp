@@ -299,16 +299,26 @@ tc_status int8fft_kernel_part(int n, int R_N, const double *p, const ModeScratch
 // same kernel vectors and n whose kernel part ran earlier on the same stream.
 // (Running the small smooth-term kernels before the convolution instead of
 // after the int8 Gram measured 0.1 ms slower per step with concurrent modes.)
-tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double *U, double *G,
+// The part of a mode that does not need the kernel part: twiddles (when
+// borrowing), the spectra of U and its int8 slices.
+tc_status int8fft_u_prep(int n, int R_f, int R_N, const double *U, const ModeScratch &s,
+                         bool borrowing, hipStream_t st)
+{
+    const int N = fft_length(n);
+    const OzakiLayout L = ozaki_layout(n, R_f, R_N);
+    if (borrowing)
+        TRYK("fft_twiddles", launch_fft_twiddles(s.twN, N, st));
+    TRYK("rfft_rows", launch_rfft_rows(U, R_f, n, N, s.twN, s.Uspec, st));
+    TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
+    return TC_OK;
+}
+
+tc_status int8fft_u_main(int n, int R_f, int R_N, const double *p, const double *U, double *G,
                          const ModeScratch &s, const ModeScratch &kp, bool mirror,
                          hipStream_t st)
 {
     const int N = fft_length(n);
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
-    if (&kp != &s)
-        TRYK("fft_twiddles", launch_fft_twiddles(s.twN, N, st));
-    TRYK("rfft_rows", launch_rfft_rows(U, R_f, n, N, s.twN, s.Uspec, st));
-    TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
     TRYK("fft_conv_split", launch_fft_conv(s.Uspec, kp.Cspec, n, N, R_f, R_N, s.twN, nullptr,
                                            s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, U, p,
                                            kp.cls, st));
@@ -320,6 +330,16 @@ tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double 
              launch_lowrank_gram(s.X, kp.S, kp.cls, s.Y, G, R_f, R_N, mirror, st));
     }
     return TC_OK;
+}
+
+tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double *U, double *G,
+                         const ModeScratch &s, const ModeScratch &kp, bool mirror,
+                         hipStream_t st)
+{
+    const tc_status r = int8fft_u_prep(n, R_f, R_N, U, s, &kp != &s, st);
+    if (r != TC_OK)
+        return r;
+    return int8fft_u_main(n, R_f, R_N, p, U, G, s, kp, mirror, st);
 }
 
 // G_k = U^T T_k U for all k of one mode (W is scratch).
@@ -532,6 +552,7 @@ struct BranchPool {
     hipStream_t st[kBranches] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kBranches] = {};
+    hipEvent_t kpart[3] = {};  // a mode's kernel part done (borrowed by later modes)
 };
 std::mutex g_pool_mu;
 BranchPool g_pool;
@@ -547,6 +568,9 @@ bool pool_init()
         return false;
     for (int b = 0; b < kBranches; ++b)
         if (hipEventCreateWithFlags(&g_pool.join[b], hipEventDisableTiming) != hipSuccess)
+            return false;
+    for (int l = 0; l < 3; ++l)
+        if (hipEventCreateWithFlags(&g_pool.kpart[l], hipEventDisableTiming) != hipSuccess)
             return false;
     g_pool.ok = true;
     return true;
@@ -567,11 +591,13 @@ bool profiling()
 // On the int8 FFT route a mode whose kernel vectors and n equal those of an
 // earlier mode (the same pointer: the common case of one grid spacing in all
 // three directions) reuses that mode's kernel part (spectra, term classes,
-// S_k) instead of recomputing it.  With concurrent modes the shared part runs
-// on st before the fork (measured 1% faster per step than three copies, one
-// per branch; a branch waiting on another branch's part measured slower).
-// The smooth-term Grams stay after the int8 Gram of their mode: moving them
-// first measured 2.5% slower.
+// S_k) instead of recomputing it.  With concurrent modes the owner computes
+// it first on its stream and records an event; a borrowing branch prepares
+// its own U (spectra, int8 slices) meanwhile and waits for the event only
+// before its convolution (2.59 -> 2.55 ms per step against computing the
+// shared part before the fork, which in turn beat three copies).  The
+// smooth-term Grams stay after the int8 Gram of their mode: moving them first
+// measured 2.5% slower.
 tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st,
                            bool split_plan = false)
 {
@@ -596,22 +622,8 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
     // A kernel part that other modes borrow runs once; with the modes on
     // branches it runs on the caller's stream before the fork, so that every
     // branch finds it complete.
-    bool before_fork[3] = {false, false, false};
-    if (split) {
-        for (int l = 0; l < 3; ++l) {
-            bool borrowed = false;
-            for (int m = l + 1; m < 3; ++m)
-                borrowed |= owner[m] == l && m != l;
-            if (owner[l] == l && borrowed) {
-                const tc_status r = int8fft_kernel_part(I.n[l], I.R_N, I.p[l], P.ms[l], st);
-                if (r != TC_OK)
-                    return r;
-                before_fork[l] = true;
-            }
-        }
-        if (hipEventRecord(g_pool.fork, st) != hipSuccess)
-            return TC_ERR_HIP;
-    }
+    if (split && hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
     tc_status status = TC_OK;
     for (int l = 0; l < 3 && status == TC_OK; ++l) {
         // the first mode stays on the caller's stream (no cross-queue wait
@@ -629,10 +641,19 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
             continue;
         }
         const int o = owner[l];
-        if (o == l && !before_fork[l])
+        if (o == l) {
             status = int8fft_kernel_part(I.n[l], I.R_N, I.p[l], P.ms[l], sl);
+            if (status == TC_OK && split && hipEventRecord(g_pool.kpart[l], sl) != hipSuccess)
+                status = TC_ERR_HIP;
+        }
         if (status == TC_OK)
-            status = int8fft_u_part(I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], Gl, P.ms[l], P.ms[o],
+            status = int8fft_u_prep(I.n[l], I.R_f, I.R_N, I.U[l], P.ms[l], o != l, sl);
+        // a borrowing branch waits for the owner's kernel part only now
+        if (status == TC_OK && split && o != l &&
+            hipStreamWaitEvent(sl, g_pool.kpart[o], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+        if (status == TC_OK)
+            status = int8fft_u_main(I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], Gl, P.ms[l], P.ms[o],
                                     mirror, sl);
     }
     if (split) {
