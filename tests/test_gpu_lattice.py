@@ -171,3 +171,27 @@ def test_lattice_at_the_largest_grid(tc, orc):
             assert E == 0.0
         else:
             assert abs(E - Er) <= 1e-12 * abs(Er)
+
+
+def test_lattice_sum_full_size_sampled(tc, orc):
+    """The bench configuration of the lattice sum (n0 = 268, L = 128 per
+    direction, n = 34304 cells, 190 terms; kernel vectors from the oracle):
+    sampled outputs against the sum over the lattice written out."""
+    import math
+    L, n0 = 128, 268
+    h = 2.0 / n0
+    lo, hu = math.log(1e-14), 0.25
+    R_N = int(math.ceil((math.log(2e4 / h) - lo) / hu)) + 1
+    say(f"lattice sum full size: n={n0 * L} R_N={R_N}")
+    t, a, c, ph = orc.newton_kernel(n0 * L, h, R_N, lo, hu)
+    p = dev(ph)
+    A3 = tc.lattice_sum([p, p, p], n0, (L, L, L))
+    A = host(A3[1])
+    n = n0 * L
+    rng = np.random.default_rng(5)
+    for _ in range(64):
+        q, i = int(rng.integers(0, R_N)), int(rng.integers(0, n))
+        terms = ph[q, i - (np.arange(L) * n0 + n0 // 2) + n - 1]
+        ref = math.fsum(terms)
+        assert abs(A[q, i] - ref) <= (L + 1) * 2.0 ** -53 * np.sum(np.abs(terms))
+    assert np.array_equal(host(A3[0]), A) and np.array_equal(host(A3[2]), A)
