@@ -744,3 +744,17 @@ def test_canonical_to_tucker_sweep_is_the_unfolding_svd(orc):
     assert e1 <= e0 * (1 + 1e-12)
     # the core of orthonormal bases holds the projected norm
     assert abs(np.linalg.norm(beta) - np.linalg.norm(beta_ref)) <= 1e-12 * np.linalg.norm(beta_ref)
+
+
+def test_tucker_ranks_threshold_and_clamp(orc):
+    """The epsilon truncation rule on given spectra: the count of singular
+    values at least eps times the largest, kept between 1 and the maximal
+    rank, then clamped to the product of the other two modes' ranks."""
+    sv = [np.array([1.0, 0.5, 0.1, 0.01, 1e-5]),
+          np.array([2.0, 1e-3, 1e-4, 1e-6, 1e-9]),
+          np.array([3.0, 2.9, 2.8, 2.7, 2.6])]
+    assert orc.tucker_ranks(sv, (5, 5, 5), 0.0) == [5, 5, 5]
+    assert orc.tucker_ranks(sv, (5, 5, 5), 0.05) == [3, 1, 3]   # mode 3: min(5, 3 * 1)
+    assert orc.tucker_ranks(sv, (2, 5, 5), 0.05) == [2, 1, 2]   # mode 3: min(5, 2 * 1)
+    assert orc.tucker_ranks(sv, (5, 5, 5), 1e-4) == [4, 2, 5]   # 1e-4 * 2 excludes 1e-4
+    assert orc.tucker_ranks(sv, (5, 5, 5), 0.99) == [1, 1, 1]   # at least one vector each
