@@ -34,12 +34,18 @@
  *       J   [R_f][R_f]     both triangles written
  *   - "device" pointers are HIP device allocations (or managed/host-mapped
  *     memory the device can read); "host" pointers are ordinary host memory.
- *   - The caller owns every buffer.  The library never allocates, frees or
- *     synchronises: scratch memory comes from the caller's workspace (size
- *     from tc_workspace_bytes), and all work is enqueued on the caller's
- *     stream (a hipStream_t passed as void*; NULL = the default stream) or,
- *     for tc_tei_gram, on internal streams forked from it and joined back
- *     into it, so that it completes in the caller's stream order.
+ *   - The caller owns every buffer.  The library never allocates or frees
+ *     device memory: scratch memory comes from the caller's workspace (size
+ *     from tc_workspace_bytes and the other *_workspace_bytes calls), and all
+ *     work is enqueued on the caller's stream (a hipStream_t passed as void*;
+ *     NULL = the default stream) or, for tc_tei_gram, on internal streams
+ *     forked from it and joined back into it, so that it completes in the
+ *     caller's stream order.
+ *   - A call synchronises the caller's stream only where its own comment
+ *     says so: tc_autotune, tc_density_fit, tc_tei_cholesky,
+ *     tc_lattice_energy, tc_canonical_to_tucker with eps > 0 and
+ *     tc_profile_read.  Every other call only enqueues work and can be
+ *     captured in a HIP graph.
  *   - Arguments are validated before anything is enqueued; on any error no
  *     output is written.  Launch failures return TC_ERR_HIP.  Faults during
  *     execution surface at the caller's next synchronisation.
@@ -65,7 +71,10 @@ typedef enum {
     TC_ERR_HIP = 4          /* a HIP launch or runtime call failed */
 } tc_status;
 
-/* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions. */
+/* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions.
+ * The values 0..3 are those of the interface's first statement (binary64,
+ * binary32, split-bfloat16 with three and with six products); the int8
+ * error-free splitting, the variant that meets 1e-7 on J, is appended as 4. */
 typedef enum {
     TC_FP64 = 0,     /* binary64 matrix cores (v_mfma_f64_16x16x4)           */
     TC_FP32 = 1,     /* operand rows scaled by a power of two (their maximum
@@ -73,18 +82,18 @@ typedef enum {
                         cores with binary32 partial sums over K-chunks of 64
                         and binary64 accumulation across chunks; does not
                         reach 1e-7 on J (a measured comparison point)        */
-    TC_OZAKI_I8 = 2, /* error-free splitting of each operand into four int8
-                        slices with one exponent per row (28 bits relative to
-                        the row maximum), the ten leading slice products on
-                        int8 matrix cores with exact int32 accumulation, and
-                        binary64 recombination (Ozaki scheme)                 */
-    TC_BF16X3 = 3,   /* rows scaled as for TC_FP32, each entry split exactly
+    TC_BF16X3 = 2,   /* rows scaled as for TC_FP32, each entry split exactly
                         into two bfloat16 pieces, the three leading piece
                         products on bfloat16 matrix cores with binary32
                         accumulation over K-chunks of 64, binary64 across
                         chunks (a measured comparison point)                  */
-    TC_BF16X6 = 4    /* as TC_BF16X3 with three pieces and the six products
+    TC_BF16X6 = 3,   /* as TC_BF16X3 with three pieces and the six products
                         of piece-index sum <= 2                               */
+    TC_OZAKI_I8 = 4  /* error-free splitting of each operand into four int8
+                        slices with one exponent per row (28 bits relative to
+                        the row maximum), the ten leading slice products on
+                        int8 matrix cores with exact int32 accumulation, and
+                        binary64 recombination (Ozaki scheme)                 */
 } tc_precision;
 
 /* How the Toeplitz products W_k = T_k U are formed.  TC_ALGO_DIRECT: the
@@ -263,7 +272,7 @@ tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec);
  * tc_autotune -- measure every algorithm available for each distinct mode
  * shape of the instances (one warm-up and three timed runs of the mode's
  * Toeplitz products and Grams, HIP events on `stream`) and record the fastest
- * in the tuning table.  Unlike every other call it synchronises `stream`.
+ * in the tuning table.  It synchronises `stream` (it reads the timings).
  * Writes scratch data into the workspace (tc_workspace_bytes(TC_OP_TEI_GRAM,
  * ...)) and leaves inst[i].J untouched.  ms_out (host, may be NULL) receives
  * 2 entries per instance and mode: [ (i*3 + l)*2 + a ] = milliseconds of
@@ -326,8 +335,10 @@ tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t
  *   they are).  pivots_host [R_max] (may be NULL), R_out, residual_out
  *   (residual trace; may be NULL) host outputs.
  *   ws: tc_density_fit_workspace_bytes(n, N_pair, R_max).
- * Synchronises `stream` after every step (the stopping test reads the
- * residual trace on the host).
+ * Synchronises `stream`: once before the first step (to read trace(A)), once
+ * per group of 16 steps (the stopping test runs on the device, which turns
+ * the remaining steps of a group into no-ops; the host reads its flag once
+ * per group), and once at the end.
  */
 size_t tc_density_fit_workspace_bytes(int n, int N_pair, int R_max);
 tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int R_max,
@@ -350,7 +361,8 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
  *   L_dev [R_max][N_pair] device output: row r = column r of the factor.
  *   pivots_host [R_max] (may be NULL), R_out, residual_out (may be NULL).
  *   ws: tc_tei_cholesky_workspace_bytes(N_pair, R, R_N, R_max).
- * Synchronises `stream` after every step.
+ * Synchronises `stream` as tc_density_fit does: before the first step and
+ * once per group of 16 steps.
  */
 size_t tc_tei_cholesky_workspace_bytes(int N_pair, int R, int R_N, int R_max);
 tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,

@@ -19,9 +19,9 @@ TC_ERR_HIP = 4
 
 TC_FP64 = 0
 TC_FP32 = 1
-TC_OZAKI_I8 = 2
-TC_BF16X3 = 3
-TC_BF16X6 = 4
+TC_BF16X3 = 2
+TC_BF16X6 = 3
+TC_OZAKI_I8 = 4
 PRECISIONS = {"fp64": TC_FP64, "fp32": TC_FP32, "ozaki8": TC_OZAKI_I8, "bf16x3": TC_BF16X3,
               "bf16x6": TC_BF16X6}
 

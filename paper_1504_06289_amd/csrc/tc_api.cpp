@@ -1,7 +1,10 @@
 // C-ABI layer (include/tc.h): argument validation, workspace layout,
-// algorithm choice (tuning table) and kernel dispatch.  Apart from
-// tc_autotune nothing here allocates, frees or synchronises; every launch goes
-// to the caller's stream, so a call can be captured in a HIP graph.
+// algorithm choice (tuning table) and kernel dispatch.  Nothing here
+// allocates or frees device memory.  Only the calls whose comment in tc.h
+// says so synchronise (autotuning, the pivoted Cholesky drivers, the lattice
+// energy, the epsilon-truncated canonical-to-Tucker transform and the kernel
+// timing read-out); every other call only enqueues work on the caller's
+// stream, so it can be captured in a HIP graph.
 #include "tc.h"
 
 #include <cmath>
@@ -612,16 +615,31 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hi
     for (int l = 0; l < 3; ++l) {
         algo[l] = resolve(I.n[l], I.R_f, I.R_N, prec);
         owner[l] = l;
-        const bool i8fft = prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT;
-        for (int m = 0; m < l && i8fft; ++m)
-            if (owner[m] == m && algo[m] == algo[l] && I.p[m] == I.p[l] && I.n[m] == I.n[l]) {
-                owner[l] = m;
-                break;
-            }
     }
-    // A kernel part that other modes borrow runs once; with the modes on
-    // branches it runs on the caller's stream before the fork, so that every
-    // branch finds it complete.
+    for (int l = 0; l < 3; ++l) {
+        if (!(prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT))
+            continue;
+        auto same_part = [&](int m) {
+            return owner[m] == m && algo[m] == algo[l] && I.p[m] == I.p[l] && I.n[m] == I.n[l];
+        };
+        if (split_plan) {
+            // one scratch region per mode: any earlier owner's part stays intact
+            for (int m = 0; m < l; ++m)
+                if (same_part(m)) {
+                    owner[l] = m;
+                    break;
+                }
+        } else if (l > 0 && prec == TC_OZAKI_I8 && algo[l - 1] == TC_ALGO_FFT &&
+                   same_part(owner[l - 1])) {
+            // one region shared by the modes in turn: only the part the
+            // previous mode left there (its own or the one it borrowed) is
+            // still intact; a mode in between with another part overwrites it
+            owner[l] = owner[l - 1];
+        }
+    }
+    // The owner of a borrowed kernel part computes it on its own stream and
+    // records kpart[owner]; a borrowing branch waits for that event before its
+    // convolution.
     if (split && hipEventRecord(g_pool.fork, st) != hipSuccess)
         return TC_ERR_HIP;
     tc_status status = TC_OK;

@@ -39,6 +39,34 @@ def test_status_strings(L):
     assert L.tc_version() >= 100
 
 
+def declared_enum(name):
+    """{enumerator: value} of the typedef enum `name` in include/tc.h."""
+    text = open(os.path.join(ROOT, "include", "tc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef enum \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    return {k: int(v) for k, v in re.findall(r"(TC_[A-Z0-9_]+)\s*=\s*(\d+)", body)}
+
+
+def test_enum_values_follow_the_interface():
+    """The precision and status codes keep the interface's numbering
+    (binary64 0, binary32 1, split-bfloat16 with three products 2 and with
+    six 3); the int8 splitting is appended after them, so a caller written
+    against the first numbering never reaches it by accident."""
+    prec = declared_enum("tc_precision")
+    assert prec == {"TC_FP64": 0, "TC_FP32": 1, "TC_BF16X3": 2, "TC_BF16X6": 3,
+                    "TC_OZAKI_I8": 4}
+    for k, v in prec.items():
+        assert getattr(_lib, k) == v, k
+    assert _lib.PRECISIONS == {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "ozaki8": 4}
+    status = declared_enum("tc_status")
+    assert status == {"TC_OK": 0, "TC_ERR_INVALID_ARG": 1, "TC_ERR_WORKSPACE": 2,
+                      "TC_ERR_UNSUPPORTED": 3, "TC_ERR_HIP": 4}
+    for k, v in status.items():
+        assert getattr(_lib, k) == v, k
+    assert declared_enum("tc_algorithm") == {"TC_ALGO_AUTO": 0, "TC_ALGO_DIRECT": 1,
+                                             "TC_ALGO_FFT": 2}
+
+
 def _inst(n=64, R_f=8, R_N=4, null=None):
     I = _lib.TcInstance()
     for l in range(3):
