@@ -163,6 +163,7 @@ typedef struct {
 #define TC_OP_CONVOLVE 0
 #define TC_OP_TEI_GRAM 1
 #define TC_OP_TEI_GRAM_BACKWARD 2
+#define TC_OP_AUTOTUNE 3   /* tc_autotune: every route of every mode may run */
 
 /*
  * tc_newton_kernel -- rank-R_N canonical Newton kernel on an n-cell grid of
@@ -273,7 +274,7 @@ tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec);
  * shape of the instances (one warm-up and three timed runs of the mode's
  * Toeplitz products and Grams, HIP events on `stream`) and record the fastest
  * in the tuning table.  It synchronises `stream` (it reads the timings).
- * Writes scratch data into the workspace (tc_workspace_bytes(TC_OP_TEI_GRAM,
+ * Writes scratch data into the workspace (tc_workspace_bytes(TC_OP_AUTOTUNE,
  * ...)) and leaves inst[i].J untouched.  ms_out (host, may be NULL) receives
  * 2 entries per instance and mode: [ (i*3 + l)*2 + a ] = milliseconds of
  * algorithm a (0 = direct, 1 = FFT; negative if unavailable).

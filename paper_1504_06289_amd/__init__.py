@@ -4,7 +4,8 @@ two-electron-integral Gram assembly of Khoromskaia & Khoromskij
 Python binding (see api.py) plus the seeded synthetic workloads."""
 from .api import (TeiGram, TeiGramGraph, autotune, autotune_batched,  # noqa: F401
                   canonical_to_tucker, convolve,
-                  coulomb, density_fit, lattice_energy, lattice_sum, newton_kernel, nuclear,
+                  coulomb, density_fit, lattice_energy, lattice_sum, make_instance,
+                  newton_kernel, nuclear,
                   profile_enable, profile_read,
                   tei_cholesky, tei_gram, tei_gram_backward, tei_gram_batched, term_classes,
                   tune_get, tune_set)

@@ -28,6 +28,7 @@ PRECISIONS = {"fp64": TC_FP64, "fp32": TC_FP32, "ozaki8": TC_OZAKI_I8, "bf16x3":
 TC_OP_CONVOLVE = 0
 TC_OP_TEI_GRAM = 1
 TC_OP_TEI_GRAM_BACKWARD = 2
+TC_OP_AUTOTUNE = 3
 
 # the ABI symbols declared in include/tc.h
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",

@@ -429,7 +429,7 @@ def autotune(c: torch.Tensor, p3, U3, prec="fp64"):
     inst = make_instance(c, p3, U3, J, None)
     arr = (TcInstance * 1)(inst)
     L = _lib.lib()
-    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _prec(prec))
+    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_AUTOTUNE, arr, 1, _prec(prec))
     ws = _workspace(ws_bytes, dev)
     ms = np.zeros(6)
     check(L.tc_autotune(arr, 1, _prec(prec), _ptr(ws), ws_bytes, _stream(dev),
@@ -450,8 +450,7 @@ def autotune_batched(instances, prec="fp64"):
         arr[i] = make_instance(c, p3, U3, J, None)
         Js.append(J)
     L = _lib.lib()
-    ws_bytes = max(L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, (TcInstance * 1)(arr[i]), 1,
-                                        _prec(prec)) for i in range(len(instances)))
+    ws_bytes = L.tc_workspace_bytes(_lib.TC_OP_AUTOTUNE, arr, len(instances), _prec(prec))
     ws = _workspace(ws_bytes, dev)
     ms = np.zeros(6 * len(instances))
     check(L.tc_autotune(arr, len(instances), _prec(prec), _ptr(ws), ws_bytes, _stream(dev),

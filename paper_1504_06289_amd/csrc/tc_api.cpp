@@ -407,7 +407,7 @@ struct InstancePlan {
 };
 
 InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bool backward,
-                           bool split = false)
+                           bool split = false, bool by_route = false)
 {
     InstancePlan P{};
     Carver c(ws);
@@ -425,15 +425,26 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
         if (np > 0)
             P.part = c.take<double>(np);
     }
+    // binary64 W: every route but the forward int8 FFT route, which writes
+    // the int8 slices of W straight from the convolution; by_route == false
+    // keeps it for every mode (any route may run: the autotuner)
+    bool needW[3];
+    for (int l = 0; l < 3; ++l)
+        needW[l] = backward || !by_route ||
+                   !(prec == TC_OZAKI_I8 && resolve(I.n[l], I.R_f, I.R_N, prec) == TC_ALGO_FFT);
     if (split) {
         for (int l = 0; l < 3; ++l) {
-            P.W[l] = c.take<double>((size_t)I.R_N * I.R_f * I.n[l]);
+            P.W[l] = needW[l] ? c.take<double>((size_t)I.R_N * I.R_f * I.n[l]) : nullptr;
             P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true);
         }
         P.bytes = c.used;
         return P;
     }
-    P.W[0] = P.W[1] = P.W[2] = c.take<double>((size_t)I.R_N * I.R_f * max_n(I));
+    size_t wn = 0;
+    for (int l = 0; l < 3; ++l)
+        if (needW[l] && (size_t)I.n[l] > wn)
+            wn = I.n[l];
+    P.W[0] = P.W[1] = P.W[2] = wn ? c.take<double>((size_t)I.R_N * I.R_f * wn) : nullptr;
     const size_t scratch0 = c.used;
     size_t scratch_max = 0;
     for (int l = 0; l < 3; ++l) {
@@ -539,7 +550,7 @@ BatchPlan plan_batch(const tc_instance *inst, int count, tc_precision prec)
                 best = b;
         B.branch[i] = best;
         load[best] += instance_cost(inst[i]);
-        const size_t wi = plan_instance(nullptr, inst[i], prec, false).bytes;
+        const size_t wi = plan_instance(nullptr, inst[i], prec, false, false, true).bytes;
         if (wi > need[best])
             need[best] = wi;
     }
@@ -601,10 +612,14 @@ bool profiling()
 // shared part before the fork, which in turn beat three copies).  The
 // smooth-term Grams stay after the int8 Gram of their mode: moving them first
 // measured 2.5% slower.
-tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, hipStream_t st,
-                           bool split_plan = false)
+tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, size_t ws_bytes,
+                           hipStream_t st, bool split_plan = false)
 {
-    const InstancePlan P = plan_instance(ws, I, prec, false, split_plan);
+    const InstancePlan P = plan_instance(ws, I, prec, false, split_plan, true);
+    // the plan follows the tuning table: a table changed since the caller
+    // sized the workspace may need more
+    if (P.bytes > ws_bytes)
+        return TC_ERR_WORKSPACE;
     const size_t F2 = (size_t)I.R_f * I.R_f;
     const bool split = split_plan && !profiling();
     // the Hadamard sum reads only the upper triangles: the lower ones are
@@ -816,6 +831,62 @@ size_t tei_chol_ws(int N_pair, int R, int R_N, int R_max)
 
 }  // namespace
 
+namespace tc {
+// tc_tei_gram on a given workspace
+tc_status tei_gram_check(const tc_instance *inst, int count, tc_precision prec)
+{
+    if (!inst || count < 1 || !prec_known(prec))
+        return TC_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i)
+        if (!instance_ok(inst[i]))
+            return TC_ERR_INVALID_ARG;
+    if (!prec_supported(prec))
+        return TC_ERR_UNSUPPORTED;
+    return TC_OK;
+}
+
+tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    const tc_status chk = tei_gram_check(inst, count, prec);
+    if (chk != TC_OK)
+        return chk;
+    const size_t need = tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return TC_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!pool_init())
+        return TC_ERR_HIP;
+    if (count == 1)  // one instance: its three modes on three branches
+        return forward_instance(inst[0], prec, ws, ws_bytes, st, true);
+
+    const BatchPlan B = plan_batch(inst, count, prec);
+    if (B.bytes > ws_bytes)
+        return TC_ERR_WORKSPACE;
+    // fork: every branch waits for the work already queued on the caller's stream
+    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
+            return TC_ERR_HIP;
+    tc_status status = TC_OK;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const int b = B.branch[i];
+        const size_t end = b + 1 < kBranches ? B.offset[b + 1] : B.bytes;
+        status = forward_instance(inst[i], prec, (char *)ws + B.offset[b], end - B.offset[b],
+                                  g_pool.st[b]);
+    }
+    // join (also after a failed launch, so no branch is left forked)
+    for (int b = 0; b < kBranches; ++b) {
+        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+    }
+    return status;
+}
+}  // namespace tc
+
 extern "C" {
 
 const char *tc_status_string(tc_status s)
@@ -846,7 +917,7 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
             return (size_t)-1;
         return convolve_ws(inst[0].n[0], inst[0].R_f, inst[0].R_N, prec);
     }
-    if (op != TC_OP_TEI_GRAM && op != TC_OP_TEI_GRAM_BACKWARD)
+    if (op != TC_OP_TEI_GRAM && op != TC_OP_TEI_GRAM_BACKWARD && op != TC_OP_AUTOTUNE)
         return (size_t)-1;
     for (int i = 0; i < count; ++i)
         for (int l = 0; l < 3; ++l)
@@ -854,11 +925,14 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
                 return (size_t)-1;
     if (op == TC_OP_TEI_GRAM)
         return count > 1 ? plan_batch(inst, count, prec).bytes
-                         : plan_instance(nullptr, inst[0], prec, false, true).bytes;
+                         : plan_instance(nullptr, inst[0], prec, false, true, true).bytes;
     size_t w = 0;
     for (int i = 0; i < count; ++i) {
-        const size_t wi =
-            plan_instance(nullptr, inst[i], prec, op == TC_OP_TEI_GRAM_BACKWARD).bytes;
+        // the autotuner's Grams go to the workspace, never to G_saved
+        tc_instance Ii = inst[i];
+        if (op == TC_OP_AUTOTUNE)
+            Ii.G_saved = nullptr;
+        const size_t wi = plan_instance(nullptr, Ii, prec, op == TC_OP_TEI_GRAM_BACKWARD).bytes;
         if (wi > w)
             w = wi;
     }
@@ -1374,42 +1448,7 @@ tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t
 tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec, void *ws,
                       size_t ws_bytes, void *stream)
 {
-    if (!inst || count < 1 || !prec_known(prec))
-        return TC_ERR_INVALID_ARG;
-    for (int i = 0; i < count; ++i)
-        if (!instance_ok(inst[i]))
-            return TC_ERR_INVALID_ARG;
-    if (!prec_supported(prec))
-        return TC_ERR_UNSUPPORTED;
-    const size_t need = tc_workspace_bytes(TC_OP_TEI_GRAM, inst, count, prec);
-    if (need > 0 && (!ws || ws_bytes < need))
-        return TC_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (!pool_init())
-        return TC_ERR_HIP;
-    if (count == 1)  // one instance: its three modes on three branches
-        return forward_instance(inst[0], prec, ws, st, true);
-
-    const BatchPlan B = plan_batch(inst, count, prec);
-    // fork: every branch waits for the work already queued on the caller's stream
-    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
-        return TC_ERR_HIP;
-    for (int b = 0; b < kBranches; ++b)
-        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
-            return TC_ERR_HIP;
-    tc_status status = TC_OK;
-    for (int i = 0; i < count && status == TC_OK; ++i) {
-        const int b = B.branch[i];
-        status = forward_instance(inst[i], prec, (char *)ws + B.offset[b], g_pool.st[b]);
-    }
-    // join (also after a failed launch, so no branch is left forked)
-    for (int b = 0; b < kBranches; ++b) {
-        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
-            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
-            status = TC_ERR_HIP;
-    }
-    return status;
+    return tc::tei_gram_call(inst, count, prec, ws, ws_bytes, stream);
 }
 
 tc_status tc_tei_gram_backward(const tc_instance *inst, int count, const double *const *Jbar,
@@ -1451,14 +1490,7 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
     if (!prec_supported(prec))
         return TC_ERR_UNSUPPORTED;
     // the Grams of the measurement runs go to the workspace, never to G_saved
-    size_t need = 0;
-    for (int i = 0; i < count; ++i) {
-        tc_instance scratchI = inst[i];
-        scratchI.G_saved = nullptr;
-        const size_t wi = plan_instance(nullptr, scratchI, prec, false).bytes;
-        if (wi > need)
-            need = wi;
-    }
+    const size_t need = tc_workspace_bytes(TC_OP_AUTOTUNE, inst, count, prec);
     if (!ws || ws_bytes < need)
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;

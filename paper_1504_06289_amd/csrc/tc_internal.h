@@ -257,3 +257,14 @@ hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls,
                                double *G, int R_f, int R_N, bool mirror, hipStream_t stream);
 
 }  // namespace tc
+
+// ---- the C-ABI's TEI Gram call on a given workspace (tc_api.cpp) ----------
+#include "tc.h"
+namespace tc {
+// the argument checks of tc_tei_gram (no device call)
+tc_status tei_gram_check(const tc_instance *inst, int count, tc_precision prec);
+// tc_tei_gram on the workspace ws of ws_bytes bytes: validation, plans,
+// dispatch.
+tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, void *ws,
+                        size_t ws_bytes, void *stream);
+}  // namespace tc

@@ -194,6 +194,41 @@ def test_product_path_has_no_fallback():
             assert "liboracle" not in src, f
 
 
+def declared_define(name):
+    text = open(os.path.join(ROOT, "include", "tc.h")).read()
+    return int(re.search(r"#define\s+" + name + r"\s+(\d+)", text).group(1))
+
+
+def test_op_codes():
+    for name in ("TC_OP_CONVOLVE", "TC_OP_TEI_GRAM", "TC_OP_TEI_GRAM_BACKWARD",
+                 "TC_OP_AUTOTUNE"):
+        assert getattr(_lib, name) == declared_define(name), name
+
+
+def test_int8_fft_forward_needs_no_binary64_W(L):
+    """The int8 FFT route writes the int8 slices of W straight from the
+    convolution: its forward plan holds no binary64 W, the direct route's and
+    the autotuner's (every route may run) do."""
+    I = _inst(n=1024, R_f=64, R_N=6)
+    arr = (_lib.TcInstance * 1)(I)
+    A = _lib.ALGORITHMS
+    up = lambda x: (x + 255) // 256 * 256
+    W = up(8 * 6 * 64 * 1024)
+    assert L.tc_tune_get(1024, 64, 6, _lib.TC_OZAKI_I8) == A["fft"]
+    fft = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_OZAKI_I8)
+    try:
+        assert L.tc_tune_set(1024, 64, 6, _lib.TC_OZAKI_I8, A["direct"]) == _lib.TC_OK
+        direct = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_OZAKI_I8)
+    finally:
+        L.tc_tune_set(1024, 64, 6, _lib.TC_OZAKI_I8, A["auto"])
+    assert direct == fft + 3 * W          # one W per concurrent mode
+    tune = L.tc_workspace_bytes(_lib.TC_OP_AUTOTUNE, arr, 1, _lib.TC_OZAKI_I8)
+    assert tune == (fft - up(8 * 3 * 6 * 64 * 64)) // 3 + up(8 * 3 * 6 * 64 * 64) + W
+    # the backward recomputes W on every route
+    back = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_OZAKI_I8)
+    assert back >= W
+
+
 def test_tuning_table(L):
     A = _lib.ALGORITHMS
     # built-in rule: FFT from 256 cells up to the FFT size limit, direct otherwise
