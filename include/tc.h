@@ -236,6 +236,26 @@ tc_status tc_tei_gram(const tc_instance *inst, int count, tc_precision prec,
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * tc_tei_gram_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): tc_tei_gram with the workspace taken from a static device
+ * array of TC_NOALLOC_SCRATCH_BYTES (256 MiB) that the library holds on each
+ * GPU it runs on until the process ends.  It calls no allocating routine.
+ * Same arguments, plans, kernels and results as tc_tei_gram (bitwise), less
+ * the workspace.  A problem whose tc_workspace_bytes(TC_OP_TEI_GRAM, ...)
+ * exceeds the array returns TC_ERR_WORKSPACE before any device call.
+ * `stream` must belong to the current device: the array is looked up
+ * (hipGetSymbolAddress) with that device current on its first call there.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other host threads without ordering) race; calls ordered
+ * on one stream do not.  The array keeps the last call's data; nothing in
+ * the computation reads workspace it has not written in the same call.
+ */
+#define TC_NOALLOC_SCRATCH_BYTES 268435456
+tc_status tc_tei_gram_noalloc(const tc_instance *inst, int count, tc_precision prec,
+                              void *stream);
+
+/*
  * tc_tei_gram_backward -- adjoint of f = <Jbar, J> with respect to the side
  * matrices: with S = (Jbar + Jbar^T)/2 and D^l_k = c_k S o G^{l+1}_k o
  * G^{l+2}_k (modes cyclic), dU^l = 2 sum_k T^l_k U^l D^l_k = 2 sum_k W^l_k D^l_k

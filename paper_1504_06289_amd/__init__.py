@@ -7,5 +7,6 @@ from .api import (TeiGram, TeiGramGraph, autotune, autotune_batched,  # noqa: F4
                   coulomb, density_fit, lattice_energy, lattice_sum, make_instance,
                   newton_kernel, nuclear,
                   profile_enable, profile_read,
-                  tei_cholesky, tei_gram, tei_gram_backward, tei_gram_batched, term_classes,
+                  tei_cholesky, tei_gram, tei_gram_backward, tei_gram_batched,
+                  tei_gram_noalloc, term_classes,
                   tune_get, tune_set)

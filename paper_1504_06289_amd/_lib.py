@@ -29,9 +29,11 @@ TC_OP_CONVOLVE = 0
 TC_OP_TEI_GRAM = 1
 TC_OP_TEI_GRAM_BACKWARD = 2
 TC_OP_AUTOTUNE = 3
+TC_NOALLOC_SCRATCH_BYTES = 268435456
 
 # the ABI symbols declared in include/tc.h
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
+           "tc_tei_gram_noalloc",
            "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
            "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
@@ -118,6 +120,9 @@ def lib() -> ctypes.CDLL:
         L.tc_tei_gram.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int, vp,
                                   ctypes.c_size_t, vp]
         L.tc_tei_gram.restype = ctypes.c_int
+        L.tc_tei_gram_noalloc.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int,
+                                          vp]
+        L.tc_tei_gram_noalloc.restype = ctypes.c_int
         L.tc_tei_gram_backward.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int,
                                            ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
                                            vp, ctypes.c_size_t, vp]

@@ -344,6 +344,22 @@ def tei_gram_batched(instances, prec="fp64", save_G: bool = False):
     return (Js, Gs) if save_G else Js
 
 
+def tei_gram_noalloc(instances, prec="fp64"):
+    """tc_tei_gram_noalloc: as tei_gram_batched (sequence of (c, p3, U3)), with
+    the library's static device scratch in place of a workspace.  The output
+    J tensors are the caller's (allocated here, outside the call)."""
+    dev = instances[0][2][0].device
+    Js, arr = [], (TcInstance * len(instances))()
+    for i, (c, p3, U3) in enumerate(instances):
+        R_f = U3[0].shape[0]
+        J = torch.empty((R_f, R_f), dtype=torch.float64, device=dev)
+        arr[i] = make_instance(c, p3, U3, J, None)
+        Js.append(J)
+    check(_lib.lib().tc_tei_gram_noalloc(arr, len(instances), _prec(prec), _stream(dev)),
+          "tc_tei_gram_noalloc")
+    return Js
+
+
 def _run_gram(insts, prec, dev):
     if isinstance(insts, list):
         arr = (TcInstance * len(insts))(*insts)

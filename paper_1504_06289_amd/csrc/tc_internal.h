@@ -263,8 +263,8 @@ hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls,
 namespace tc {
 // the argument checks of tc_tei_gram (no device call)
 tc_status tei_gram_check(const tc_instance *inst, int count, tc_precision prec);
-// tc_tei_gram on the workspace ws of ws_bytes bytes: validation, plans,
-// dispatch.
+// tc_tei_gram on the workspace ws of ws_bytes bytes (the caller's, or the
+// static scratch of tc_tei_gram_noalloc): validation, plans, dispatch.
 tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, void *ws,
                         size_t ws_bytes, void *stream);
 }  // namespace tc

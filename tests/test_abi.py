@@ -199,10 +199,11 @@ def declared_define(name):
     return int(re.search(r"#define\s+" + name + r"\s+(\d+)", text).group(1))
 
 
-def test_op_codes():
+def test_op_codes_and_static_scratch_size():
     for name in ("TC_OP_CONVOLVE", "TC_OP_TEI_GRAM", "TC_OP_TEI_GRAM_BACKWARD",
-                 "TC_OP_AUTOTUNE"):
+                 "TC_OP_AUTOTUNE", "TC_NOALLOC_SCRATCH_BYTES"):
         assert getattr(_lib, name) == declared_define(name), name
+    assert _lib.TC_NOALLOC_SCRATCH_BYTES == 256 << 20
 
 
 def test_int8_fft_forward_needs_no_binary64_W(L):
@@ -227,6 +228,23 @@ def test_int8_fft_forward_needs_no_binary64_W(L):
     # the backward recomputes W on every route
     back = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_OZAKI_I8)
     assert back >= W
+
+
+def test_noalloc_rejects_before_any_device_call(L):
+    """tc_tei_gram_noalloc validates like tc_tei_gram and rejects a problem
+    beyond its static scratch with TC_ERR_WORKSPACE before touching a device
+    (this runs without a GPU)."""
+    big = (_lib.TcInstance * 1)(_inst(n=4096, R_f=1024, R_N=32))
+    need = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, big, 1, _lib.TC_FP64)
+    assert need > _lib.TC_NOALLOC_SCRATCH_BYTES
+    assert L.tc_tei_gram_noalloc(big, 1, _lib.TC_FP64, None) == _lib.TC_ERR_WORKSPACE
+    for kw in (dict(n=0), dict(R_f=0), dict(null="J"), dict(null="c")):
+        bad = (_lib.TcInstance * 1)(_inst(**kw))
+        assert L.tc_tei_gram_noalloc(bad, 1, _lib.TC_FP64, None) == _lib.TC_ERR_INVALID_ARG
+    ok = (_lib.TcInstance * 1)(_inst())
+    assert L.tc_tei_gram_noalloc(ok, 0, _lib.TC_FP64, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tei_gram_noalloc(ok, 1, 42, None) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_tei_gram_noalloc(None, 1, _lib.TC_FP64, None) == _lib.TC_ERR_INVALID_ARG
 
 
 def test_tuning_table(L):
