@@ -53,6 +53,19 @@
  *     problem size (no floating-point atomics; fixed reduction orders).
  *   - Calls on different streams may run concurrently if their outputs and
  *     workspaces do not overlap.
+ *   - Diagnostics, read from the environment at every call (both make the
+ *     calls synchronise, so keep them off while capturing a graph):
+ *       TC_CHECK_FINITE=1  tc_convolve, tc_tei_gram, tc_tei_gram_noalloc,
+ *                          tc_tei_gram_backward, tc_coulomb and tc_nuclear
+ *                          scan their binary64 device inputs (c, p, U, and
+ *                          V, d, Jbar, G_saved where present) for NaN and
+ *                          Inf before any other work, synchronise once to
+ *                          read the result, and return TC_ERR_INVALID_ARG,
+ *                          writing no output, when one is found;
+ *       TC_DEBUG_SYNC=1    every kernel launch is followed by a
+ *                          synchronisation of its stream; the first failing
+ *                          kernel is named on stderr and the call returns
+ *                          TC_ERR_HIP.
  */
 #ifndef TC_H
 #define TC_H
@@ -68,7 +81,11 @@ typedef enum {
     TC_ERR_INVALID_ARG = 1, /* null pointer, size out of range, non-finite parameter */
     TC_ERR_WORKSPACE = 2,   /* workspace missing or smaller than tc_workspace_bytes */
     TC_ERR_UNSUPPORTED = 3, /* precision or size the library does not implement */
-    TC_ERR_HIP = 4          /* a HIP launch or runtime call failed */
+    TC_ERR_HIP = 4,         /* a HIP launch or runtime call failed */
+    /* not codes: they give the enum the range of int, so that any int a
+     * caller passes is a defined value (and is rejected if unknown) */
+    TC_STATUS_RANGE_MIN_ = -2147483647 - 1,
+    TC_STATUS_RANGE_MAX_ = 2147483647
 } tc_status;
 
 /* Arithmetic of the Toeplitz (W = T U) and Gram (G = U^T W) contractions.
@@ -89,11 +106,13 @@ typedef enum {
                         chunks (a measured comparison point)                  */
     TC_BF16X6 = 3,   /* as TC_BF16X3 with three pieces and the six products
                         of piece-index sum <= 2                               */
-    TC_OZAKI_I8 = 4  /* error-free splitting of each operand into four int8
+    TC_OZAKI_I8 = 4, /* error-free splitting of each operand into four int8
                         slices with one exponent per row (28 bits relative to
                         the row maximum), the ten leading slice products on
                         int8 matrix cores with exact int32 accumulation, and
                         binary64 recombination (Ozaki scheme)                 */
+    TC_PRECISION_RANGE_MIN_ = -2147483647 - 1,  /* range of int (see tc_status) */
+    TC_PRECISION_RANGE_MAX_ = 2147483647
 } tc_precision;
 
 /* How the Toeplitz products W_k = T_k U are formed.  TC_ALGO_DIRECT: the
@@ -107,7 +126,9 @@ typedef enum {
 typedef enum {
     TC_ALGO_AUTO = 0,
     TC_ALGO_DIRECT = 1,
-    TC_ALGO_FFT = 2
+    TC_ALGO_FFT = 2,
+    TC_ALGORITHM_RANGE_MIN_ = -2147483647 - 1,  /* range of int (see tc_status) */
+    TC_ALGORITHM_RANGE_MAX_ = 2147483647
 } tc_algorithm;
 
 /* Largest supported sizes (guards for index arithmetic). */

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <string>
 #include <algorithm>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <set>
@@ -224,14 +225,37 @@ struct ProfScope {
     }
 };
 
-// launch `expr` (returns hipError_t) under the kernel name `name` on stream st
+// launch `expr` (returns hipError_t) under the kernel name `name` on stream st;
+// with TC_DEBUG_SYNC set, synchronise st after it and report a failure
 #define TRYK(name, expr)                                                                       \
     do {                                                                                       \
         ProfScope ps_(name, st);                                                               \
         if ((expr) != hipSuccess)                                                              \
             return TC_ERR_HIP;                                                                 \
         ps_.end();                                                                             \
+        if (debug_sync_on() && !debug_sync_check(name, st))                                    \
+            return TC_ERR_HIP;                                                                 \
     } while (0)
+
+// With TC_CHECK_FINITE set: TC_ERR_INVALID_ARG when any of the arrays holds a
+// NaN or Inf (checked on the device before any other work; synchronises st).
+tc_status finite_inputs(std::initializer_list<FiniteSpan> spans, hipStream_t st)
+{
+    if (!check_finite_on())
+        return TC_OK;
+    const std::vector<FiniteSpan> v(spans);
+    const int r = scan_nonfinite(v.data(), (int)v.size(), st);
+    return r < 0 ? TC_ERR_HIP : r > 0 ? TC_ERR_INVALID_ARG : TC_OK;
+}
+
+tc_status finite_instance(const tc_instance &I, hipStream_t st)
+{
+    tc_status s = finite_inputs({{I.c, I.R_N}}, st);
+    for (int l = 0; l < 3 && s == TC_OK; ++l)
+        s = finite_inputs({{I.p[l], (long)I.R_N * (2L * I.n[l] - 1)},
+                           {I.U[l], (long)I.R_f * I.n[l]}}, st);
+    return s;
+}
 
 // spectra of U's rows and of the kernel embeddings (FFT route)
 tc_status fft_spectra(int n, int R_f, int R_N, const double *p, const double *U,
@@ -855,6 +879,11 @@ tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, v
     if (need > 0 && (!ws || ws_bytes < need))
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) {
+        const tc_status f = finite_instance(inst[i], st);
+        if (f != TC_OK)
+            return f;
+    }
     std::lock_guard<std::mutex> lk(g_pool_mu);
     if (!pool_init())
         return TC_ERR_HIP;
@@ -902,6 +931,8 @@ const char *tc_status_string(tc_status s)
         return "TC_ERR_UNSUPPORTED: precision or size not supported";
     case TC_ERR_HIP:
         return "TC_ERR_HIP: HIP launch or runtime error";
+    default:
+        break;
     }
     return "unknown tc_status";
 }
@@ -1008,6 +1039,10 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double
     const size_t need = convolve_ws(n, R_f, R_N, prec);
     if (need > 0 && (!ws || ws_bytes < need))
         return TC_ERR_WORKSPACE;
+    const tc_status f = finite_inputs({{p_dev, (long)R_N * (2L * n - 1)}, {U_dev, (long)R_f * n}},
+                                      (hipStream_t)stream);
+    if (f != TC_OK)
+        return f;
     Carver c(ws);
     const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false);
     return mode_W(prec, resolve(n, R_f, R_N, prec), n, R_f, R_N, p_dev, U_dev, W_dev, s,
@@ -1342,6 +1377,12 @@ tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, 
     if (!ws || ws_bytes < N.bytes)
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
+    tc_status f = finite_inputs({{P.c, P.R_N}}, st);
+    for (int l = 0; l < 3 && f == TC_OK; ++l)
+        f = finite_inputs({{P.p[l], (long)P.R_N * (2L * P.n[l] - 1)},
+                           {P.U[l], (long)P.R_f * P.n[l]}}, st);
+    if (f != TC_OK)
+        return f;
     const double inv_vol = 1.0 / (P.h[0] * P.h[1] * P.h[2]);
     for (int base = 0; base < P.M; base += kNuclearChunk) {
         NuclearChunk ch{};
@@ -1429,6 +1470,13 @@ tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t
     if (!ws || ws_bytes < P.bytes)
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
+    tc_status f = finite_inputs({{D.c, D.R_N}, {D.d, D.R_rho}}, st);
+    for (int l = 0; l < 3 && f == TC_OK; ++l)
+        f = finite_inputs({{D.p[l], (long)D.R_N * (2L * D.n[l] - 1)},
+                           {D.U[l], (long)D.R_f * D.n[l]},
+                           {D.V[l], (long)D.R_rho * D.n[l]}}, st);
+    if (f != TC_OK)
+        return f;
     const size_t plane = (size_t)D.R_N * D.R_f * D.R_rho;
     for (int l = 0; l < 3; ++l) {
         // the factors T_q V of the Hartree potential, then their scalar
@@ -1470,6 +1518,16 @@ tc_status tc_tei_gram_backward(const tc_instance *inst, int count, const double 
     const size_t need = tc_workspace_bytes(TC_OP_TEI_GRAM_BACKWARD, inst, count, prec);
     if (!ws || ws_bytes < need)
         return TC_ERR_WORKSPACE;
+    for (int i = 0; i < count; ++i) {
+        const tc_instance &I = inst[i];
+        const long F2 = (long)I.R_f * I.R_f;
+        tc_status f = finite_instance(I, (hipStream_t)stream);
+        if (f == TC_OK)
+            f = finite_inputs({{Jbar[i], F2}, {I.G_saved, I.G_saved ? 3L * I.R_N * F2 : 0}},
+                              (hipStream_t)stream);
+        if (f != TC_OK)
+            return f;
+    }
     for (int i = 0; i < count; ++i) {
         const tc_status s =
             backward_instance(inst[i], Jbar[i], dU + 3 * i, prec, ws, (hipStream_t)stream);

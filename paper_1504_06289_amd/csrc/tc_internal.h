@@ -268,3 +268,17 @@ tc_status tei_gram_check(const tc_instance *inst, int count, tc_precision prec);
 tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, void *ws,
                         size_t ws_bytes, void *stream);
 }  // namespace tc
+
+// ---- diagnostics (diag.hip) -------------------------------------------------
+namespace tc {
+bool check_finite_on();   // TC_CHECK_FINITE set (and not "0")
+bool debug_sync_on();     // TC_DEBUG_SYNC set (and not "0")
+// synchronise st after launching `kernel`; false (and a line on stderr) on error
+bool debug_sync_check(const char *kernel, hipStream_t st);
+struct FiniteSpan {
+    const double *x;  // device
+    long count;
+};
+// 1 if any span holds a NaN or Inf, 0 if none, -1 on a HIP error; synchronises st
+int scan_nonfinite(const FiniteSpan *spans, int count, hipStream_t st);
+}  // namespace tc
