@@ -118,8 +118,9 @@ typedef enum {
 /* How the Toeplitz products W_k = T_k U are formed.  TC_ALGO_DIRECT: the
  * implicit-Toeplitz matrix-core product in the arithmetic selected by
  * tc_precision.  TC_ALGO_FFT: aperiodic convolution through a circulant
- * embedding of length N >= 2n-1 with binary64 FFTs (n <= 4096); the Grams then
- * use the tc_precision arithmetic.  With TC_OZAKI_I8 the route treats narrow
+ * embedding of length N >= 2n-1 with binary64 FFTs (LDS-resident transforms
+ * for n <= 4096, four-step transforms through device memory for
+ * 4096 < n <= TC_MAX_N); the Grams then use the tc_precision arithmetic.  With TC_OZAKI_I8 the route treats narrow
  * and smooth kernel terms separately (tc_term_classes).  TC_ALGO_AUTO: the
  * entry of the tuning
  * table for the mode's (n, R_f, R_N, precision), else a built-in rule. */

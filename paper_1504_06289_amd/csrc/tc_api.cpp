@@ -72,6 +72,9 @@ std::map<TuneKey, int> g_tune;
 // tc_autotune), the direct matrix-core product otherwise.
 constexpr int kFftMinN = 256;
 
+// an FFT route exists for n cells (LDS-resident or four-step)
+bool fft_any(int n) { return fft_supported(n) || fft_large_supported(n); }
+
 tc_algorithm resolve(int n, int R_f, int R_N, tc_precision prec)
 {
     {
@@ -79,11 +82,19 @@ tc_algorithm resolve(int n, int R_f, int R_N, tc_precision prec)
         auto it = g_tune.find(TuneKey(n, R_f, R_N, (int)prec));
         if (it != g_tune.end()) {
             const tc_algorithm a = (tc_algorithm)it->second;
-            if (a != TC_ALGO_FFT || fft_supported(n))
+            if (a != TC_ALGO_FFT || fft_any(n))
                 return a;
         }
     }
-    return (fft_supported(n) && n >= kFftMinN) ? TC_ALGO_FFT : TC_ALGO_DIRECT;
+    return (fft_supported(n) && n >= kFftMinN) || fft_large_supported(n) ? TC_ALGO_FFT
+                                                                          : TC_ALGO_DIRECT;
+}
+
+// the int8 route whose convolution writes W's int8 slices directly (and
+// treats narrow and smooth kernel terms apart): the LDS-resident FFT lengths
+bool i8_fused_fft(tc_precision prec, tc_algorithm algo, int n)
+{
+    return prec == TC_OZAKI_I8 && algo == TC_ALGO_FFT && fft_supported(n);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,9 +134,16 @@ struct ModeScratch {
     double *Sp = nullptr;      // partial sums of S over frequency ranges
     double *S = nullptr;       // [R_N][kPolyRank][kPolyRank] = Q T_k Q^T
     double *Y = nullptr;       // [R_N][R_f][kPolyRank] = X S_k
+    // FFT route beyond 4096 cells (four-step transforms)
+    double2 *Zl = nullptr;     // spectra of the pairs of U rows
+    double2 *Cl = nullptr;     // spectra of the kernel embeddings
+    double2 *Tl = nullptr;     // inverse scratch
+    int *El = nullptr;         // row exponents of U (the pairs' scales)
 };
 
-ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram)
+// large_fft: reserve the scratch of the four-step FFT route (n > 4096)
+ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bool gram,
+                       bool large_fft = true)
 {
     ModeScratch s;
     if (prec == TC_OZAKI_I8) {
@@ -144,6 +162,14 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
         s.EP = c.take<int>(R_N);
         if (gram)
             s.EW = c.take<int>((size_t)R_N * R_f);
+    }
+    if (fft_large_supported(n) && large_fft) {
+        const LargeFftLayout L = fft_large_layout(n, R_f, R_N);
+        s.twN = c.take<double2>(L.N);
+        s.Zl = c.take<double2>(L.z_entries);
+        s.Cl = c.take<double2>(L.c_entries);
+        s.Tl = c.take<double2>(L.t_entries);
+        s.El = c.take<int>(R_f);
     }
     if (fft_supported(n)) {
         const int N = fft_length(n);
@@ -272,6 +298,15 @@ tc_status fft_spectra(int n, int R_f, int R_N, const double *p, const double *U,
 tc_status mode_W(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N, const double *p,
                  const double *U, double *W, const ModeScratch &s, hipStream_t st)
 {
+    if (algo == TC_ALGO_FFT && fft_large_supported(n)) {
+        if (!s.Zl)
+            return TC_ERR_WORKSPACE;
+        TRYK("fft_twiddles", launch_fft_twiddles(s.twN, fft_length(n), st));
+        TRYK("row_exponents", launch_row_exponents(U, R_f, n, s.El, st));
+        TRYK("fft_large",
+             launch_fft_large_W(p, U, s.El, n, R_f, R_N, s.twN, s.Zl, s.Cl, s.Tl, W, st));
+        return TC_OK;
+    }
     if (algo == TC_ALGO_FFT) {
         const tc_status r = fft_spectra(n, R_f, R_N, p, U, s, st);
         if (r != TC_OK)
@@ -394,7 +429,7 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
                                                bf16_pieces(prec), mirror, st));
         return TC_OK;
     }
-    if (algo == TC_ALGO_FFT) {
+    if (i8_fused_fft(prec, algo, n)) {
         const tc_status r = int8fft_kernel_part(n, R_N, p, s, st);
         if (r != TC_OK)
             return r;
@@ -404,6 +439,10 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
     const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
     if (r != TC_OK)
         return r;
+    // the direct route split U's rows for its own product; the four-step FFT
+    // route (n > 4096) did not
+    if (algo == TC_ALGO_FFT)
+        TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
     TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
     TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, st));
     return TC_OK;
@@ -452,14 +491,17 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
     // binary64 W: every route but the forward int8 FFT route, which writes
     // the int8 slices of W straight from the convolution; by_route == false
     // keeps it for every mode (any route may run: the autotuner)
-    bool needW[3];
-    for (int l = 0; l < 3; ++l)
-        needW[l] = backward || !by_route ||
-                   !(prec == TC_OZAKI_I8 && resolve(I.n[l], I.R_f, I.R_N, prec) == TC_ALGO_FFT);
+    // The four-step FFT scratch (n > 4096) likewise only where that route runs.
+    bool needW[3], largeF[3];
+    for (int l = 0; l < 3; ++l) {
+        const tc_algorithm a = resolve(I.n[l], I.R_f, I.R_N, prec);
+        needW[l] = backward || !by_route || !i8_fused_fft(prec, a, I.n[l]);
+        largeF[l] = !by_route || a == TC_ALGO_FFT;
+    }
     if (split) {
         for (int l = 0; l < 3; ++l) {
             P.W[l] = needW[l] ? c.take<double>((size_t)I.R_N * I.R_f * I.n[l]) : nullptr;
-            P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true);
+            P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true, largeF[l]);
         }
         P.bytes = c.used;
         return P;
@@ -473,7 +515,7 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
     size_t scratch_max = 0;
     for (int l = 0; l < 3; ++l) {
         c.used = scratch0;
-        P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true);
+        P.ms[l] = carve_mode(c, prec, I.n[l], I.R_f, I.R_N, true, largeF[l]);
         if (c.used - scratch0 > scratch_max)
             scratch_max = c.used - scratch0;
     }
@@ -484,7 +526,7 @@ InstancePlan plan_instance(void *ws, const tc_instance &I, tc_precision prec, bo
 size_t convolve_ws(int n, int R_f, int R_N, tc_precision prec)
 {
     Carver c(nullptr);
-    carve_mode(c, prec, n, R_f, R_N, false);
+    carve_mode(c, prec, n, R_f, R_N, false, resolve(n, R_f, R_N, prec) == TC_ALGO_FFT);
     return c.used;
 }
 
@@ -521,7 +563,8 @@ DensityPlan plan_density(void *ws, const tc_density &D)
     size_t scratch_max = 0;
     for (int l = 0; l < 3; ++l) {
         c.used = scratch0;
-        P.ms[l] = carve_mode(c, TC_FP64, D.n[l], D.R_rho, D.R_N, false);
+        P.ms[l] = carve_mode(c, TC_FP64, D.n[l], D.R_rho, D.R_N, false,
+                             resolve(D.n[l], D.R_rho, D.R_N, TC_FP64) == TC_ALGO_FFT);
         if (c.used - scratch0 > scratch_max)
             scratch_max = c.used - scratch0;
     }
@@ -656,7 +699,7 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, si
         owner[l] = l;
     }
     for (int l = 0; l < 3; ++l) {
-        if (!(prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT))
+        if (!i8_fused_fft(prec, algo[l], I.n[l]))
             continue;
         auto same_part = [&](int m) {
             return owner[m] == m && algo[m] == algo[l] && I.p[m] == I.p[l] && I.n[m] == I.n[l];
@@ -668,7 +711,7 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, si
                     owner[l] = m;
                     break;
                 }
-        } else if (l > 0 && prec == TC_OZAKI_I8 && algo[l - 1] == TC_ALGO_FFT &&
+        } else if (l > 0 && i8_fused_fft(prec, algo[l - 1], I.n[l - 1]) &&
                    same_part(owner[l - 1])) {
             // one region shared by the modes in turn: only the part the
             // previous mode left there (its own or the one it borrowed) is
@@ -691,7 +734,7 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, si
             break;
         }
         double *Gl = P.G + (size_t)l * I.R_N * F2;
-        const bool i8fft = prec == TC_OZAKI_I8 && algo[l] == TC_ALGO_FFT;
+        const bool i8fft = i8_fused_fft(prec, algo[l], I.n[l]);
         if (!i8fft) {
             status = mode_grams(prec, algo[l], I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l], Gl,
                                 P.ms[l], sl, mirror);
@@ -976,7 +1019,7 @@ tc_status tc_tune_set(int n, int R_f, int R_N, tc_precision prec, tc_algorithm a
         return TC_ERR_INVALID_ARG;
     if (algo != TC_ALGO_AUTO && algo != TC_ALGO_DIRECT && algo != TC_ALGO_FFT)
         return TC_ERR_INVALID_ARG;
-    if (algo == TC_ALGO_FFT && !fft_supported(n))
+    if (algo == TC_ALGO_FFT && !fft_any(n))
         return TC_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const TuneKey key(n, R_f, R_N, (int)prec);
@@ -1044,9 +1087,11 @@ tc_status tc_convolve(int n, int R_f, int R_N, const double *p_dev, const double
     if (f != TC_OK)
         return f;
     Carver c(ws);
-    const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false);
-    return mode_W(prec, resolve(n, R_f, R_N, prec), n, R_f, R_N, p_dev, U_dev, W_dev, s,
-                  (hipStream_t)stream);
+    const tc_algorithm algo = resolve(n, R_f, R_N, prec);
+    const ModeScratch s = carve_mode(c, prec, n, R_f, R_N, false, algo == TC_ALGO_FFT);
+    if (c.used > ws_bytes && c.used > 0)
+        return TC_ERR_WORKSPACE;
+    return mode_W(prec, algo, n, R_f, R_N, p_dev, U_dev, W_dev, s, (hipStream_t)stream);
 }
 
 
@@ -1574,7 +1619,7 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
                 double ms[2] = {-1.0, -1.0};
                 const tc_algorithm cand[2] = {TC_ALGO_DIRECT, TC_ALGO_FFT};
                 for (int a = 0; a < 2 && status == TC_OK; ++a) {
-                    if (cand[a] == TC_ALGO_FFT && !fft_supported(I.n[l]))
+                    if (cand[a] == TC_ALGO_FFT && !fft_any(I.n[l]))
                         continue;
                     for (int rep = 0; rep < 4 && status == TC_OK; ++rep) {
                         if (rep == 1 && hipEventRecord(e0, st) != hipSuccess)

@@ -147,6 +147,25 @@ hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, in
                            int R_f_pad, int n_pad, long wplane, const double *U,
                            const double *p, const int *band, hipStream_t stream);
 
+// ---- FFT route beyond the LDS-resident lengths (fft_large.hip) --------------
+// 4096 < n <= 65536: N = fft_length(n) in 16384 .. 131072, four-step binary64
+// transforms with two real rows per complex sequence.
+bool fft_large_supported(int n);
+struct LargeFftLayout {
+    int N;           // transform length
+    int P;           // complex sequences of U (pairs of rows): ceil(R_f / 2)
+    int kc;          // kernel terms per inverse chunk
+    long z_entries;  // complex entries of the U spectra   [P][N]
+    long c_entries;  // complex entries of the kernel spectra [R_N][N]
+    long t_entries;  // complex entries of the inverse scratch [kc][P][N]
+};
+LargeFftLayout fft_large_layout(int n, int R_f, int R_N);
+// W [R_N][R_f][n] (binary64) = T_k U for all k; twN from launch_fft_twiddles(N);
+// EU [R_f] from launch_row_exponents(U); Z, C, T scratch of the layout's sizes.
+hipError_t launch_fft_large_W(const double *p, const double *U, const int *EU, int n, int R_f,
+                              int R_N, const double2 *twN, double2 *Z, double2 *C, double2 *T,
+                              double *W, hipStream_t stream);
+
 // ---- Coulomb entries against a density (coulomb.hip) -----------------------
 // H[q][i][m] = sum_a U[i][a] W[q][m][a] for i < R_f, m < R_rho, q < R_N
 hipError_t launch_cross_gram_f64(const double *U, const double *W, double *H, int n, int R_f,

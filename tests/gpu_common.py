@@ -26,7 +26,7 @@ def algorithm(tc, algo, shapes, prec):
     """Force the Toeplitz algorithm for the given (n, R_f, R_N) mode shapes."""
     keys = sorted(set(shapes))
     for key in keys:
-        if algo == "fft" and key[0] > 4096:
+        if algo == "fft" and key[0] > 65536:
             continue
         tc.tune_set(*key, prec, algo)
     try:

@@ -107,11 +107,22 @@ def test_workspace_bytes(L):
     # the adjoint runs the modes in turn: one W and one mode's scratch, and D
     wb = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM_BACKWARD, arr, 1, _lib.TC_FP64)
     assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100) + fft
-    # no FFT scratch beyond the FFT route's size limit (n > 4096)
+    # beyond 4096 cells the FFT route is four-step: per mode the twiddles
+    # [N], the spectra of the row pairs [P][N] and of the kernel [R_N][N],
+    # and the inverse scratch [kc][P][N] (N = 16384 for 5000 cells, P = 1,
+    # kc = 1); with the direct route pinned only W remains
     I = _inst(n=5000, R_f=2, R_N=1)
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
-    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == 3 * up(8 * 2 * 5000)
+    assert L.tc_tune_get(5000, 2, 1, _lib.TC_FP64) == _lib.ALGORITHMS["fft"]
+    assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
+        3 * (up(8 * 2 * 5000) + 4 * up(16 * 16384))
+    try:
+        L.tc_tune_set(5000, 2, 1, _lib.TC_FP64, _lib.ALGORITHMS["direct"])
+        assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
+            3 * up(8 * 2 * 5000)
+    finally:
+        L.tc_tune_set(5000, 2, 1, _lib.TC_FP64, _lib.ALGORITHMS["auto"])
     bad = (_lib.TcInstance * 1)(_inst(n=0))
     assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, bad, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
     assert L.tc_workspace_bytes(7, arr, 1, _lib.TC_FP64) == ctypes.c_size_t(-1).value
@@ -251,16 +262,18 @@ def test_noalloc_rejects_before_any_device_call(L):
 
 def test_tuning_table(L):
     A = _lib.ALGORITHMS
-    # built-in rule: FFT from 256 cells up to the FFT size limit, direct otherwise
+    # built-in rule: FFT from 256 cells up (four-step beyond 4096), direct below
     assert L.tc_tune_get(128, 8, 20, _lib.TC_FP64) == A["direct"]
     assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["fft"]
-    assert L.tc_tune_get(5000, 8, 20, _lib.TC_FP64) == A["direct"]
+    assert L.tc_tune_get(5000, 8, 20, _lib.TC_FP64) == A["fft"]
+    assert L.tc_tune_get(65536, 8, 20, _lib.TC_FP64) == A["fft"]
     assert L.tc_tune_set(1024, 8, 20, _lib.TC_FP64, A["direct"]) == _lib.TC_OK
     assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["direct"]
     assert L.tc_tune_get(1024, 8, 20, _lib.TC_OZAKI_I8) == A["fft"]   # other key untouched
     assert L.tc_tune_set(1024, 8, 20, _lib.TC_FP64, A["auto"]) == _lib.TC_OK
     assert L.tc_tune_get(1024, 8, 20, _lib.TC_FP64) == A["fft"]
-    assert L.tc_tune_set(5000, 8, 20, _lib.TC_FP64, A["fft"]) == _lib.TC_ERR_UNSUPPORTED
+    assert L.tc_tune_set(5000, 8, 20, _lib.TC_FP64, A["fft"]) == _lib.TC_OK
+    assert L.tc_tune_set(5000, 8, 20, _lib.TC_FP64, A["auto"]) == _lib.TC_OK
     assert L.tc_tune_set(0, 8, 20, _lib.TC_FP64, A["fft"]) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_tune_set(64, 8, 20, _lib.TC_FP64, 9) == _lib.TC_ERR_INVALID_ARG
 
