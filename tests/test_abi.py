@@ -109,14 +109,15 @@ def test_workspace_bytes(L):
     assert wb == up(8 * 3 * 10 * 100) + up(8 * 3 * 100) + fft
     # beyond 4096 cells the FFT route is four-step: per mode the twiddles
     # [N], the spectra of the row pairs [P][N] and of the kernel [R_N][N],
-    # and the inverse scratch [kc][P][N] (N = 16384 for 5000 cells, P = 1,
-    # kc = 1); with the direct route pinned only W remains
+    # the inverse scratch [kc][P][N] (N = 16384 for 5000 cells, P = 1,
+    # kc = 1) and the rows' exponents [R_f]; with the direct route pinned only
+    # W remains
     I = _inst(n=5000, R_f=2, R_N=1)
     I.G_saved = 0x5000
     arr = (_lib.TcInstance * 1)(I)
     assert L.tc_tune_get(5000, 2, 1, _lib.TC_FP64) == _lib.ALGORITHMS["fft"]
     assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
-        3 * (up(8 * 2 * 5000) + 4 * up(16 * 16384))
+        3 * (up(8 * 2 * 5000) + 4 * up(16 * 16384) + up(4 * 2))
     try:
         L.tc_tune_set(5000, 2, 1, _lib.TC_FP64, _lib.ALGORITHMS["direct"])
         assert L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, arr, 1, _lib.TC_FP64) == \
