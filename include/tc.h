@@ -132,6 +132,28 @@ typedef enum {
     TC_ALGORITHM_RANGE_MAX_ = 2147483647
 } tc_algorithm;
 
+/* How tc_tei_gram runs a batch (count > 1).  TC_BATCH_FORK_JOIN: the
+ * instances spread over internal streams, each with its own per-mode
+ * launches.  TC_BATCH_QUEUE*: TC_OZAKI_I8 only: every mode of every instance
+ * prepares its int8 slices on the streams, then ONE persistent launch forms
+ * the int8 Grams of all of them from a device work queue of (instance, mode,
+ * term, tile[, K part]) items sorted by cost (contraction length first), then
+ * the Hadamard sums follow; the variants choose the tile edge (128, or 64 for
+ * instances with R_f < 256) and whether each tile's contraction is split in
+ * two parts (added in a fixed order).  TC_BATCH_AUTO: the batch's entry in
+ * the tuning table (set by tc_batch_tune_set or tc_autotune), else
+ * TC_BATCH_QUEUE_T64 for TC_OZAKI_I8 and TC_BATCH_FORK_JOIN otherwise. */
+typedef enum {
+    TC_BATCH_AUTO = 0,
+    TC_BATCH_FORK_JOIN = 1,
+    TC_BATCH_QUEUE = 2,          /* 128-tiles, one K part            */
+    TC_BATCH_QUEUE_T64 = 3,      /* 64-tiles below R_f = 256         */
+    TC_BATCH_QUEUE_K2 = 4,       /* 128-tiles, two K parts           */
+    TC_BATCH_QUEUE_T64_K2 = 5,   /* 64-tiles below 256, two K parts  */
+    TC_BATCH_ROUTE_RANGE_MIN_ = -2147483647 - 1,  /* range of int (see tc_status) */
+    TC_BATCH_ROUTE_RANGE_MAX_ = 2147483647
+} tc_batch_route;
+
 /* Largest supported sizes (guards for index arithmetic). */
 #define TC_MAX_N 65536
 #define TC_MAX_RF 65536
@@ -312,10 +334,24 @@ tc_status tc_tune_set(int n, int R_f, int R_N, tc_precision prec, tc_algorithm a
 tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec);
 
 /*
+ * Batch routes in the tuning table, keyed by the batch (precision, count and
+ * every instance's n, R_f, R_N and whether it keeps its Grams).
+ * tc_batch_tune_set with TC_BATCH_AUTO removes the entry; a TC_BATCH_QUEUE*
+ * route for a precision other than TC_OZAKI_I8 returns TC_ERR_UNSUPPORTED.
+ * tc_batch_tune_get returns the route tc_tei_gram would take now.
+ */
+tc_status tc_batch_tune_set(const tc_instance *inst, int count, tc_precision prec,
+                            tc_batch_route route);
+tc_batch_route tc_batch_tune_get(const tc_instance *inst, int count, tc_precision prec);
+
+/*
  * tc_autotune -- measure every algorithm available for each distinct mode
  * shape of the instances (one warm-up and three timed runs of the mode's
  * Toeplitz products and Grams, HIP events on `stream`) and record the fastest
- * in the tuning table.  It synchronises `stream` (it reads the timings).
+ * in the tuning table.  For a TC_OZAKI_I8 batch (count > 1) it then times the
+ * whole batch on every tc_batch_route (one warm-up and two timed runs each,
+ * with the J outputs in the workspace) and records the fastest route for the
+ * batch.  It synchronises `stream` (it reads the timings).
  * Writes scratch data into the workspace (tc_workspace_bytes(TC_OP_AUTOTUNE,
  * ...)) and leaves inst[i].J untouched.  ms_out (host, may be NULL) receives
  * 2 entries per instance and mode: [ (i*3 + l)*2 + a ] = milliseconds of

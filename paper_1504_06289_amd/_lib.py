@@ -33,7 +33,7 @@ TC_NOALLOC_SCRATCH_BYTES = 268435456
 
 # the ABI symbols declared in include/tc.h
 EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backward",
-           "tc_tei_gram_noalloc",
+           "tc_tei_gram_noalloc", "tc_batch_tune_set", "tc_batch_tune_get",
            "tc_workspace_bytes", "tc_status_string", "tc_version", "tc_tune_set",
            "tc_tune_get", "tc_autotune", "tc_profile_enable", "tc_profile_read",
            "tc_term_classes", "tc_coulomb", "tc_coulomb_workspace_bytes", "tc_density_fit",
@@ -41,6 +41,9 @@ EXPORTS = ("tc_newton_kernel", "tc_convolve", "tc_tei_gram", "tc_tei_gram_backwa
            "tc_tei_cholesky_workspace_bytes", "tc_lattice_sum", "tc_lattice_energy", "tc_nuclear",
            "tc_nuclear_workspace_bytes", "tc_canonical_to_tucker",
            "tc_canonical_to_tucker_workspace_bytes")
+
+BATCH_ROUTES = {"auto": 0, "fork_join": 1, "queue": 2, "queue_t64": 3, "queue_k2": 4,
+                "queue_t64_k2": 5}
 
 TC_ALGO_AUTO = 0
 TC_ALGO_DIRECT = 1
@@ -138,6 +141,11 @@ def lib() -> ctypes.CDLL:
         L.tc_tune_set.restype = ctypes.c_int
         L.tc_tune_get.argtypes = [ctypes.c_int] * 4
         L.tc_tune_get.restype = ctypes.c_int
+        L.tc_batch_tune_set.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int]
+        L.tc_batch_tune_set.restype = ctypes.c_int
+        L.tc_batch_tune_get.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int]
+        L.tc_batch_tune_get.restype = ctypes.c_int
         L.tc_autotune.argtypes = [ctypes.POINTER(TcInstance), ctypes.c_int, ctypes.c_int, vp,
                                   ctypes.c_size_t, vp, pd]
         L.tc_autotune.restype = ctypes.c_int

@@ -436,6 +436,32 @@ def tune_get(n: int, R_f: int, R_N: int, prec) -> str:
     return {v: k for k, v in ALGORITHMS.items()}[a]
 
 
+def _batch_array(instances, save_G=False):
+    """Descriptors of a batch for the tuning table, which keys a batch by its
+    sizes and by whether its Grams are kept (only the presence of G matters)."""
+    dev = instances[0][2][0].device
+    arr = (TcInstance * len(instances))()
+    dummy = torch.empty((1, 1), dtype=torch.float64, device=dev)
+    for i, (c, p3, U3) in enumerate(instances):
+        arr[i] = make_instance(c, p3, U3, dummy, dummy if save_G else None)
+    return arr
+
+
+def batch_tune_set(instances, prec, route, save_G: bool = False) -> None:
+    """Pin how tc_tei_gram runs this batch (sequence of (c, p3, U3); save_G as
+    for tei_gram_batched): "fork_join", "queue", "queue_t64", "queue_k2",
+    "queue_t64_k2", or "auto" to clear."""
+    arr = _batch_array(instances, save_G)
+    check(_lib.lib().tc_batch_tune_set(arr, len(instances), _prec(prec),
+                                       _lib.BATCH_ROUTES[route]), "tc_batch_tune_set")
+
+
+def batch_tune_get(instances, prec, save_G: bool = False) -> str:
+    arr = _batch_array(instances, save_G)
+    r = _lib.lib().tc_batch_tune_get(arr, len(instances), _prec(prec))
+    return {v: k for k, v in _lib.BATCH_ROUTES.items()}[r]
+
+
 def autotune(c: torch.Tensor, p3, U3, prec="fp64"):
     """Time both Toeplitz algorithms on this problem's modes (tc_autotune),
     record the faster per mode shape, and return {mode: (ms_direct, ms_fft)}."""

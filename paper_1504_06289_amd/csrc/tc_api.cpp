@@ -97,6 +97,45 @@ bool i8_fused_fft(tc_precision prec, tc_algorithm algo, int n)
     return prec == TC_OZAKI_I8 && algo == TC_ALGO_FFT && fft_supported(n);
 }
 
+// Batch routes: one entry per batch signature (precision, count and every
+// instance's sizes), set by tc_batch_tune_set or tc_autotune.
+std::map<uint64_t, int> g_batch_tune;
+
+uint64_t batch_signature(const tc_instance *inst, int count, tc_precision prec)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    auto mix = [&](long v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix((long)prec);
+    mix(count);
+    for (int i = 0; i < count; ++i) {
+        for (int l = 0; l < 3; ++l)
+            mix(inst[i].n[l]);
+        mix(inst[i].R_f);
+        mix(inst[i].R_N);
+        mix(inst[i].G_saved != nullptr);
+    }
+    return h;
+}
+
+// Built-in: the work queue with 64-tiles below R_f = 256 for int8 batches
+// (the route measured fastest on the 64-instance workload), fork-join for
+// every other precision (the queue holds only the int8 Gram).
+constexpr int kBatchDefaultI8 = TC_BATCH_QUEUE_T64;
+
+int batch_route(const tc_instance *inst, int count, tc_precision prec)
+{
+    if (prec != TC_OZAKI_I8 || count < 2)
+        return TC_BATCH_FORK_JOIN;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_batch_tune.find(batch_signature(inst, count, prec));
+    return it != g_batch_tune.end() ? it->second : kBatchDefaultI8;
+}
+
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
@@ -375,16 +414,19 @@ tc_status int8fft_u_prep(int n, int R_f, int R_N, const double *U, const ModeScr
     return TC_OK;
 }
 
+// with_gram == false leaves the int8 Gram of the listed terms to the caller
+// (the work queue of a batch); the smooth terms' Grams are still formed here
 tc_status int8fft_u_main(int n, int R_f, int R_N, const double *p, const double *U, double *G,
                          const ModeScratch &s, const ModeScratch &kp, bool mirror,
-                         hipStream_t st)
+                         hipStream_t st, bool with_gram = true)
 {
     const int N = fft_length(n);
     const OzakiLayout L = ozaki_layout(n, R_f, R_N);
     TRYK("fft_conv_split", launch_fft_conv(s.Uspec, kp.Cspec, n, N, R_f, R_N, s.twN, nullptr,
                                            s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, U, p,
                                            kp.cls, st));
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, mirror, st));
+    if (with_gram)
+        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, mirror, st));
     if (smooth_terms_supported(n)) {
         // smooth terms: G_k = X S_k X^T with X = U Q^T
         TRYK("poly_project", launch_poly_project(U, n, R_f, kp.Q, s.Xp, s.X, st));
@@ -407,7 +449,8 @@ tc_status int8fft_u_part(int n, int R_f, int R_N, const double *p, const double 
 // G_k = U^T T_k U for all k of one mode (W is scratch).
 tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R_N,
                      const double *p, const double *U, double *W, double *G,
-                     const ModeScratch &s, hipStream_t st, bool mirror = true)
+                     const ModeScratch &s, hipStream_t st, bool mirror = true,
+                     bool with_gram = true)
 {
     if (prec == TC_FP64) {
         const tc_status r = mode_W(prec, algo, n, R_f, R_N, p, U, W, s, st);
@@ -444,7 +487,8 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
     if (algo == TC_ALGO_FFT)
         TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
     TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
-    TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, st));
+    if (with_gram)
+        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, st));
     return TC_OK;
 }
 
@@ -598,7 +642,9 @@ struct BatchPlan {
     size_t bytes = 0;
 };
 
-BatchPlan plan_batch(const tc_instance *inst, int count, tc_precision prec)
+// by_route == false sizes the regions for any route of every mode (the
+// autotuner changes the routes while it runs)
+BatchPlan plan_batch(const tc_instance *inst, int count, tc_precision prec, bool by_route = true)
 {
     BatchPlan B;
     B.branch.assign(count, 0);
@@ -617,7 +663,7 @@ BatchPlan plan_batch(const tc_instance *inst, int count, tc_precision prec)
                 best = b;
         B.branch[i] = best;
         load[best] += instance_cost(inst[i]);
-        const size_t wi = plan_instance(nullptr, inst[i], prec, false, false, true).bytes;
+        const size_t wi = plan_instance(nullptr, inst[i], prec, false, false, by_route).bytes;
         if (wi > need[best])
             need[best] = wi;
     }
@@ -768,6 +814,224 @@ tc_status forward_instance(const tc_instance &I, tc_precision prec, void *ws, si
     TRYK("hadamard_sum", launch_hadamard_sum(I.c, P.G, P.G + (size_t)I.R_N * F2,
                                              P.G + 2 * (size_t)I.R_N * F2, I.J, I.R_f, I.R_N, st));
     return TC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// int8 batches through the work queue: every mode of every instance prepares
+// its int8 slices (and its smooth-term Grams) on the branch of its instance,
+// then one persistent launch forms all the int8 Grams, then the Hadamard sums.
+// ---------------------------------------------------------------------------
+// Batch routes (tc_batch_route): fork-join, or the queue with 128-tiles or
+// with 64-tiles below R_f = 256, each with one or two K parts.
+struct QueueShape {
+    bool small_tiles;  // 64-tiles for R_f < 256
+    int kparts;
+};
+QueueShape queue_shape(int route)
+{
+    return {route == TC_BATCH_QUEUE_T64 || route == TC_BATCH_QUEUE_T64_K2,
+            route == TC_BATCH_QUEUE_K2 || route == TC_BATCH_QUEUE_T64_K2 ? 2 : 1};
+}
+
+bool queue_route(int route) { return route >= TC_BATCH_QUEUE && route <= TC_BATCH_QUEUE_T64_K2; }
+
+// Layout of the queue plan: per instance one split-plan region (its Grams and
+// one scratch region per mode), then the job table, the counter and, for two
+// K parts, one slab of Grams per job.
+struct QueuePlan {
+    std::vector<size_t> offset;  // of each instance's region
+    size_t jobs = 0, counter = 0, slabs = 0, bytes = 0;
+};
+
+QueuePlan plan_queue(const tc_instance *inst, int count, tc_precision prec, bool by_route = true)
+{
+    QueuePlan Q;
+    Q.offset.resize(count);
+    size_t used = 0;
+    for (int i = 0; i < count; ++i) {
+        Q.offset[i] = used;
+        used += align_up(plan_instance(nullptr, inst[i], prec, false, true, by_route).bytes);
+    }
+    Q.jobs = used;
+    used += align_up(sizeof(GramJob) * 3 * (size_t)count);
+    Q.counter = used;
+    used += align_up(sizeof(int));
+    Q.slabs = used;
+    for (int i = 0; i < count; ++i)
+        used += 3 * align_up(sizeof(double) * (size_t)inst[i].R_N * inst[i].R_f * inst[i].R_f);
+    Q.bytes = used;
+    return Q;
+}
+
+tc_status forward_batch_queue(const tc_instance *inst, int count, tc_precision prec, int route,
+                              void *ws, size_t ws_bytes, hipStream_t st)
+{
+    const QueuePlan Q = plan_queue(inst, count, prec);
+    if (Q.bytes > ws_bytes)
+        return TC_ERR_WORKSPACE;
+    const QueueShape shape = queue_shape(route);
+    char *base = (char *)ws;
+    const BatchPlan B = plan_batch(inst, count, prec);  // branch of each instance
+    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
+            return TC_ERR_HIP;
+    std::vector<GramJob> jobs;
+    jobs.reserve(3 * (size_t)count);
+    double *slab = (double *)(base + Q.slabs);
+    tc_status status = TC_OK;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const tc_instance &I = inst[i];
+        hipStream_t sb = g_pool.st[B.branch[i]];
+        const InstancePlan P = plan_instance(base + Q.offset[i], I, prec, false, true, true);
+        const size_t F2 = (size_t)I.R_f * I.R_f;
+        const bool mirror = I.G_saved != nullptr;
+        tc_algorithm algo[3];
+        int owner[3];
+        for (int l = 0; l < 3; ++l) {
+            algo[l] = resolve(I.n[l], I.R_f, I.R_N, prec);
+            owner[l] = l;
+            if (i8_fused_fft(prec, algo[l], I.n[l]))
+                for (int m = 0; m < l; ++m)
+                    if (owner[m] == m && i8_fused_fft(prec, algo[m], I.n[m]) &&
+                        I.p[m] == I.p[l] && I.n[m] == I.n[l]) {
+                        owner[l] = m;
+                        break;
+                    }
+        }
+        for (int l = 0; l < 3 && status == TC_OK; ++l) {
+            double *Gl = P.G + (size_t)l * I.R_N * F2;
+            const bool fused = i8_fused_fft(prec, algo[l], I.n[l]);
+            // the modes of an instance run in turn on its branch, so a
+            // borrowed kernel part is complete before it is read
+            if (!fused) {
+                status = mode_grams(prec, algo[l], I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], P.W[l],
+                                    Gl, P.ms[l], sb, mirror, false);
+            } else {
+                if (owner[l] == l)
+                    status = int8fft_kernel_part(I.n[l], I.R_N, I.p[l], P.ms[l], sb);
+                if (status == TC_OK)
+                    status = int8fft_u_prep(I.n[l], I.R_f, I.R_N, I.U[l], P.ms[l],
+                                            owner[l] != l, sb);
+                if (status == TC_OK)
+                    status = int8fft_u_main(I.n[l], I.R_f, I.R_N, I.p[l], I.U[l], Gl, P.ms[l],
+                                            P.ms[owner[l]], mirror, sb, false);
+            }
+            const OzakiLayout L = ozaki_layout(I.n[l], I.R_f, I.R_N);
+            GramJob J{};
+            J.US = P.ms[l].US;
+            J.EU = P.ms[l].EU;
+            J.WS = P.ms[l].WS;
+            J.EW = P.ms[l].EW;
+            J.cls = fused ? P.ms[owner[l]].cls : nullptr;
+            J.G = Gl;
+            J.uplane = L.uplane;
+            J.wplane = L.wplane;
+            J.n_pad = L.n_pad;
+            J.R_f_pad = L.R_f_pad;
+            J.R_f = I.R_f;
+            J.R_N = I.R_N;
+            J.tile = shape.small_tiles && I.R_f < 256 ? 64 : 128;
+            const int nt = (L.R_f_pad + J.tile - 1) / J.tile;
+            J.ntri = nt * (nt + 1) / 2;
+            J.kparts = shape.kparts;
+            J.slab = J.kparts > 1 ? slab : nullptr;
+            J.mirror = mirror ? 1 : 0;
+            jobs.push_back(J);
+            slab += align_up(sizeof(double) * (size_t)I.R_N * F2) / sizeof(double);
+        }
+    }
+    for (int b = 0; b < kBranches; ++b)
+        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+    if (status != TC_OK)
+        return status;
+    // the queue: costliest jobs first (contraction length, then tile rows)
+    std::stable_sort(jobs.begin(), jobs.end(), [](const GramJob &a, const GramJob &b) {
+        if (a.n_pad != b.n_pad)
+            return a.n_pad > b.n_pad;
+        return a.R_f_pad > b.R_f_pad;
+    });
+    long total = 0;
+    for (GramJob &J : jobs) {
+        J.item_begin = (int)total;
+        total += (long)J.R_N * J.ntri * J.kparts;
+    }
+    if (total > 0x7fffffff)
+        return TC_ERR_UNSUPPORTED;
+    TRYK("gram_queue", launch_gram_queue(jobs.data(), (int)jobs.size(), (int)total,
+                                         (GramJob *)(base + Q.jobs), (int *)(base + Q.counter),
+                                         st));
+    // the Hadamard sums, spread over the branches again
+    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
+            return TC_ERR_HIP;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const tc_instance &I = inst[i];
+        hipStream_t sb = g_pool.st[B.branch[i]];
+        const InstancePlan P = plan_instance(base + Q.offset[i], I, prec, false, true, true);
+        const size_t F2 = (size_t)I.R_f * I.R_f;
+        ProfScope ps_("hadamard_sum", sb);
+        if (launch_hadamard_sum(I.c, P.G, P.G + (size_t)I.R_N * F2, P.G + 2 * (size_t)I.R_N * F2,
+                                I.J, I.R_f, I.R_N, sb) != hipSuccess)
+            status = TC_ERR_HIP;
+        ps_.end();
+        if (status == TC_OK && debug_sync_on() && !debug_sync_check("hadamard_sum", sb))
+            status = TC_ERR_HIP;
+    }
+    for (int b = 0; b < kBranches; ++b)
+        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+    return status;
+}
+
+// Workspace of tc_autotune's batch timing: copies of the instances with J in
+// the workspace and no G_saved, run through every batch route.
+size_t autotune_batch_bytes(const tc_instance *inst, int count, tc_precision prec)
+{
+    std::vector<tc_instance> cp(inst, inst + count);
+    size_t js = 0;
+    for (tc_instance &I : cp) {
+        I.G_saved = nullptr;
+        js += align_up(sizeof(double) * (size_t)I.R_f * I.R_f);
+    }
+    return js + std::max(plan_batch(cp.data(), count, prec, false).bytes,
+                         plan_queue(cp.data(), count, prec, false).bytes);
+}
+
+// A batch through the fork-join route: every instance on a branch, its
+// modes in turn, its own per-mode launches.
+tc_status forward_batch_fork_join(const tc_instance *inst, int count, tc_precision prec, void *ws,
+                                  size_t ws_bytes, hipStream_t st)
+{
+    const BatchPlan B = plan_batch(inst, count, prec);
+    if (B.bytes > ws_bytes)
+        return TC_ERR_WORKSPACE;
+    // fork: every branch waits for the work already queued on the caller's stream
+    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
+        return TC_ERR_HIP;
+    for (int b = 0; b < kBranches; ++b)
+        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
+            return TC_ERR_HIP;
+    tc_status status = TC_OK;
+    for (int i = 0; i < count && status == TC_OK; ++i) {
+        const int b = B.branch[i];
+        const size_t end = b + 1 < kBranches ? B.offset[b + 1] : B.bytes;
+        status = forward_instance(inst[i], prec, (char *)ws + B.offset[b], end - B.offset[b],
+                                  g_pool.st[b]);
+    }
+    // join (also after a failed launch, so no branch is left forked)
+    for (int b = 0; b < kBranches; ++b) {
+        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
+            status = TC_ERR_HIP;
+    }
+    return status;
 }
 
 tc_status backward_instance(const tc_instance &I, const double *Jbar, double *const *dU,
@@ -933,29 +1197,10 @@ tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, v
     if (count == 1)  // one instance: its three modes on three branches
         return forward_instance(inst[0], prec, ws, ws_bytes, st, true);
 
-    const BatchPlan B = plan_batch(inst, count, prec);
-    if (B.bytes > ws_bytes)
-        return TC_ERR_WORKSPACE;
-    // fork: every branch waits for the work already queued on the caller's stream
-    if (hipEventRecord(g_pool.fork, st) != hipSuccess)
-        return TC_ERR_HIP;
-    for (int b = 0; b < kBranches; ++b)
-        if (hipStreamWaitEvent(g_pool.st[b], g_pool.fork, 0) != hipSuccess)
-            return TC_ERR_HIP;
-    tc_status status = TC_OK;
-    for (int i = 0; i < count && status == TC_OK; ++i) {
-        const int b = B.branch[i];
-        const size_t end = b + 1 < kBranches ? B.offset[b + 1] : B.bytes;
-        status = forward_instance(inst[i], prec, (char *)ws + B.offset[b], end - B.offset[b],
-                                  g_pool.st[b]);
-    }
-    // join (also after a failed launch, so no branch is left forked)
-    for (int b = 0; b < kBranches; ++b) {
-        if (hipEventRecord(g_pool.join[b], g_pool.st[b]) != hipSuccess ||
-            hipStreamWaitEvent(st, g_pool.join[b], 0) != hipSuccess)
-            status = TC_ERR_HIP;
-    }
-    return status;
+    const int route = batch_route(inst, count, prec);
+    if (queue_route(route))
+        return forward_batch_queue(inst, count, prec, route, ws, ws_bytes, st);
+    return forward_batch_fork_join(inst, count, prec, ws, ws_bytes, st);
 }
 }  // namespace tc
 
@@ -997,9 +1242,15 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
         for (int l = 0; l < 3; ++l)
             if (!size_ok(inst[i].n[l], inst[i].R_f, inst[i].R_N))
                 return (size_t)-1;
-    if (op == TC_OP_TEI_GRAM)
-        return count > 1 ? plan_batch(inst, count, prec).bytes
-                         : plan_instance(nullptr, inst[0], prec, false, true, true).bytes;
+    if (op == TC_OP_TEI_GRAM) {
+        if (count == 1)
+            return plan_instance(nullptr, inst[0], prec, false, true, true).bytes;
+        // every batch route the tuning table may select
+        const size_t fj = plan_batch(inst, count, prec).bytes;
+        if (prec != TC_OZAKI_I8)
+            return fj;
+        return std::max(fj, plan_queue(inst, count, prec).bytes);
+    }
     size_t w = 0;
     for (int i = 0; i < count; ++i) {
         // the autotuner's Grams go to the workspace, never to G_saved
@@ -1010,6 +1261,8 @@ size_t tc_workspace_bytes(int op, const tc_instance *inst, int count, tc_precisi
         if (wi > w)
             w = wi;
     }
+    if (op == TC_OP_AUTOTUNE && count > 1 && prec == TC_OZAKI_I8)
+        w = std::max(w, autotune_batch_bytes(inst, count, prec));
     return w;
 }
 
@@ -1028,6 +1281,34 @@ tc_status tc_tune_set(int n, int R_f, int R_N, tc_precision prec, tc_algorithm a
     else
         g_tune[key] = (int)algo;
     return TC_OK;
+}
+
+tc_status tc_batch_tune_set(const tc_instance *inst, int count, tc_precision prec,
+                            tc_batch_route route)
+{
+    if (!inst || count < 1 || !prec_known(prec) || route < TC_BATCH_AUTO ||
+        route > TC_BATCH_QUEUE_T64_K2)
+        return TC_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i)
+        for (int l = 0; l < 3; ++l)
+            if (!size_ok(inst[i].n[l], inst[i].R_f, inst[i].R_N))
+                return TC_ERR_INVALID_ARG;
+    if (queue_route(route) && prec != TC_OZAKI_I8)
+        return TC_ERR_UNSUPPORTED;
+    const uint64_t key = batch_signature(inst, count, prec);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (route == TC_BATCH_AUTO)
+        g_batch_tune.erase(key);
+    else
+        g_batch_tune[key] = (int)route;
+    return TC_OK;
+}
+
+tc_batch_route tc_batch_tune_get(const tc_instance *inst, int count, tc_precision prec)
+{
+    if (!inst || count < 1 || !prec_known(prec))
+        return TC_BATCH_AUTO;
+    return (tc_batch_route)batch_route(inst, count, prec);
 }
 
 tc_algorithm tc_tune_get(int n, int R_f, int R_N, tc_precision prec)
@@ -1647,6 +1928,49 @@ tc_status tc_autotune(const tc_instance *inst, int count, tc_precision prec, voi
                 ms_out[(i * 3 + l) * 2 + 0] = it->second.first;
                 ms_out[(i * 3 + l) * 2 + 1] = it->second.second;
             }
+        }
+    }
+    if (status == TC_OK && count > 1 && prec == TC_OZAKI_I8) {
+        // the whole batch on every route: copies of the instances with J in
+        // the workspace (the callers' J stay untouched) and no saved Grams
+        std::vector<tc_instance> cp(inst, inst + count);
+        size_t off = 0;
+        for (tc_instance &I : cp) {
+            I.G_saved = nullptr;
+            I.J = (double *)((char *)ws + off);
+            off += align_up(sizeof(double) * (size_t)I.R_f * I.R_f);
+        }
+        void *bws = (char *)ws + off;
+        const size_t bbytes = ws_bytes - off;
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!pool_init())
+            status = TC_ERR_HIP;
+        float best = -1.0f;
+        int best_route = TC_BATCH_FORK_JOIN;
+        for (int route = TC_BATCH_FORK_JOIN; route <= TC_BATCH_QUEUE_T64_K2 && status == TC_OK;
+             ++route) {
+            for (int rep = 0; rep < 3 && status == TC_OK; ++rep) {
+                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess)
+                    status = TC_ERR_HIP;
+                if (status == TC_OK)
+                    status = queue_route(route)
+                                 ? forward_batch_queue(cp.data(), count, prec, route, bws, bbytes,
+                                                       st)
+                                 : forward_batch_fork_join(cp.data(), count, prec, bws, bbytes, st);
+            }
+            float t = 0.0f;
+            if (status == TC_OK &&
+                (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                status = TC_ERR_HIP;
+            if (status == TC_OK && (best < 0.0f || t < best)) {
+                best = t;
+                best_route = route;
+            }
+        }
+        if (status == TC_OK) {
+            std::lock_guard<std::mutex> lt(g_tune_mu);
+            g_batch_tune[batch_signature(inst, count, prec)] = best_route;
         }
     }
     (void)hipEventDestroy(e0);

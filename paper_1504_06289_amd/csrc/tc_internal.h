@@ -147,6 +147,35 @@ hipError_t launch_fft_conv(const double2 *Uspec, const double2 *Cspec, int n, in
                            int R_f_pad, int n_pad, long wplane, const double *U,
                            const double *p, const int *band, hipStream_t stream);
 
+// ---- persistent int8 Gram over a device work queue (gram_queue.hip) --------
+// One job per (instance, mode); see gram_queue.hip.
+struct GramJob {
+    const int8_t *US;    // int8 slices of U [4][R_f_pad][n_pad]
+    const int *EU;       // [R_f_pad]
+    const int8_t *WS;    // int8 slices of W [4][R_N][R_f_pad][n_pad]
+    const int *EW;       // [R_N][R_f_pad]
+    const int *cls;      // term classes [R_N] (terms of class -2 skipped) or null
+    double *G;           // Grams [R_N][R_f][R_f]
+    double *slab;        // K part 1's Grams (kparts == 2) or null
+    long uplane, wplane;
+    int n_pad, R_f_pad, R_f, R_N;
+    int ntri;            // upper-triangle tiles per term
+    int tile;            // 64 or 128
+    int kparts;          // 1 or 2
+    int mirror;          // also write the lower triangle
+    int item_begin;      // first queue item of the job
+};
+constexpr int kGramJobChunk = 24;  // jobs per table-writing launch (kernel arguments)
+struct GramJobChunk {
+    int base, count;
+    GramJob job[kGramJobChunk];
+};
+// Writes the job table (host_jobs, sorted and with item_begin set) to
+// dev_jobs, zeroes the counter and runs the queue of `total` items; then adds
+// the slabs of jobs with two K parts.
+hipError_t launch_gram_queue(const GramJob *host_jobs, int njobs, int total, GramJob *dev_jobs,
+                             int *counter, hipStream_t st);
+
 // ---- FFT route beyond the LDS-resident lengths (fft_large.hip) --------------
 // 4096 < n <= 65536: N = fft_length(n) in 16384 .. 131072, four-step binary64
 // transforms with two real rows per complex sequence.

@@ -67,6 +67,10 @@ def test_enum_values_follow_the_interface():
         assert getattr(_lib, k) == v, k
     assert declared_enum("tc_algorithm") == {"TC_ALGO_AUTO": 0, "TC_ALGO_DIRECT": 1,
                                              "TC_ALGO_FFT": 2}
+    routes = declared_enum("tc_batch_route")
+    assert routes == {"TC_BATCH_AUTO": 0, "TC_BATCH_FORK_JOIN": 1, "TC_BATCH_QUEUE": 2,
+                      "TC_BATCH_QUEUE_T64": 3, "TC_BATCH_QUEUE_K2": 4, "TC_BATCH_QUEUE_T64_K2": 5}
+    assert sorted(_lib.BATCH_ROUTES.values()) == sorted(routes.values())
 
 
 def _inst(n=64, R_f=8, R_N=4, null=None):
@@ -259,6 +263,47 @@ def test_noalloc_rejects_before_any_device_call(L):
     assert L.tc_tei_gram_noalloc(ok, 0, _lib.TC_FP64, None) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_tei_gram_noalloc(ok, 1, 42, None) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_tei_gram_noalloc(None, 1, _lib.TC_FP64, None) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_batch_route_table(L):
+    """Built-in batch routes (the work queue with 64-tiles for int8 batches,
+    fork-join otherwise), per-batch entries, and the argument checks."""
+    R = _lib.BATCH_ROUTES
+    insts = (_lib.TcInstance * 3)(_inst(n=512, R_f=40), _inst(n=1024, R_f=300), _inst(n=64))
+    other = (_lib.TcInstance * 3)(_inst(n=512, R_f=41), _inst(n=1024, R_f=300), _inst(n=64))
+    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
+    assert L.tc_batch_tune_get(insts, 3, _lib.TC_FP64) == R["fork_join"]
+    assert L.tc_batch_tune_get(insts, 1, _lib.TC_OZAKI_I8) == R["fork_join"]  # one instance
+    try:
+        assert L.tc_batch_tune_set(insts, 3, _lib.TC_OZAKI_I8, R["queue_k2"]) == _lib.TC_OK
+        assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_k2"]
+        # another batch (one R_f differs) keeps the built-in route
+        assert L.tc_batch_tune_get(other, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
+        assert L.tc_batch_tune_get(insts, 2, _lib.TC_OZAKI_I8) == R["queue_t64"]
+    finally:
+        assert L.tc_batch_tune_set(insts, 3, _lib.TC_OZAKI_I8, R["auto"]) == _lib.TC_OK
+    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
+    assert L.tc_batch_tune_set(insts, 3, _lib.TC_FP64, R["queue"]) == _lib.TC_ERR_UNSUPPORTED
+    assert L.tc_batch_tune_set(insts, 3, _lib.TC_FP64, 9) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_batch_tune_set(insts, 0, _lib.TC_FP64, 1) == _lib.TC_ERR_INVALID_ARG
+    assert L.tc_batch_tune_set(None, 1, _lib.TC_FP64, 1) == _lib.TC_ERR_INVALID_ARG
+    bad = (_lib.TcInstance * 1)(_inst(n=0))
+    assert L.tc_batch_tune_set(bad, 1, _lib.TC_FP64, 1) == _lib.TC_ERR_INVALID_ARG
+
+
+def test_int8_batch_workspace_covers_the_queue(L):
+    """An int8 batch's workspace covers both routes: the fork-join regions and
+    the queue plan (every instance's own regions, the job table and one slab
+    of Grams per mode for two K parts)."""
+    insts = (_lib.TcInstance * 3)(_inst(n=512, R_f=40), _inst(n=1024, R_f=300), _inst(n=64))
+    w8 = L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, insts, 3, _lib.TC_OZAKI_I8)
+    single = sum(L.tc_workspace_bytes(_lib.TC_OP_TEI_GRAM, (_lib.TcInstance * 1)(insts[i]), 1,
+                                      _lib.TC_OZAKI_I8) for i in range(3))
+    up = lambda x: (x + 255) // 256 * 256
+    slabs = sum(3 * up(8 * I.R_N * I.R_f * I.R_f) for I in insts)
+    assert w8 >= single + slabs
+    tune = L.tc_workspace_bytes(_lib.TC_OP_AUTOTUNE, insts, 3, _lib.TC_OZAKI_I8)
+    assert tune >= w8 + sum(up(8 * I.R_f * I.R_f) for I in insts)
 
 
 def test_tuning_table(L):

@@ -136,20 +136,43 @@ def _check_batch(Js, chosen, refs, tol, tag):
     say(f"   {tag}: worst normalised column error {worst:.2e}")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "ozaki8"])
-def test_batched_c4_subset(tc, c4_subset, prec):
+_EAGER = {}
+
+
+@pytest.mark.parametrize("prec,route", [("fp64", "auto"), ("ozaki8", "fork_join"),
+                                        ("ozaki8", "queue"), ("ozaki8", "queue_t64"),
+                                        ("ozaki8", "queue_k2"), ("ozaki8", "queue_t64_k2"),
+                                        ("ozaki8", "auto")])
+def test_batched_c4_subset(tc, c4_subset, prec, route):
+    """The 8-instance subset on every batch route: eager against the oracle
+    columns, graph replays bitwise equal to the eager batch.  Every
+    work-queue route gives bitwise the fork-join J: the int8 products
+    accumulate exactly whatever the tile, and the binary64 recombination of a
+    tile's int32 sums spans at most 53 bits, so it is exact, also for each of
+    two K parts and for their sum.
+    "auto": the autotuner picks the Toeplitz algorithm per mode shape and
+    (int8) the batch route, as the benchmark runs the batch."""
     chosen, refs = c4_subset
-    say(f"batched c4 subset {prec}")
     batch = _batch(chosen, refs)
     tol = TOL[prec]
-    # the autotuner's direct/FFT choice per distinct mode shape, as the
-    # benchmark runs the batch
     shapes = sorted({(w.n[0], w.R_f, w.R_N) for w in chosen})
     try:
-        tc.autotune_batched(batch, prec=prec)
+        if route == "auto":
+            tc.autotune_batched(batch, prec=prec)
+        else:
+            tc.batch_tune_set(batch, prec, route)
+        used = tc.batch_tune_get(batch, prec)
+        say(f"batched c4 subset {prec}: route {route} -> {used}")
         eager = tc.tei_gram_batched(batch, prec=prec)
-        _check_batch(eager, chosen, refs, tol, "eager")
+        _check_batch(eager, chosen, refs, tol, f"eager ({used})")
         eager_h = [host(J) for J in eager]
+        if route != "auto":
+            _EAGER[(prec, route)] = eager_h
+            ref = _EAGER.get((prec, "fork_join"))
+            if ref is not None and route != "fork_join":
+                for Jq, Jf in zip(eager_h, ref):
+                    np.testing.assert_array_equal(Jq, Jf)
+                say("   bitwise equal to the fork-join batch")
         g = tc.TeiGramGraph(batch, prec=prec)
         for rep in range(3):
             Js = g.replay()
@@ -162,6 +185,38 @@ def test_batched_c4_subset(tc, c4_subset, prec):
     finally:
         for sh in shapes:
             tc.tune_set(*sh, prec, "auto")
+        tc.batch_tune_set(batch, prec, "auto")
+
+
+@pytest.mark.parametrize("route", ["queue", "queue_t64", "queue_k2", "queue_t64_k2"])
+def test_queue_batch_saved_grams(tc, orc, route):
+    """Saved Grams (both triangles, as the adjoint reads them) from the work
+    queue, bitwise those of the fork-join route, with smooth, narrow and
+    general terms (FFT route), the direct route and ragged R_f."""
+    specs = [(300, 100, 24), (257, 300, 12), (64, 9, 4), (130, 70, 5)]
+    batch, ws_ = [], []
+    for i, (n, R_f, R_N) in enumerate(specs):
+        w = wl.small_products(n, R_f, R_N=R_N, b=8.0, seed=70 + i)
+        c, ps = oracle_setup(orc, w)
+        batch.append((dev(c), [dev(p) for p in ps], [dev(u) for u in w.U]))
+        ws_.append((w, c, ps))
+    try:
+        # a batch that keeps its Grams has its own entry in the tuning table
+        tc.batch_tune_set(batch, "ozaki8", "fork_join", save_G=True)
+        assert tc.batch_tune_get(batch, "ozaki8", save_G=True) == "fork_join"
+        Jf, Gf = tc.tei_gram_batched(batch, prec="ozaki8", save_G=True)
+        Gf = [host(G) for G in Gf]
+        Jf = [host(J) for J in Jf]
+        tc.batch_tune_set(batch, "ozaki8", route, save_G=True)
+        Jq, Gq = tc.tei_gram_batched(batch, prec="ozaki8", save_G=True)
+    finally:
+        tc.batch_tune_set(batch, "ozaki8", "auto", save_G=True)
+    for (w, c, ps), J1, G1, J2, G2 in zip(ws_, Jf, Gf, Jq, Gq):
+        J2, G2 = host(J2), host(G2)
+        np.testing.assert_array_equal(G2, np.swapaxes(G2, -1, -2))
+        np.testing.assert_array_equal(G2, G1)
+        np.testing.assert_array_equal(J2, J1)
+        assert e_J(J2, orc.tei_gram(c, ps, w.U)) <= 1e-7
 
 
 # --------------------------------------------------------------------------
