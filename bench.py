@@ -422,11 +422,53 @@ def extra_rows(tc, wl, torch, dev, args):
         batch.append((c, [p, p, p], [torch.from_numpy(u).to(dev) for u in wi.U]))
     Fb = sum(wi.flops() for wi in insts)
     for prec in ("fp64", "ozaki8"):
-        # direct/FFT choice per distinct mode shape from the autotuner
+        # direct/FFT choice per distinct mode shape and (int8) the batch route
+        # from the autotuner; the batch then runs as one captured graph
         tc.autotune_batched(batch, prec=prec)
+        route = tc.batch_tune_get(batch, prec)
         msb = timed(lambda: tc.tei_gram_batched(batch, prec=prec), 2, 1, torch)
+        g = tc.TeiGramGraph(batch, prec=prec)
+        msg = timed(g.replay, 3, 1, torch)
+        del g
+        rows[f"batched_c4_{prec}_route"] = route
         rows[f"batched_c4_{prec}_ms"] = round(msb, 3)
-        rows[f"batched_c4_{prec}_GFLOPs"] = round(Fb / (msb * 1e-3) / 1e9, 1)
+        rows[f"batched_c4_{prec}_graph_ms"] = round(msg, 3)
+        rows[f"batched_c4_{prec}_GFLOPs"] = round(Fb / (msg * 1e-3) / 1e9, 1)
+        if prec == "ozaki8":
+            # every batch route, eager (A/B of the work queue against fork-join)
+            per_route = {}
+            for r in ("fork_join", "queue", "queue_t64", "queue_k2", "queue_t64_k2"):
+                tc.batch_tune_set(batch, prec, r)
+                per_route[r] = round(timed(lambda: tc.tei_gram_batched(batch, prec=prec), 2, 1,
+                                           torch), 3)
+            tc.batch_tune_set(batch, prec, route)
+            rows["batched_c4_ozaki8_ms_per_route"] = per_route
+            # the persistent Gram launch of the queue route, timed by the library
+            tc.batch_tune_set(batch, prec, "queue_t64")
+            tc.profile_enable(True)
+            tc.profile_read()
+            tc.tei_gram_batched(batch, prec=prec)
+            prof = tc.profile_read()
+            tc.profile_enable(False)
+            tc.batch_tune_set(batch, prec, route)
+            gq = prof.get("gram_queue")
+            if gq:
+                # ten int8 slice products over the upper triangles of the
+                # Grams of every listed term (all terms on the direct route,
+                # the non-smooth ones on the int8 FFT route)
+                ops = 0.0
+                for wi, (c, p3, U3) in zip(insts, batch):
+                    nl, R_f = wi.n[0], wi.R_f
+                    if tc.tune_get(nl, R_f, wi.R_N, prec) == "fft" and nl <= 4096:
+                        nk = int((tc.term_classes(p3[0]) != -2).sum())
+                    else:
+                        nk = wi.R_N
+                    ops += 3 * 10.0 * nk * nl * R_f * (R_f + 1)
+                rows["batched_c4_gram_queue"] = {
+                    "kernel_ms": round(gq[0], 4), "launches": gq[1],
+                    "TOP/s": round(ops / (gq[0] * 1e-3) / 1e12, 1),
+                    "frac_int8_peak": round(ops / (gq[0] * 1e-3) / 1e12 / PEAK["int8"], 4),
+                    "work": "10 slice products x n R_f (R_f + 1) per listed term and mode"}
     rows["batched_c4_flops"] = Fb
     # Coulomb entries of the 4096-cell functions against a 64-term density
     w3 = wl.config("c3")

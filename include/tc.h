@@ -140,9 +140,10 @@ typedef enum {
  * term, tile[, K part]) items sorted by cost (contraction length first), then
  * the Hadamard sums follow; the variants choose the tile edge (128, or 64 for
  * instances with R_f < 256) and whether each tile's contraction is split in
- * two parts (added in a fixed order).  TC_BATCH_AUTO: the batch's entry in
- * the tuning table (set by tc_batch_tune_set or tc_autotune), else
- * TC_BATCH_QUEUE_T64 for TC_OZAKI_I8 and TC_BATCH_FORK_JOIN otherwise. */
+ * two parts (added in a fixed order; the results are bitwise those of the
+ * fork-join route: the int8 sums are exact and their binary64 recombination
+ * spans at most 53 bits).  TC_BATCH_AUTO: the batch's entry in the tuning
+ * table (set by tc_batch_tune_set or tc_autotune), else TC_BATCH_FORK_JOIN. */
 typedef enum {
     TC_BATCH_AUTO = 0,
     TC_BATCH_FORK_JOIN = 1,

@@ -122,10 +122,11 @@ uint64_t batch_signature(const tc_instance *inst, int count, tc_precision prec)
     return h;
 }
 
-// Built-in: the work queue with 64-tiles below R_f = 256 for int8 batches
-// (the route measured fastest on the 64-instance workload), fork-join for
-// every other precision (the queue holds only the int8 Gram).
-constexpr int kBatchDefaultI8 = TC_BATCH_QUEUE_T64;
+// Built-in: fork-join.  On the 64-instance workload (int8) it measured
+// 31.7 ms against 33.3 ms for the work queue: the queue's Grams start only
+// once every instance has its slices, so they no longer overlap the other
+// instances' convolutions; tc_autotune measures both per batch.
+constexpr int kBatchDefaultI8 = TC_BATCH_FORK_JOIN;
 
 int batch_route(const tc_instance *inst, int count, tc_precision prec)
 {

@@ -266,23 +266,23 @@ def test_noalloc_rejects_before_any_device_call(L):
 
 
 def test_batch_route_table(L):
-    """Built-in batch routes (the work queue with 64-tiles for int8 batches,
-    fork-join otherwise), per-batch entries, and the argument checks."""
+    """Built-in batch route (fork-join), per-batch entries, and the argument
+    checks."""
     R = _lib.BATCH_ROUTES
     insts = (_lib.TcInstance * 3)(_inst(n=512, R_f=40), _inst(n=1024, R_f=300), _inst(n=64))
     other = (_lib.TcInstance * 3)(_inst(n=512, R_f=41), _inst(n=1024, R_f=300), _inst(n=64))
-    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
+    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["fork_join"]
     assert L.tc_batch_tune_get(insts, 3, _lib.TC_FP64) == R["fork_join"]
     assert L.tc_batch_tune_get(insts, 1, _lib.TC_OZAKI_I8) == R["fork_join"]  # one instance
     try:
         assert L.tc_batch_tune_set(insts, 3, _lib.TC_OZAKI_I8, R["queue_k2"]) == _lib.TC_OK
         assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_k2"]
         # another batch (one R_f differs) keeps the built-in route
-        assert L.tc_batch_tune_get(other, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
-        assert L.tc_batch_tune_get(insts, 2, _lib.TC_OZAKI_I8) == R["queue_t64"]
+        assert L.tc_batch_tune_get(other, 3, _lib.TC_OZAKI_I8) == R["fork_join"]
+        assert L.tc_batch_tune_get(insts, 2, _lib.TC_OZAKI_I8) == R["fork_join"]
     finally:
         assert L.tc_batch_tune_set(insts, 3, _lib.TC_OZAKI_I8, R["auto"]) == _lib.TC_OK
-    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["queue_t64"]
+    assert L.tc_batch_tune_get(insts, 3, _lib.TC_OZAKI_I8) == R["fork_join"]
     assert L.tc_batch_tune_set(insts, 3, _lib.TC_FP64, R["queue"]) == _lib.TC_ERR_UNSUPPORTED
     assert L.tc_batch_tune_set(insts, 3, _lib.TC_FP64, 9) == _lib.TC_ERR_INVALID_ARG
     assert L.tc_batch_tune_set(insts, 0, _lib.TC_FP64, 1) == _lib.TC_ERR_INVALID_ARG
