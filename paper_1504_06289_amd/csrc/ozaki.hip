@@ -441,6 +441,7 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
 // reads (sixteen consecutive rows, one chunk) hit distinct banks both for 8-
 // and for 16-lane service groups.
 constexpr int GT2 = 128;
+constexpr int kTailSlots = kOzakiTailSlots;  // slots per XCD for later K parts of tail items
 constexpr int GW_ROW = 64;
 constexpr int GW_PLANE = GT2 * GW_ROW;    // one slice of one operand
 constexpr int GW_BYTES = 4 * GW_PLANE;    // 32768 per operand
@@ -450,43 +451,102 @@ __device__ inline int gw_offset(int sl, int row, int c16)
     return sl * GW_PLANE + row * GW_ROW + 16 * (c16 ^ swz);
 }
 
+// The (term, tile) items of XCD x, in the order its workgroups take them:
+// with term classes (FFT route) the items of the nk listed terms in term
+// order, cut into eight contiguous chunks; otherwise the terms x, x + 8, ...
+// with all their tiles.  Of the list's Ix items, the first
+// floor(Ix / cux) cux are whole (full rounds of the XCD's cux CUs); the rem
+// items of the last, partial round are split into P K ranges each (P at most
+// kTailParts, cux / rem and 1 + kTailSlots / rem), so that round holds
+// rem P <= cux shorter items.  Part 0 of a split item writes the Gram tile,
+// parts 1 .. P-1 write partial tiles to slots of the tail slab, and
+// gram_i8_tail_sum adds them in part order.  Each part's binary64
+// recombination of its exact int32 sums is exact (it spans at most 53
+// bits), and so is every partial sum of the parts: the result is bitwise
+// that of the unsplit tile.
+constexpr int kTailParts = 4;
+struct XcdList {
+    int Ix, full, rem, P, start;
+};
+__device__ inline XcdList xcd_list(int x, const int *__restrict__ cls, int R_N, int ntri, int cux)
+{
+    XcdList L;
+    if (cls) {
+        int nk = 0;
+        for (int kk = 0; kk < R_N; ++kk)
+            nk += cls[kk] != -2;
+        const int tot = nk * ntri, per = (tot + 7) / 8;
+        L.start = x * per;
+        L.Ix = tot - L.start < per ? tot - L.start : per;
+        if (L.Ix < 0)
+            L.Ix = 0;
+    } else {
+        L.start = 0;
+        L.Ix = x < R_N ? ((R_N - x + 7) / 8) * ntri : 0;
+    }
+    L.full = (L.Ix / cux) * cux;
+    L.rem = L.Ix - L.full;
+    L.P = 1;
+    if (L.rem > 0) {
+        L.P = cux / L.rem;
+        if (L.P > 1 + kTailSlots / L.rem)
+            L.P = 1 + kTailSlots / L.rem;
+        L.P = L.P < 1 ? 1 : L.P > kTailParts ? kTailParts : L.P;
+    }
+    return L;
+}
+// term and tile of list index li of XCD x (k < 0: nothing to do)
+__device__ inline void xcd_item(const XcdList &L, int x, int li, const int *__restrict__ cls,
+                                int R_N, int ntri, int &k, int &t)
+{
+    if (cls) {
+        const int gi = L.start + li;
+        t = gi % ntri;
+        k = nth_listed_term(cls, R_N, gi / ntri);
+    } else {
+        k = x + 8 * (li / ntri);
+        t = li % ntri;
+    }
+}
+
+// slot of part p >= 1 of tail item r of XCD x: [8][kTailSlots] slots of
+// GT2 x GT2 doubles
+__device__ inline double *tail_slot(double *slab, int x, int r, int p, int P)
+{
+    return slab + ((long)x * kTailSlots + r * (P - 1) + (p - 1)) * GT2 * GT2;
+}
+
 __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
     int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri,
-    const int *__restrict__ cls, int mirror)
+    const int *__restrict__ cls, int mirror, int cux, double *__restrict__ slab)
 {
     __shared__ __attribute__((aligned(16))) int8_t As[2][GW_BYTES];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][GW_BYTES];
 
+    // work item w runs on XCD w mod 8; local = w / 8 indexes that XCD's list
     const int w = blockIdx.x;
-    int k, t;
-    if (cls) {
-        // the nk terms of class other than -2: the nk * ntri items in term
-        // order, cut into eight contiguous chunks, chunk x on XCD x (work
-        // item w runs on XCD w mod 8), so the workgroups on one XCD share
-        // one term's U and W blocks in its L2
-        int nk = 0;
-        for (int kk = 0; kk < R_N; ++kk)
-            nk += cls[kk] != -2;
-        const int per = (nk * ntri + 7) / 8;
-        const int local = w >> 3;
-        if (local >= per)
-            return;
-        const int gi = (w & 7) * per + local;
-        if (gi >= nk * ntri)
-            return;
-        t = gi % ntri;
-        k = nth_listed_term(cls, R_N, gi / ntri);
-        if (k < 0)
-            return;
+    const int xcd = w & 7, local = w >> 3;
+    const XcdList XL = xcd_list(xcd, cls, R_N, ntri, slab ? cux : 1 << 30);
+    int li, part = 0, parts = 1, tail = 0;
+    if (local < XL.full || !slab) {
+        li = local;
     } else {
-        const int xcd = w & 7, local = w >> 3;
-        k = xcd + 8 * (local / ntri);
-        t = local % ntri;
-        if (k >= R_N)
+        const int j = local - XL.full;
+        if (j >= XL.rem * XL.P)
             return;
+        tail = j / XL.P;
+        li = XL.full + tail;
+        part = j % XL.P;
+        parts = XL.P;
     }
+    if (li >= XL.Ix)
+        return;
+    int k, t;
+    xcd_item(XL, xcd, li, cls, R_N, ntri, k, t);
+    if (k < 0 || k >= R_N)
+        return;
     int tj = 0;
     while ((tj + 1) * (tj + 2) / 2 <= t)
         ++tj;
@@ -535,20 +595,21 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     // loaded during step s-1), and stage s+2 is then loaded into those
     // registers, so the LDS writes overlap this step's matrix-core work
     // instead of preceding the barrier.
-    const int nsteps = n_pad / TK;
-    load_stage(0);
+    // this item's K steps [s0, s0 + nsteps)
+    const int ktot = n_pad / TK;
+    const int s0 = (int)((long)part * ktot / parts);
+    const int nsteps = (int)((long)(part + 1) * ktot / parts) - s0;
+    load_stage(s0 * TK);
     store_stage(0);
     if (nsteps > 1)
-        load_stage(TK);
+        load_stage((s0 + 1) * TK);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1;
-        // the other buffer was last read in step s-1, before the barrier that ended it
-        if (s + 1 < nsteps)
-            store_stage(cur ^ 1);
-        if (s + 2 < nsteps)
-            load_stage((s + 2) * TK);
-        v4i afr[2][4];
+        // this step's A fragments and first B fragments are read before the
+        // next stage is written, so these reads lead the writes in the LDS
+        // queue and the first products need not wait behind them
+        v4i afr[2][4], bfr0[4];
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
@@ -556,12 +617,21 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
                 afr[x][sl] = *reinterpret_cast<const v4i *>(As[cur] +
                                                             gw_offset(sl, wi + 16 * x + l16, g));
 #pragma unroll
+        for (int y = 0; y < 4; ++y)
+            bfr0[y] = *reinterpret_cast<const v4i *>(Bs[cur] + gw_offset(0, wj + 16 * y + l16, g));
+        // the other buffer was last read in step s-1, before the barrier that ended it
+        if (s + 1 < nsteps)
+            store_stage(cur ^ 1);
+        if (s + 2 < nsteps)
+            load_stage((s0 + s + 2) * TK);
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
             v4i bfr[4];
 #pragma unroll
             for (int y = 0; y < 4; ++y)
-                bfr[y] = *reinterpret_cast<const v4i *>(Bs[cur] +
-                                                        gw_offset(j, wj + 16 * y + l16, g));
+                bfr[y] = j == 0 ? bfr0[y]
+                                : *reinterpret_cast<const v4i *>(Bs[cur] +
+                                                                 gw_offset(j, wj + 16 * y + l16, g));
 #pragma unroll
             for (int i = 0; i + j <= 3; ++i)
 #pragma unroll
@@ -574,8 +644,27 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
         __syncthreads();
     }
 
-    double *Gk = G + (long)k * R_f * R_f;
     const int *EWk = EW + (long)k * R_f_pad;
+    if (part > 0) {
+        // a later K part of a split tail item: the partial tile to its slot
+        double *sl = tail_slot(slab, xcd, tail, part, parts);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = wi + 16 * x + 4 * g + r;
+                const int i = i0 + a;
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const int b = wj + 16 * y + l16;
+                    const int j = j0 + b;
+                    if (i < R_f && j < R_f && i <= j)
+                        sl[a * GT2 + b] = combine(acc[x][y], r, EU[i] + EWk[j]);
+                }
+            }
+        return;
+    }
+    double *Gk = G + (long)k * R_f * R_f;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -589,11 +678,46 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
                 if (j < R_f && i <= j) {
                     const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
                     Gk[(long)i * R_f + j] = v;
-                    if (mirror)
+                    if (mirror && parts == 1)
                         Gk[(long)j * R_f + i] = v;
                 }
             }
         }
+}
+
+// The split tail items: part 0's tile in G plus the later parts' slots, in
+// part order; then the mirrored entries.  Workgroup (x, r): tail item r of
+// XCD x.
+__global__ __launch_bounds__(256) void gram_i8_tail_sum(double *__restrict__ G, int R_f, int R_N,
+                                                        int ntri, const int *__restrict__ cls,
+                                                        int mirror, int cux,
+                                                        const double *__restrict__ slab)
+{
+    const int x = blockIdx.x, r = blockIdx.y;
+    const XcdList XL = xcd_list(x, cls, R_N, ntri, cux);
+    if (XL.P < 2 || r >= XL.rem)
+        return;
+    int k, t;
+    xcd_item(XL, x, XL.full + r, cls, R_N, ntri, k, t);
+    if (k < 0 || k >= R_N)
+        return;
+    int tj = 0;
+    while ((tj + 1) * (tj + 2) / 2 <= t)
+        ++tj;
+    const int ti = t - tj * (tj + 1) / 2;
+    double *Gk = G + (long)k * R_f * R_f;
+    for (int e = threadIdx.x; e < GT2 * GT2; e += 256) {
+        const int a = e / GT2, b = e % GT2;
+        const int i = ti * GT2 + a, j = tj * GT2 + b;
+        if (i >= R_f || j >= R_f || i > j)
+            continue;
+        double v = Gk[(long)i * R_f + j];
+        for (int p = 1; p < XL.P; ++p)
+            v += tail_slot(const_cast<double *>(slab), x, r, p, XL.P)[a * GT2 + b];
+        Gk[(long)i * R_f + j] = v;
+        if (mirror)
+            Gk[(long)j * R_f + i] = v;
+    }
 }
 
 }  // namespace
@@ -637,20 +761,47 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
     return hipGetLastError();
 }
 
+bool gram_i8_wide(int R_f, int R_f_pad) { return R_f >= 256 && R_f_pad % GT2 == 0; }
+
+static int cus_per_xcd()
+{
+    static int cux[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 32;
+    if (!cux[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v < 8)
+            v = 256;
+        cux[dev] = v / 8;
+    }
+    return cux[dev];
+}
+
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
-                          bool mirror, hipStream_t stream)
+                          bool mirror, double *tail, hipStream_t stream)
 {
-    if (R_f >= 256 && L.R_f_pad % GT2 == 0) {
+    if (gram_i8_wide(R_f, L.R_f_pad)) {
         const int nt = L.R_f_pad / GT2;
         const int ntri = nt * (nt + 1) / 2;
         // all terms: for every XCD x, the terms k = x, x + 8, ... each with ntri
         // tiles; classes given: the items of the listed terms in eight
-        // contiguous chunks, one per XCD (a multiple of 8 items, the excess exits)
-        const int items = cls ? 8 * ((R_N * ntri + 7) / 8) : 8 * ((R_N + 7) / 8) * ntri;
+        // contiguous chunks, one per XCD; with a tail slab, up to kTailSlots
+        // more workgroups per XCD for the later K parts of the last round
+        // (a multiple of 8 workgroups, the excess exits)
+        const int per = cls ? (R_N * ntri + 7) / 8 : ((R_N + 7) / 8) * ntri;
+        const int cux = cus_per_xcd();
+        const int items = 8 * (per + (tail ? kTailSlots : 0));
         hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
                            L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
-                           cls, (int)mirror);
+                           cls, (int)mirror, cux, tail);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !tail)
+            return e;
+        hipLaunchKernelGGL(gram_i8_tail_sum, dim3(8, cux), dim3(256), 0, stream, G, R_f, R_N,
+                           ntri, cls, (int)mirror, cux, tail);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;

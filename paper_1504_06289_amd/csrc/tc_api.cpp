@@ -179,6 +179,7 @@ struct ModeScratch {
     double2 *Cl = nullptr;     // spectra of the kernel embeddings
     double2 *Tl = nullptr;     // inverse scratch
     int *El = nullptr;         // row exponents of U (the pairs' scales)
+    double *tail = nullptr;    // later K parts of the int8 Gram's split tail items
 };
 
 // large_fft: reserve the scratch of the four-step FFT route (n > 4096)
@@ -195,6 +196,8 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
         if (gram) {
             s.WS = c.take<int8_t>(4 * (size_t)L.wplane);
             s.EW = c.take<int>((size_t)R_N * L.R_f_pad);
+            if (gram_i8_wide(R_f, L.R_f_pad))
+                s.tail = c.take<double>(kOzakiTailBytes / sizeof(double));
         }
     }
     if (row_scaled(prec)) {
@@ -427,7 +430,8 @@ tc_status int8fft_u_main(int n, int R_f, int R_N, const double *p, const double 
                                            s.WS, s.EW, L.R_f_pad, L.n_pad, L.wplane, U, p,
                                            kp.cls, st));
     if (with_gram)
-        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, mirror, st));
+        TRYK("gram_i8",
+             launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, kp.cls, mirror, s.tail, st));
     if (smooth_terms_supported(n)) {
         // smooth terms: G_k = X S_k X^T with X = U Q^T
         TRYK("poly_project", launch_poly_project(U, n, R_f, kp.Q, s.Xp, s.X, st));
@@ -489,7 +493,8 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
         TRYK("split_rows", launch_split_rows(U, 1, R_f, n, L.R_f_pad, L.n_pad, L.uplane, s.US, s.EU, st));
     TRYK("split_rows_W", launch_split_rows(W, R_N, R_f, n, L.R_f_pad, L.n_pad, L.wplane, s.WS, s.EW, st));
     if (with_gram)
-        TRYK("gram_i8", launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, st));
+        TRYK("gram_i8",
+             launch_gram_i8(s.US, s.EU, s.WS, s.EW, L, G, R_f, R_N, nullptr, mirror, s.tail, st));
     return TC_OK;
 }
 

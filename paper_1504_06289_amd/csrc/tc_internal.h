@@ -120,10 +120,16 @@ hipError_t launch_toeplitz_i8(const int8_t *US, const int *EU, const int8_t *PS,
                               const OzakiLayout &L, double *W, int n, int R_f, int R_N,
                               hipStream_t stream);
 // G[k][i][j] = sum_a U[i][a] W[k][j][a] from the slices (binary64, symmetric),
-// for every k, or (cls != nullptr, device [R_N]) for the k with cls[k] != -2 only
+// for every k, or (cls != nullptr, device [R_N]) for the k with cls[k] != -2 only.
+// tail (kOzakiTailBytes of scratch, or null): with the 128-tile kernel, the
+// items of the last, partial round of each XCD are split in K and their later
+// parts summed from there (bitwise the unsplit result).
+constexpr int kOzakiTailSlots = 16;
+constexpr size_t kOzakiTailBytes = (size_t)8 * kOzakiTailSlots * 128 * 128 * sizeof(double);
+bool gram_i8_wide(int R_f, int R_f_pad);
 hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, const int *EW,
                           const OzakiLayout &L, double *G, int R_f, int R_N, const int *cls,
-                          bool mirror, hipStream_t stream);
+                          bool mirror, double *tail, hipStream_t stream);
 
 // ---- FFT route (fft.hip) ---------------------------------------------------
 // N = smallest power of two >= 2n-1; the route needs N/2 <= 4096 (n <= 4096).
