@@ -71,93 +71,6 @@ __global__ __launch_bounds__(CT) void fit_column_reduce(const double *__restrict
     col[a] = s;
 }
 
-// y[l][k][s] = sum_t M^l_k[s][t] V^l[j][t] for the pivot j (one workgroup per
-// (l, k), threads over s)
-// y^l_k = M^l_k v_j (v_j the pivot's row of V^l): workgroup (l k, row block)
-// takes 64 rows s, its 4 waves the t = g mod 4 terms of each, summed in a
-// fixed order.  M is symmetric: row s is read as column s, so that the
-// lanes' loads are contiguous.
-constexpr int kYRows = 64;
-constexpr int kYGroups = 4;
-
-__global__ __launch_bounds__(kYRows * kYGroups) void tei_y_kernel(
-    const double *__restrict__ V0, const double *__restrict__ V1, const double *__restrict__ V2,
-    const double *__restrict__ M0, const double *__restrict__ M1, const double *__restrict__ M2,
-    int R, int R_N, const int *__restrict__ state, double *__restrict__ y)
-{
-    __shared__ double red[kYGroups][kYRows + 1];
-    if (state[1])
-        return;
-    const int l = blockIdx.x / R_N, k = blockIdx.x % R_N;
-    const double *V = l == 0 ? V0 : (l == 1 ? V1 : V2);
-    const double *M = (l == 0 ? M0 : (l == 1 ? M1 : M2)) + (long)k * R * R;
-    const double *vj = V + (long)state[0] * R;
-    const int sl = threadIdx.x % kYRows, g = threadIdx.x / kYRows;
-    const int s = blockIdx.y * kYRows + sl;
-    double acc = 0.0;
-    if (s < R)
-        for (int t = g; t < R; t += kYGroups)
-            acc = fma(M[(long)t * R + s], vj[t], acc);
-    red[g][sl] = acc;
-    __syncthreads();
-    if (g == 0 && s < R) {
-        double v = red[0][sl];
-        for (int h = 1; h < kYGroups; ++h)
-            v += red[h][sl];
-        y[((long)l * R_N + k) * R + s] = v;
-    }
-}
-
-// col[i] = sum_k c_k prod_l Z^l[i][k] with Z^l = V^l y^l^T (the column of B
-// at the pivot; Z from cross_gram_f64)
-__global__ __launch_bounds__(CT) void tei_column_kernel(const double *__restrict__ c,
-                                                        const double *__restrict__ Z, int R_N,
-                                                        int N_pair,
-                                                        const int *__restrict__ state,
-                                                        double *__restrict__ col)
-{
-    const int i = blockIdx.x * CT + threadIdx.x;
-    if (i >= N_pair || state[1])
-        return;
-    const long plane = (long)N_pair * R_N;
-    double s = 0.0;
-    for (int k = 0; k < R_N; ++k) {
-        const long o = (long)i * R_N + k;
-        s += c[k] * (Z[o] * Z[plane + o] * Z[2 * plane + o]);
-    }
-    col[i] = s;
-}
-
-// d[i] = B(i, i) = sum_k c_k prod_l V^l[i] . Y^l[k][i] with Y^l_k = V^l M^l_k
-// (from cross_gram_f64; M symmetric)
-__global__ __launch_bounds__(CT) void tei_diag_kernel(const double *__restrict__ c,
-                                                      const double *__restrict__ V0,
-                                                      const double *__restrict__ V1,
-                                                      const double *__restrict__ V2,
-                                                      const double *__restrict__ Y, int R,
-                                                      int R_N, int N_pair,
-                                                      double *__restrict__ d)
-{
-    const int i = blockIdx.x * CT + threadIdx.x;
-    if (i >= N_pair)
-        return;
-    const double *v[3] = {V0 + (long)i * R, V1 + (long)i * R, V2 + (long)i * R};
-    const long plane = (long)R_N * N_pair * R;
-    double s = 0.0;
-    for (int k = 0; k < R_N; ++k) {
-        double prod = c[k];
-        for (int l = 0; l < 3; ++l) {
-            const double *yk = Y + l * plane + ((long)k * N_pair + i) * R;
-            double q = 0.0;
-            for (int a = 0; a < R; ++a)
-                q = fma(v[l][a], yk[a], q);
-            prod *= q;
-        }
-        s += prod;
-    }
-    d[i] = s;
-}
-
 // step r: L_r = (col - sum_{s<r} L_s L_s[p]) / sqrt(d[p]), zero on the
 // earlier pivots; d -= L_r^2; d[p] = 0
 // One step: column r of L at every index a, with the sum over the earlier
@@ -168,8 +81,8 @@ constexpr int kStepA = 64;
 constexpr int kStepG = 16;
 
 __global__ __launch_bounds__(kStepA * kStepG) void chol_step_kernel(
-    const double *__restrict__ col, double *__restrict__ L, int N, int r,
-    const int *__restrict__ ispiv, const int *__restrict__ state, double *__restrict__ d)
+    const double *__restrict__ col, const double *__restrict__ A, double *__restrict__ L, int N,
+    int r, const int *__restrict__ ispiv, const int *__restrict__ state, double *__restrict__ d)
 {
     __shared__ double red[kStepG][kStepA + 1];
     if (state[1])
@@ -184,7 +97,9 @@ __global__ __launch_bounds__(kStepA * kStepG) void chol_step_kernel(
     red[g][al] = sum;
     __syncthreads();
     if (g == 0 && a < N) {
-        double v = col[a];
+        // the pivot's column of A: from the formed matrix (symmetric, so its
+        // row p), or as computed by the column kernels
+        double v = A ? A[(long)p * N + a] : col[a];
         for (int h = 0; h < kStepG; ++h)
             v -= red[h][al];
         double l = v / sqrt(d[p]);
@@ -207,7 +122,9 @@ __global__ __launch_bounds__(kStepA * kStepG) void chol_step_kernel(
 __global__ __launch_bounds__(1024) void chol_select_kernel(double *__restrict__ d, int N,
                                                            int clear, int steps, double thr,
                                                            int R_max, int *__restrict__ state,
-                                                           double *__restrict__ stats)
+                                                           double *__restrict__ stats,
+                                                           int *__restrict__ piv,
+                                                           int *__restrict__ ispiv)
 {
     __shared__ double smax[1024], ssum[1024];
     __shared__ int sidx[1024];
@@ -253,7 +170,10 @@ __global__ __launch_bounds__(1024) void chol_select_kernel(double *__restrict__ 
             state[1] = 1;
             state[2] = steps;
         } else {
+            // the next pivot, recorded as step `steps`
             state[0] = sidx[0];
+            piv[steps] = sidx[0];
+            ispiv[sidx[0]] = 1;
         }
     }
 }
@@ -263,16 +183,6 @@ __global__ void fill_int_kernel(int *__restrict__ x, int count, int value)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count)
         x[i] = value;
-}
-
-// piv[r] = the current pivot (unless done)
-__global__ void chol_record_kernel(int r, const int *__restrict__ state, int *__restrict__ piv,
-                                   int *__restrict__ ispiv)
-{
-    if (threadIdx.x == 0 && !state[1]) {
-        piv[r] = state[0];
-        ispiv[state[0]] = 1;
-    }
 }
 
 // fit result: T[r][s] = L_s[P[r]] is lower triangular (pivot order); for each
@@ -326,6 +236,89 @@ __global__ __launch_bounds__(CT) void fit_v_kernel(const double *__restrict__ F,
     V[e] = r < R ? F[i * n + piv[r]] : 0.0;
 }
 
+// Entries of B from V and Y = V M (M symmetric): for the pivot p (state
+// given) the column col[i] = B(i, p) = sum_k c_k prod_l V^l[i] . Y^l_k[p], else
+// the diagonal d[i] = B(i, i) = sum_k c_k prod_l V^l[i] . Y^l_k[i].  One
+// thread per (i, k mod KP) (KP = R_N rounded up to a power of two, at most
+// 64): it forms the three dot products of its terms k, k + KP, ... and sums
+// c_k times their product; the KP lanes of an index i then add their sums by
+// a shuffle tree, and lane k = 0 (fixed order) writes the entry.
+__global__ __launch_bounds__(256) void tei_entries_kernel(
+    const double *__restrict__ c, const double *__restrict__ V0, const double *__restrict__ V1,
+    const double *__restrict__ V2, const double *__restrict__ Y, int R, int R_N, int N_pair,
+    int KP, const int *__restrict__ state, double *__restrict__ out)
+{
+    if (state && state[1])
+        return;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const int i = (int)(t / KP), k0 = (int)(t % KP);
+    const bool live = i < N_pair;
+    const int row = state ? state[0] : i;
+    const long plane = (long)R_N * N_pair * R;
+    double s = 0.0;
+    if (live)
+        for (int k = k0; k < R_N; k += KP) {
+            double prod = c[k];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double *v = (l == 0 ? V0 : l == 1 ? V1 : V2) + (long)i * R;
+                const double *y = Y + l * plane + ((long)k * N_pair + row) * R;
+                double dd = 0.0;
+                for (int a = 0; a < R; ++a)
+                    dd = fma(v[a], y[a], dd);
+                prod *= dd;
+            }
+            s += prod;
+        }
+    for (int o = KP / 2; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
+    if (live && k0 == 0)
+        out[i] = s;
+}
+
+// B += sum_{k < kc} c_k Z^0_k o Z^1_k o Z^2_k over the N x N entries (Z^l
+// [kc][N][N], the terms of one chunk; first: B = that sum), in term order
+__global__ __launch_bounds__(256) void tei_b_accum_kernel(const double *__restrict__ c,
+                                                          const double *__restrict__ Z, long NN,
+                                                          int kc, int first,
+                                                          double *__restrict__ B)
+{
+    const long plane = (long)kc * NN;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < NN; e += (long)gridDim.x * 256) {
+        double v = first ? 0.0 : B[e];
+        for (int k = 0; k < kc; ++k) {
+            const long o = (long)k * NN + e;
+            v += c[k] * (Z[o] * Z[plane + o] * Z[2 * plane + o]);
+        }
+        B[e] = v;
+    }
+}
+
+// d[i] = A[i][i]
+__global__ __launch_bounds__(256) void diag_copy_kernel(const double *__restrict__ A, int N,
+                                                        double *__restrict__ d)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N)
+        d[i] = A[(long)i * N + i];
+}
+
+// T [cols][rows] = X^T for X [rows][cols] (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void transpose_kernel(const double *__restrict__ X, int rows,
+                                                        int cols, double *__restrict__ T)
+{
+    __shared__ double tile[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
+    for (int y = ty; y < 32; y += 8)
+        if (r0 + y < rows && c0 + tx < cols)
+            tile[y][tx] = X[(long)(r0 + y) * cols + c0 + tx];
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8)
+        if (c0 + y < cols && r0 + tx < rows)
+            T[(long)(c0 + y) * rows + r0 + tx] = tile[tx][y];
+}
+
 }  // namespace
 
 hipError_t launch_fit_diag(const double *F, int n, int N_pair, double *d, hipStream_t st)
@@ -358,45 +351,90 @@ hipError_t launch_tei_diag(const double *c, const double *const *V, const double
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(tei_diag_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, V[0],
-                       V[1], V[2], Y, R, R_N, N_pair, d);
-    return hipGetLastError();
+    return launch_tei_entries(c, V, Y, R, R_N, N_pair, nullptr, d, st);
 }
 
-hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
-                             int R, int R_N, int N_pair, const int *state, double *y, double *Z,
-                             double *col, hipStream_t st)
-{
-    hipLaunchKernelGGL(tei_y_kernel, dim3(3 * R_N, (R + kYRows - 1) / kYRows),
-                       dim3(kYRows * kYGroups), 0, st, V[0], V[1], V[2], M[0],
-                       M[1], M[2], R, R_N, state, y);
-    const long plane = (long)N_pair * R_N;
-    for (int l = 0; l < 3; ++l) {
-        // Z^l[i][k] = sum_a V^l[i][a] y^l[k][a]
-        const hipError_t e = launch_cross_gram_f64(V[l], y + (long)l * R_N * R, Z + l * plane, R,
-                                                   N_pair, R_N, 1, st);
-        if (e != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(tei_column_kernel, dim3((N_pair + CT - 1) / CT), dim3(CT), 0, st, c, Z,
-                       R_N, N_pair, state, col);
-    return hipGetLastError();
-}
-
-hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *ispiv,
-                            const int *state, double *d, hipStream_t st)
+hipError_t launch_chol_step(const double *col, const double *A, double *L, int N, int r,
+                            const int *ispiv, const int *state, double *d, hipStream_t st)
 {
     hipLaunchKernelGGL(chol_step_kernel, dim3((N + kStepA - 1) / kStepA), dim3(kStepA * kStepG),
-                       0, st, col, L, N, r, ispiv, state, d);
+                       0, st, col, A, L, N, r, ispiv, state, d);
     return hipGetLastError();
 }
 
 hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
-                              int *state, double *stats, hipStream_t st)
+                              int *state, double *stats, int *piv, int *ispiv, hipStream_t st)
 {
     hipLaunchKernelGGL(chol_select_kernel, dim3(1), dim3(1024), 0, st, d, N, clear, steps, thr,
-                       R_max, state, stats);
+                       R_max, state, stats, piv, ispiv);
     return hipGetLastError();
+}
+
+hipError_t launch_tei_entries(const double *c, const double *const *V, const double *Y, int R,
+                              int R_N, int N_pair, const int *state, double *out, hipStream_t st)
+{
+    int KP = 1;
+    while (KP < R_N && KP < 64)
+        KP *= 2;
+    const long threads = (long)N_pair * KP;
+    hipLaunchKernelGGL(tei_entries_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                       st, c, V[0], V[1], V[2], Y, R, R_N, N_pair, KP, state, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_copy(const double *A, int N, double *d, hipStream_t st)
+{
+    hipLaunchKernelGGL(diag_copy_kernel, dim3((N + 255) / 256), dim3(256), 0, st, A, N, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double *X, int rows, int cols, double *T, hipStream_t st)
+{
+    hipLaunchKernelGGL(transpose_kernel, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0,
+                       st, X, rows, cols, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_tei_form_b(const double *c, const double *const *V, const double *Y, int R,
+                             int R_N, int N_pair, int kc, double *Z, double *B, double *d,
+                             hipStream_t st)
+{
+    const long NN = (long)N_pair * N_pair;
+    const long plane = (long)R_N * N_pair * R;  // of Y
+    for (int k0 = 0; k0 < R_N; k0 += kc) {
+        const int kn = R_N - k0 < kc ? R_N - k0 : kc;
+        for (int l = 0; l < 3; ++l) {
+            // Z^l[k][i][j] = sum_a V^l[i][a] Y^l[k0 + k][j][a] = (V M V^T)[i][j]
+            const hipError_t e = launch_cross_gram_f64(V[l], Y + l * plane + (long)k0 * N_pair * R,
+                                                       Z + (long)l * kn * NN, R, N_pair, N_pair,
+                                                       kn, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        long blocks = (NN + 255) / 256;
+        if (blocks > 4096)
+            blocks = 4096;
+        hipLaunchKernelGGL(tei_b_accum_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c + k0, Z,
+                           NN, kn, k0 == 0 ? 1 : 0, B);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(diag_copy_kernel, dim3((N_pair + 255) / 256), dim3(256), 0, st, B, N_pair,
+                       d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_gram(const double *F, int n, int N_pair, double *Ft, double *A,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(transpose_kernel, dim3((n + 31) / 32, (N_pair + 31) / 32), dim3(256), 0,
+                       st, F, N_pair, n, Ft);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    // A[a][b] = sum_i Ft[a][i] Ft[b][i]
+    return launch_cross_gram_f64(Ft, Ft, A, N_pair, n, n, 1, st);
 }
 
 hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st)
@@ -406,11 +444,6 @@ hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_chol_record(int r, const int *state, int *piv, int *ispiv, hipStream_t st)
-{
-    hipLaunchKernelGGL(chol_record_kernel, dim3(1), dim3(64), 0, st, r, state, piv, ispiv);
-    return hipGetLastError();
-}
 
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,
                              int R_max, const int *piv, double *Tg, double *U, double *V,

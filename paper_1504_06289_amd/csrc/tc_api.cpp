@@ -1102,9 +1102,11 @@ CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
 constexpr int kCholGroup = 16;
 
 template <class Column>
+// A: the formed matrix [N][N] (its pivot rows are the columns), or null and
+// `column` computes each pivot's column into s.col.
 tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &s, double *L,
-                           Column column, int *pivots_host, int *R_out, double *residual_out,
-                           hipStream_t st)
+                           Column column, const double *A, int *pivots_host, int *R_out,
+                           double *residual_out, hipStream_t st)
 {
     double stats[2];
     int state[3];
@@ -1117,7 +1119,8 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
     };
     TRYK("chol_init", launch_fill_int(s.state, 3, 0, st));
     TRYK("chol_init", launch_fill_int(s.ispiv, N, 0, st));
-    TRYK("chol_select", launch_chol_select(s.d, N, 0, 0, -1.0, R_max, s.state, s.stats, st));
+    TRYK("chol_select",
+         launch_chol_select(s.d, N, 0, 0, -1.0, R_max, s.state, s.stats, s.piv, s.ispiv, st));
     if (!fetch())
         return TC_ERR_HIP;
     const double thr = thr_rel * stats[1];
@@ -1128,13 +1131,14 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
     int r = 0;
     while (!state[1]) {
         for (int g = 0; g < kCholGroup && r < R_max; ++g, ++r) {
-            TRYK("chol_record", launch_chol_record(r, s.state, s.piv, s.ispiv, st));
-            const tc_status cs = column(st);
-            if (cs != TC_OK)
-                return cs;
-            TRYK("chol_step", launch_chol_step(s.col, L, N, r, s.ispiv, s.state, s.d, st));
+            if (!A) {
+                const tc_status cs = column(st);
+                if (cs != TC_OK)
+                    return cs;
+            }
+            TRYK("chol_step", launch_chol_step(s.col, A, L, N, r, s.ispiv, s.state, s.d, st));
             TRYK("chol_select", launch_chol_select(s.d, N, 1, r + 1, thr, R_max, s.state,
-                                                   s.stats, st));
+                                                   s.stats, s.piv, s.ispiv, st));
         }
         if (!fetch())
             return TC_ERR_HIP;
@@ -1151,18 +1155,40 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
     return TC_OK;
 }
 
-size_t fit_ws(int n, int R_max)
+// The fit forms A = F^T F (n x n) when it is at most 512 MiB (n <= 8192):
+// each step then reads the pivot's row instead of a pass over F.
+constexpr int kFitFormedMaxN = 8192;
+
+size_t fit_ws(int n, int N_pair, int R_max)
 {
     Carver c(nullptr);
     carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n, (size_t)R_max * R_max);
+    if (n <= kFitFormedMaxN) {
+        c.take<double>((size_t)n * N_pair);
+        c.take<double>((size_t)n * n);
+    }
     return c.used;
+}
+
+// B is formed (each step then reads the pivot's row) when it is at most
+// 128 MiB (N_pair <= 4096); its terms go through Z in chunks of about 256 MiB
+constexpr int kTeiFormedMaxN = 4096;
+int tei_form_chunk(int N_pair, int R_N)
+{
+    const size_t per = (size_t)3 * N_pair * N_pair * sizeof(double);
+    size_t kc = ((size_t)256 << 20) / per;
+    kc = kc < 1 ? 1 : kc;
+    return (int)(kc < (size_t)R_N ? kc : (size_t)R_N);
 }
 
 size_t tei_chol_ws(int N_pair, int R, int R_N, int R_max)
 {
     Carver c(nullptr);
-    carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * (R + N_pair),
-               (size_t)3 * R_N * N_pair * R);
+    carve_chol(c, N_pair, R_max, false, 0, (size_t)3 * R_N * N_pair * R);
+    if (N_pair <= kTeiFormedMaxN) {
+        c.take<double>((size_t)N_pair * N_pair);
+        c.take<double>((size_t)3 * tei_form_chunk(N_pair, R_N) * N_pair * N_pair);
+    }
     return c.used;
 }
 
@@ -1386,7 +1412,7 @@ size_t tc_density_fit_workspace_bytes(int n, int N_pair, int R_max)
 {
     if (n < 1 || n > TC_MAX_N || N_pair < 1 || N_pair > TC_MAX_RF || R_max < 1 || R_max > n)
         return (size_t)-1;
-    return fit_ws(n, R_max);
+    return fit_ws(n, N_pair, R_max);
 }
 
 tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int R_max,
@@ -1396,19 +1422,28 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
     if (n < 1 || n > TC_MAX_N || N_pair < 1 || N_pair > TC_MAX_RF || R_max < 1 || R_max > n ||
         !F_dev || !U_dev || !V_dev || !R_out || !(tol >= 0.0) || !std::isfinite(tol))
         return TC_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < fit_ws(n, R_max))
+    if (!ws || ws_bytes < fit_ws(n, N_pair, R_max))
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
     const CholScratch s =
         carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n, (size_t)R_max * R_max);
-    TRYK("fit_diag", launch_fit_diag(F_dev, n, N_pair, s.d, st));
-    auto column = [&](hipStream_t cst) -> tc_status {
-        if (launch_fit_column(F_dev, n, N_pair, s.state, s.y, s.col, cst) != hipSuccess)
-            return TC_ERR_HIP;
+    double *A = nullptr;
+    if (n <= kFitFormedMaxN) {
+        double *Ft = c.take<double>((size_t)n * N_pair);
+        A = c.take<double>((size_t)n * n);
+        TRYK("fit_gram", launch_fit_gram(F_dev, n, N_pair, Ft, A, st));
+        // the formed matrix's diagonal, so that the steps and the pivot
+        // choices read one matrix
+        TRYK("fit_diag", launch_diag_copy(A, n, s.d, st));
+    } else {
+        TRYK("fit_diag", launch_fit_diag(F_dev, n, N_pair, s.d, st));
+    }
+    auto column = [&](hipStream_t st) -> tc_status {
+        TRYK("fit_column", launch_fit_column(F_dev, n, N_pair, s.state, s.y, s.col, st));
         return TC_OK;
     };
-    const tc_status r = pivoted_cholesky(n, R_max, tol * tol, s, s.L, column, pivots_host,
+    const tc_status r = pivoted_cholesky(n, R_max, tol * tol, s, s.L, column, A, pivots_host,
                                          R_out, residual_out, st);
     if (r != TC_OK)
         return r;
@@ -1441,16 +1476,26 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
         return TC_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
-    const CholScratch s = carve_chol(c, N_pair, R_max, false, (size_t)3 * R_N * (R + N_pair),
-                                     (size_t)3 * R_N * N_pair * R);
+    // s.Yd: Y = V M
+    const CholScratch s = carve_chol(c, N_pair, R_max, false, 0, (size_t)3 * R_N * N_pair * R);
     TRYK("tei_diag", launch_tei_diag(c_dev, V_dev, M_dev, R, R_N, N_pair, s.Yd, s.d, st));
-    auto column = [&](hipStream_t cst) -> tc_status {
-        if (launch_tei_column(c_dev, V_dev, M_dev, R, R_N, N_pair, s.state, s.y,
-                              s.y + (size_t)3 * R_N * R, s.col, cst) != hipSuccess)
-            return TC_ERR_HIP;
+    double *B = nullptr;
+    if (N_pair <= kTeiFormedMaxN) {
+        // B formed once (GEMMs of V with Y on matrix cores); its diagonal
+        // replaces d, so that the steps and the pivot choices read one matrix
+        B = c.take<double>((size_t)N_pair * N_pair);
+        const int kc = tei_form_chunk(N_pair, R_N);
+        double *Z = c.take<double>((size_t)3 * kc * N_pair * N_pair);
+        TRYK("tei_form_b",
+             launch_tei_form_b(c_dev, V_dev, s.Yd, R, R_N, N_pair, kc, Z, B, s.d, st));
+    }
+    // the pivot's column from V and the rows of Y = V M at the pivot (one
+    // launch; M symmetric, so M v_p is row p of Y)
+    auto column = [&](hipStream_t st) -> tc_status {
+        TRYK("tei_column", launch_tei_entries(c_dev, V_dev, s.Yd, R, R_N, N_pair, s.state, s.col, st));
         return TC_OK;
     };
-    return pivoted_cholesky(N_pair, R_max, tol, s, L_dev, column, pivots_host, R_out,
+    return pivoted_cholesky(N_pair, R_max, tol, s, L_dev, column, B, pivots_host, R_out,
                             residual_out, st);
 }
 

@@ -219,17 +219,33 @@ hipError_t launch_fit_column(const double *F, int n, int N_pair, const int *stat
 // Y: scratch [3][R_N][N_pair][R] (V^l M^l_k; M symmetric)
 hipError_t launch_tei_diag(const double *c, const double *const *V, const double *const *M,
                            int R, int R_N, int N_pair, double *Y, double *d, hipStream_t st);
-// y: scratch [3][R_N][R]; Z: scratch [3][N_pair][R_N]
-hipError_t launch_tei_column(const double *c, const double *const *V, const double *const *M,
-                             int R, int R_N, int N_pair, const int *state, double *y, double *Z,
-                             double *col, hipStream_t st);
-// ispiv [N]: 1 at the pivots recorded so far (launch_chol_record sets them)
-hipError_t launch_chol_step(const double *col, double *L, int N, int r, const int *ispiv,
-                            const int *state, double *d, hipStream_t st);
-// state = {pivot, done, steps}; see cholesky.hip
+// ispiv [N]: 1 at the pivots recorded so far (launch_chol_select sets them).
+// The pivot's column comes from col [N], or from the formed matrix A [N][N]
+// (A != null, symmetric: its row p).
+hipError_t launch_chol_step(const double *col, const double *A, double *L, int N, int r,
+                            const int *ispiv, const int *state, double *d, hipStream_t st);
+// state = {pivot, done, steps}; the next pivot is recorded in piv[steps] and
+// ispiv; see cholesky.hip
 hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
-                              int *state, double *stats, hipStream_t st);
-hipError_t launch_chol_record(int r, const int *state, int *piv, int *ispiv, hipStream_t st);
+                              int *state, double *stats, int *piv, int *ispiv, hipStream_t st);
+// entries of the factorised TEI matrix from V and Y = V M (Y as left by
+// launch_tei_diag): the column at the pivot (state given) or the diagonal
+hipError_t launch_tei_entries(const double *c, const double *const *V, const double *Y, int R,
+                              int R_N, int N_pair, const int *state, double *out,
+                              hipStream_t st);
+// d[i] = A[i][i], A [N][N]
+hipError_t launch_diag_copy(const double *A, int N, double *d, hipStream_t st);
+// T [cols][rows] = X^T, X [rows][cols]
+hipError_t launch_transpose(const double *X, int rows, int cols, double *T, hipStream_t st);
+// the factorised TEI matrix formed, B [N_pair][N_pair] = sum_k c_k o_l V^l M^l_k
+// V^l^T from Y = V M (as left by launch_tei_diag), in chunks of kc terms
+// through Z [3][kc][N_pair][N_pair]; d = its diagonal
+hipError_t launch_tei_form_b(const double *c, const double *const *V, const double *Y, int R,
+                             int R_N, int N_pair, int kc, double *Z, double *B, double *d,
+                             hipStream_t st);
+// A = F^T F [n][n] for F [N_pair][n]; Ft: scratch [n][N_pair]
+hipError_t launch_fit_gram(const double *F, int n, int N_pair, double *Ft, double *A,
+                           hipStream_t st);
 hipError_t launch_fill_int(int *x, int count, int value, hipStream_t st);
 // Tg: scratch [R_max][R_max]
 hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair, int R,

@@ -103,3 +103,74 @@ def test_tei_cholesky_pipeline(tc, orc):
     assert np.max(np.abs(L[:k].T - Lo[:, :k])) <= 1e-7 * scale
     # the residual trace is below the tolerance on both sides
     assert res <= 1e-10 * np.trace(Bo) * (1 + 1e-6)
+
+
+def margins_from_factor(diag, L, piv):
+    """Decision margins of the oracle's pivot steps from its own factor: the
+    residual diagonal before step r is diag - sum_{s<r} L_s^2."""
+    d = np.array(diag, dtype=np.float64)
+    out = []
+    for r, p in enumerate(piv):
+        dd = d.copy()
+        dd[piv[:r]] = -np.inf
+        top = np.sort(dd)[::-1][:2]
+        out.append((top[0] - top[1]) / max(top[0], 1e-300) if len(top) > 1 else 1.0)
+        d = d - L[:, r] ** 2
+    return np.array(out)
+
+
+@pytest.mark.slow
+def test_fit_and_tei_cholesky_at_bench_size(tc, orc):
+    """The benchmark's pipeline at full size (the 1024 products of the
+    4096-cell workload, R_N = 32): per mode the 1D density fit (formed Gram
+    A = F^T F on the device) against the oracle's fit, then the pivoted
+    Cholesky of B (the fused column kernel) against the oracle's Cholesky of
+    its own factorised B, with the tolerances of the small pipeline test."""
+    say("fit + TEI Cholesky at 4096 cells, 1024 products")
+    w = wl.config("c3")
+    c, ps = oracle_setup(orc, w)
+    tol_fit = 1e-7
+    Vo, Mo, fits = [], [], []
+    for l in range(3):
+        F = w.U[l]
+        Uo, Vol, po, reso = orc.density_fit(F, tol_fit, w.n[l])
+        fit = tc.density_fit(dev(F), tol_fit)
+        U, V, piv, R, res = fit
+        U, V = host(U), host(V)
+        A_diag = np.sum(F * F, axis=0)
+        # oracle factor of A for the margins: L = (F^T V) U-free form is not
+        # returned, so the margins come from the pivots' residual diagonals
+        k = min(len(po), R)
+        same = int(np.argmax(piv[:k] != po[:k])) if np.any(piv[:k] != po[:k]) else k
+        trA = float(A_diag.sum())
+        err2 = float(np.sum((F - V[:, :R] @ U[:R]) ** 2))
+        say(f"   mode {l}: R = {R} (oracle {len(po)}), first {same} pivots equal, "
+            f"|F - VU|^2 / tr A = {err2 / trA:.2e}")
+        assert err2 <= tol_fit ** 2 * trA * (1 + 1e-6) + 1e-28 * trA
+        assert abs(err2 - res) <= 1e-9 * trA
+        np.testing.assert_array_equal(V[:, :R], F[:, piv])
+        assert same >= min(10, k)  # the leading, well separated pivots
+        Vo.append(Vol)
+        Mo.append(orc.gram(Uo, orc.convolve(ps[l], Uo)))
+        fits.append(fit)
+    # oracle B and its pivoted Cholesky
+    Bo = orc.tei_matrix_factored(c, Vo, Mo)
+    tol_b = 1e-10
+    Lo, po, do = orc.pivoted_cholesky(Bo, tol_b * np.trace(Bo), Bo.shape[0])
+    # GPU: the fitted rows' Grams from the TEI assembly, then the Cholesky
+    R = max(f[3] for f in fits)
+    Ud = [f[0][:R].contiguous() for f in fits]
+    Vd = [f[1][:, :R].contiguous() for f in fits]
+    J, G = tc.tei_gram(dev(c), [dev(p) for p in ps], Ud, prec="fp64", save_G=True)
+    L, piv, res = tc.tei_cholesky(dev(c), Vd, [G[l].contiguous() for l in range(3)], tol_b)
+    L = host(L)
+    say(f"   R_B = {L.shape[0]} (oracle {len(po)})")
+    nrm = np.linalg.norm(Bo)
+    LL = L.T @ L
+    assert np.linalg.norm(LL - Lo @ Lo.T) <= 1e-7 * nrm
+    k = agreed_prefix(margins_from_factor(np.diag(Bo), Lo, po))
+    say(f"   pivots agree on {k} decisive steps")
+    np.testing.assert_array_equal(piv[:k], po[:k])
+    scale = np.sqrt(np.max(np.diag(Bo)))
+    assert np.max(np.abs(L[:k].T - Lo[:, :k])) <= 1e-7 * scale
+    assert res <= tol_b * np.trace(Bo) * (1 + 1e-6) + 1e-7 * nrm
