@@ -235,8 +235,6 @@ hipError_t launch_tei_entries(const double *c, const double *const *V, const dou
                               hipStream_t st);
 // d[i] = A[i][i], A [N][N]
 hipError_t launch_diag_copy(const double *A, int N, double *d, hipStream_t st);
-// T [cols][rows] = X^T, X [rows][cols]
-hipError_t launch_transpose(const double *X, int rows, int cols, double *T, hipStream_t st);
 // the factorised TEI matrix formed, B [N_pair][N_pair] = sum_k c_k o_l V^l M^l_k
 // V^l^T from Y = V M (as left by launch_tei_diag), in chunks of kc terms
 // through Z [3][kc][N_pair][N_pair]; d = its diagonal
@@ -269,7 +267,7 @@ hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C,
 // of kOrthBlock rows; scratch D [kOrthBlock][k], nrm [kOrthBlock],
 // Linv [kOrthBlock]^2, flag [1]; part as for launch_gemm_f64 (products
 // bk x b0 over n, bk x n over b0 and bk x bk over n)
-constexpr int kOrthBlock = 16;
+constexpr int kOrthBlock = 32;
 hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, double *Linv,
                             int *flag, double *part, unsigned long long salt, hipStream_t st);
 // rows i0..k-1 of X [k][n] pseudo-random in [-1, 1)
