@@ -388,6 +388,36 @@ hipError_t launch_diag_copy(const double *A, int N, double *d, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_tei_form_b(const double *c, const double *const *V, const double *Y, int R,
+                             int R_N, int N_pair, int kc, double *Z, double *B, double *d,
+                             hipStream_t st)
+{
+    const long NN = (long)N_pair * N_pair;
+    const long plane = (long)R_N * N_pair * R;  // of Y
+    for (int k0 = 0; k0 < R_N; k0 += kc) {
+        const int kn = R_N - k0 < kc ? R_N - k0 : kc;
+        for (int l = 0; l < 3; ++l) {
+            // Z^l[k][i][j] = sum_a V^l[i][a] Y^l[k0 + k][j][a] = (V M V^T)[i][j]
+            const hipError_t e = launch_cross_gram_f64(V[l], Y + l * plane + (long)k0 * N_pair * R,
+                                                       Z + (long)l * kn * NN, R, N_pair, N_pair,
+                                                       kn, st);
+            if (e != hipSuccess)
+                return e;
+        }
+        long blocks = (NN + 255) / 256;
+        if (blocks > 4096)
+            blocks = 4096;
+        hipLaunchKernelGGL(tei_b_accum_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c + k0, Z,
+                           NN, kn, k0 == 0 ? 1 : 0, B);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(diag_copy_kernel, dim3((N_pair + 255) / 256), dim3(256), 0, st, B, N_pair,
+                       d);
+    return hipGetLastError();
+}
+
 hipError_t launch_fit_gram(const double *F, int n, int N_pair, double *Ft, double *A,
                            hipStream_t st)
 {
