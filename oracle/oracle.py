@@ -292,6 +292,22 @@ def lattice_sum(p: np.ndarray, n0: int, L: int) -> np.ndarray:
     return A
 
 
+def lattice_sum_entries(p: np.ndarray, n0: int, L: int, samples):
+    """Entries A[q][i] of lattice_sum for the listed (q, i) pairs, each an
+    exactly rounded sum (math.fsum) over the L unit cells, with the sum of
+    the magnitudes of its terms (the scale of a rounding bound)."""
+    import math
+    p = np.asarray(p, dtype=np.float64)
+    n = n0 * L
+    assert p.shape[1] == 2 * n - 1
+    vals, scales = [], []
+    for q, i in samples:
+        terms = [p[q, i - (j * n0 + n0 // 2) + n - 1] for j in range(L)]
+        vals.append(math.fsum(terms))
+        scales.append(math.fsum(abs(x) for x in terms))
+    return np.array(vals), np.array(scales)
+
+
 def lattice_potential_direct(c, p3, h3, n0, L3, points) -> np.ndarray:
     """The separable kernel summed over the lattice, point by point: for grid
     points (i1, i2, i3), V = sum_j sum_q (c_q / (h1 h2 h3)^2) prod_l p^l_q[i_l - x_jl]
@@ -389,6 +405,35 @@ def nuclear(c, p3, h3, U3, Z, pos) -> np.ndarray:
                 prod = prod * ((U3[l] * s[None, :]) @ U3[l].T)
             V -= Z[alpha] * c[q] / vol * prod
     return V
+
+
+def nuclear_entries(c, p3, h3, U3, Z, pos, pairs):
+    """Entries V[k][m] of nuclear for the listed (k, m) pairs, each formed
+    from its own definition: for every nucleus and kernel term the product
+    over the modes of sum_a U^l[k][a] U^l[m][a] p^l_q[a - pos_alpha,l].
+    Also returns, per entry, the same sum over absolute values (the scale of
+    a rounding bound; zero when the two functions do not overlap)."""
+    c = _f64(c)
+    U3 = [_f64(u) for u in U3]
+    p3 = [_f64(p) for p in p3]
+    vol = float(h3[0] * h3[1] * h3[2])
+    vals, scales = [], []
+    for k, m in pairs:
+        v, sc = 0.0, 0.0
+        for alpha in range(len(Z)):
+            for q in range(c.shape[0]):
+                prod = Z[alpha] * c[q] / vol
+                aprod = abs(Z[alpha] * c[q]) / vol
+                for l in range(3):
+                    n = U3[l].shape[1]
+                    s = p3[l][q, np.arange(n) - int(pos[alpha][l]) + n - 1]
+                    prod *= float(np.dot(U3[l][k] * U3[l][m], s))
+                    aprod *= float(np.dot(np.abs(U3[l][k] * U3[l][m]), np.abs(s)))
+                v -= prod
+                sc += aprod
+        vals.append(v)
+        scales.append(sc)
+    return np.array(vals), np.array(scales)
 
 
 def nuclear_bruteforce(c, p3, h3, U3, Z, pos) -> np.ndarray:

@@ -176,7 +176,7 @@ def test_lattice_at_the_largest_grid(tc, orc):
 def test_lattice_sum_full_size_sampled(tc, orc):
     """The bench configuration of the lattice sum (n0 = 268, L = 128 per
     direction, n = 34304 cells, 190 terms; kernel vectors from the oracle):
-    sampled outputs against the sum over the lattice written out."""
+    sampled outputs against the oracle's exactly rounded lattice sums."""
     import math
     L, n0 = 128, 268
     h = 2.0 / n0
@@ -189,9 +189,8 @@ def test_lattice_sum_full_size_sampled(tc, orc):
     A = host(A3[1])
     n = n0 * L
     rng = np.random.default_rng(5)
-    for _ in range(64):
-        q, i = int(rng.integers(0, R_N)), int(rng.integers(0, n))
-        terms = ph[q, i - (np.arange(L) * n0 + n0 // 2) + n - 1]
-        ref = math.fsum(terms)
-        assert abs(A[q, i] - ref) <= (L + 1) * 2.0 ** -53 * np.sum(np.abs(terms))
+    samples = [(int(rng.integers(0, R_N)), int(rng.integers(0, n))) for _ in range(64)]
+    ref, sc = orc.lattice_sum_entries(ph, n0, L, samples)
+    for (q, i), r, s_ in zip(samples, ref, sc):
+        assert abs(A[q, i] - r) <= (L + 1) * 2.0 ** -53 * s_
     assert np.array_equal(host(A3[0]), A) and np.array_equal(host(A3[2]), A)

@@ -106,7 +106,7 @@ def test_nuclear_largest_pair_count(tc, orc):
 def test_nuclear_full_size_sampled(tc, orc):
     """The bench configuration (the 4096-cell products, 1024 functions, 32
     kernel terms, three nuclei in a water-like geometry): 24 sampled entries
-    against the definition evaluated entry by entry."""
+    against the oracle's entry-by-entry evaluation of the definition."""
     w = wl.config("c3")
     c, ps = oracle_setup(orc, w)
     geom = np.array([[0.0, 0.0, 0.0], [1.43, 1.11, 0.0], [-1.43, 1.11, 0.0]])
@@ -115,27 +115,18 @@ def test_nuclear_full_size_sampled(tc, orc):
     say(f"nuclear full size: n={w.n} R_f={w.R_f} R_N={w.R_N}")
     V = run(tc, c, ps, w.U, w.h, Z, pos)
     rng = np.random.default_rng(12)
-    vol = w.h[0] * w.h[1] * w.h[2]
-    worst_ratio, overlapping = 0.0, 0
-    for _ in range(24):
+    pairs = []
+    for s_ in range(24):
         i = int(rng.integers(0, w.R_f))
-        j = i if _ % 3 == 0 else int(rng.integers(0, w.R_f))
-        ref, sc = 0.0, 0.0
-        for a in range(len(Z)):
-            for q in range(w.R_N):
-                prod, aprod = Z[a] * c[q] / vol, abs(Z[a] * c[q]) / vol
-                for l in range(3):
-                    n = w.n[l]
-                    s = ps[l][q, np.arange(n) - pos[a][l] + n - 1]
-                    prod *= np.dot(w.U[l][i] * w.U[l][j], s)
-                    aprod *= np.dot(np.abs(w.U[l][i] * w.U[l][j]), np.abs(s))
-                ref -= prod
-                sc += aprod
-        if sc == 0.0:  # the two functions do not overlap in some mode
+        pairs.append((i, i if s_ % 3 == 0 else int(rng.integers(0, w.R_f))))
+    ref, sc = orc.nuclear_entries(c, ps, w.h, w.U, Z, pos, pairs)
+    worst_ratio, overlapping = 0.0, 0
+    for (i, j), r, s_ in zip(pairs, ref, sc):
+        if s_ == 0.0:  # the two functions do not overlap in some mode
             assert V[i, j] == 0.0
             continue
         overlapping += 1
-        worst_ratio = max(worst_ratio, abs(V[i, j] - ref) / sc)
+        worst_ratio = max(worst_ratio, abs(V[i, j] - r) / s_)
     say(f"   max |dV| / scale over {overlapping} overlapping samples = {worst_ratio:.2e}")
     assert overlapping >= 8
     assert worst_ratio <= 1e-12

@@ -422,6 +422,17 @@ def test_lattice_sum_is_the_separable_lattice_loop(orc):
     V = np.array([np.sum(w * A3[0][:, i] * A3[1][:, j] * A3[2][:, k]) for (i, j, k) in pts])
     Vd = orc.lattice_potential_direct(c, p3, hs, n0, L3, pts)
     assert np.max(np.abs(V - Vd) / np.abs(Vd)) <= 1e-13
+    # the entry-wise form (used to sample the full-size lattice sum) through
+    # the same identity: its entries rebuild the point potentials
+    Ve = []
+    for (i, j, k) in pts:
+        cols = []
+        for l, x in enumerate((i, j, k)):
+            v, sc = orc.lattice_sum_entries(p3[l], n0, L3[l], [(q, x) for q in range(R_N)])
+            assert np.all(np.abs(v) <= sc)
+            cols.append(v)
+        Ve.append(np.sum(w * cols[0] * cols[1] * cols[2]))
+    assert np.max(np.abs(np.array(Ve) - Vd) / np.abs(Vd)) <= 1e-13
 
 
 @pytest.mark.slow
@@ -734,6 +745,13 @@ def test_nuclear_matrix_is_the_grid_sum(orc):
     Vb = orc.nuclear_bruteforce(c, p3, h3, U3, Z, pos)
     assert np.max(np.abs(V - Vb)) <= 1e-12 * np.max(np.abs(Vb))
     assert np.max(np.abs(V - V.T)) <= 1e-14 * np.max(np.abs(V))
+    # the entry-wise form (used to sample the full-size matrix) against the
+    # same grid sum, with its scale bounding every entry
+    pairs = [(k, m) for k in range(5) for m in range(5)]
+    Ve, sc = orc.nuclear_entries(c, p3, h3, U3, Z, pos, pairs)
+    Vbe = np.array([Vb[k, m] for k, m in pairs])
+    assert np.max(np.abs(Ve - Vbe)) <= 1e-12 * np.max(np.abs(Vb))
+    assert np.all(np.abs(Ve) <= sc * (1 + 1e-12))
 
 
 def _nuclear_ss(a1, A1, a2, A2, C):
