@@ -124,8 +124,9 @@ def test_fit_and_tei_cholesky_at_bench_size(tc, orc):
     """The benchmark's pipeline at full size (the 1024 products of the
     4096-cell workload, R_N = 32): per mode the 1D density fit (formed Gram
     A = F^T F on the device) against the oracle's fit, then the pivoted
-    Cholesky of B (the fused column kernel) against the oracle's Cholesky of
-    its own factorised B, with the tolerances of the small pipeline test."""
+    Cholesky of B (B formed on the device from the fitted Grams) against the
+    oracle's Cholesky of its own factorised B, with the tolerances of the
+    small pipeline test."""
     say("fit + TEI Cholesky at 4096 cells, 1024 products")
     w = wl.config("c3")
     c, ps = oracle_setup(orc, w)
