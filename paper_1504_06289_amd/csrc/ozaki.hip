@@ -688,12 +688,14 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
 // The split tail items: part 0's tile in G plus the later parts' slots, in
 // part order; then the mirrored entries.  Workgroup (x, r): tail item r of
 // XCD x.
+// one workgroup per (XCD x, tail item r, block of kTailRows rows of the tile)
+constexpr int kTailRows = 8;
 __global__ __launch_bounds__(256) void gram_i8_tail_sum(double *__restrict__ G, int R_f, int R_N,
                                                         int ntri, const int *__restrict__ cls,
                                                         int mirror, int cux,
                                                         const double *__restrict__ slab)
 {
-    const int x = blockIdx.x, r = blockIdx.y;
+    const int x = blockIdx.x, r = blockIdx.y, a0 = blockIdx.z * kTailRows;
     const XcdList XL = xcd_list(x, cls, R_N, ntri, cux);
     if (XL.P < 2 || r >= XL.rem)
         return;
@@ -706,8 +708,9 @@ __global__ __launch_bounds__(256) void gram_i8_tail_sum(double *__restrict__ G, 
         ++tj;
     const int ti = t - tj * (tj + 1) / 2;
     double *Gk = G + (long)k * R_f * R_f;
-    for (int e = threadIdx.x; e < GT2 * GT2; e += 256) {
-        const int a = e / GT2, b = e % GT2;
+#pragma unroll
+    for (int e = threadIdx.x; e < kTailRows * GT2; e += 256) {
+        const int a = a0 + e / GT2, b = e % GT2;
         const int i = ti * GT2 + a, j = tj * GT2 + b;
         if (i >= R_f || j >= R_f || i > j)
             continue;
@@ -800,8 +803,8 @@ hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, con
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !tail)
             return e;
-        hipLaunchKernelGGL(gram_i8_tail_sum, dim3(8, cux), dim3(256), 0, stream, G, R_f, R_N,
-                           ntri, cls, (int)mirror, cux, tail);
+        hipLaunchKernelGGL(gram_i8_tail_sum, dim3(8, cux, GT2 / kTailRows), dim3(256), 0, stream,
+                           G, R_f, R_N, ntri, cls, (int)mirror, cux, tail);
         return hipGetLastError();
     }
     const int nt = L.R_f_pad / GT;
