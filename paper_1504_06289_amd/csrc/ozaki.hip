@@ -32,6 +32,7 @@ namespace tc {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // splitting
@@ -155,6 +156,16 @@ constexpr int AROW = 80;                  // LDS row stride (bytes): conflict-fr
 constexpr int WLEN = 256;                 // window bytes per slice (>= TA + TK - 1 + 16)
 constexpr int A_BYTES = 4 * TJ * AROW;    // 20480
 constexpr int W_BYTES = 4 * WLEN;         // 1024
+
+__device__ inline double combine16(const v16i *acc, int r, int E)
+{
+    // as combine, for the 16-register accumulators of the 32 x 32 products
+    double v = ldexp((double)acc[3][r], -21);
+    v += ldexp((double)acc[2][r], -14);
+    v += ldexp((double)acc[1][r], -7);
+    v += (double)acc[0][r];
+    return ldexp(v, E);
+}
 
 __device__ inline double combine(const v4i *acc, int r, int E)
 {
@@ -424,11 +435,13 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
         }
 }
 
-// Large-tile variant for R_f >= 256: 128 x 128 tiles, K-step 64, eight
-// waves (512 threads) in 4 x 2 of 32 x 64 (2 x 4 MFMA blocks, 128
-// accumulator registers), so two waves share each SIMD and one wave's LDS
-// reads and barrier waits overlap the other's matrix-core work.  The
-// per-workgroup operand traffic per multiply-add halves compared with the
+// Large-tile variant for R_f >= 256: 128 x 128 tiles, K-step 64, sixteen
+// waves (1024 threads) in 4 x 4 of 32 x 32 blocks on v_mfma_i32_32x32x32_i8
+// (four 16-register accumulators, one per scale group; 124 VGPRs), so four
+// waves share each SIMD and hide each other's LDS and barrier waits.  The
+// 32 x 32 x 32 form sustains 1.7 times the int8 rate of the 16 x 16 x 64
+// form on gfx950 (which occupies the matrix pipe 32 cycles per product).
+// The per-workgroup operand traffic per multiply-add halves compared with the
 // 64 x 64 tiles.
 //
 // Work items are (k, tile) with k grouped by XCD (work item w runs on XCD
@@ -438,8 +451,8 @@ __global__ __launch_bounds__(256) void gram_i8_kernel(
 //
 // LDS rows are unpadded (64 B) with the 16-byte chunks of row r permuted by
 // c ^ swz(r): then the staging writes (four lanes per row) and the fragment
-// reads (sixteen consecutive rows, one chunk) hit distinct banks both for 8-
-// and for 16-lane service groups.
+// reads (consecutive rows, one chunk) hit distinct banks in every group of
+// sixteen lanes.
 constexpr int GT2 = 128;
 constexpr int kTailSlots = kOzakiTailSlots;  // slots per XCD for later K parts of tail items
 constexpr int GW_ROW = 64;
@@ -516,7 +529,8 @@ __device__ inline double *tail_slot(double *slab, int x, int r, int p, int P)
     return slab + ((long)x * kTailSlots + r * (P - 1) + (p - 1)) * GT2 * GT2;
 }
 
-__global__ __launch_bounds__(512) void gram_i8_wide_kernel(
+constexpr int kWideThreads = 1024;
+__global__ __launch_bounds__(kWideThreads) void gram_i8_wide_kernel(
     const int8_t *__restrict__ US, const int *__restrict__ EU, long uplane,
     const int8_t *__restrict__ WS, const int *__restrict__ EW, long wplane, int n_pad,
     int R_f_pad, double *__restrict__ G, int R_f, int R_N, int ntri,
@@ -554,16 +568,17 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     const int i0 = ti * GT2, j0 = tj * GT2;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 64;
-    const int l16 = lane & 15, g = lane >> 4;
+    // sixteen waves in 4 x 4 of 32 x 32 blocks, four per SIMD
+    const int wi = (wave >> 2) * 32, wj = (wave & 3) * 32;
+    const int l32 = lane & 31, h = lane >> 5;
     const int8_t *Wk = WS + (long)k * R_f_pad * n_pad;
 
-    // staging: per operand 2048 chunks of 16 B, 4 per thread
-    v4i areg[4], breg[4];
+    // staging: per operand 2048 chunks of 16 B, 2 per thread
+    v4i areg[2], breg[2];
     auto load_stage = [&](int a0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = tid + 512 * q;  // slice = c/512, row = (c%512)/4, col16 = c%4
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + kWideThreads * q;  // slice = c/512, row = (c%512)/4, col16 = c%4
             const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
             areg[q] = *reinterpret_cast<const v4i *>(US + sl * uplane + (long)(i0 + row) * n_pad +
                                                      a0 + 16 * c16);
@@ -573,8 +588,8 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = tid + 512 * q;
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + kWideThreads * q;
             const int sl = c >> 9, row = (c & 511) >> 2, c16 = c & 3;
             const int o = gw_offset(sl, row, c16);
             *reinterpret_cast<v4i *>(As[buf] + o) = areg[q];
@@ -582,23 +597,37 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
         }
     };
 
-    v4i acc[2][4][4];
+    // one accumulator per scale group d = s + t of the slice products
+    v16i acc[4];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int d = 0; d < 4; ++d)
-                acc[x][y][d] = v4i{0, 0, 0, 0};
+    for (int d = 0; d < 4; ++d)
+        acc[d] = v16i{};
 
-    // Stage s+1 is written to LDS at the start of step s (from registers
-    // loaded during step s-1), and stage s+2 is then loaded into those
-    // registers, so the LDS writes overlap this step's matrix-core work
-    // instead of preceding the barrier.
     // this item's K steps [s0, s0 + nsteps)
     const int ktot = n_pad / TK;
     const int s0 = (int)((long)part * ktot / parts);
     const int nsteps = (int)((long)(part + 1) * ktot / parts) - s0;
+
+    // Each 64-byte K step is two 32-byte halves kc; lane l reads row l mod 32
+    // of its block, bytes 16 (l / 32) .. + 16 of the half (chunk 2 kc + l / 32)
+    auto read_a = [&](int buf, int kc, v4i (&A)[4]) {
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl)
+            A[sl] = *reinterpret_cast<const v4i *>(As[buf] + gw_offset(sl, wi + l32, 2 * kc + h));
+    };
+    auto read_b = [&](int buf, int kc, int sl) {
+        return *reinterpret_cast<const v4i *>(Bs[buf] + gw_offset(sl, wj + l32, 2 * kc + h));
+    };
+    // products of B slice j against A slices i <= 3 - j
+    auto products = [&](int j, const v4i (&A)[4], v4i B) {
+#pragma unroll
+        for (int i = 0; i + j <= 3; ++i)
+            acc[i + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B, acc[i + j], 0, 0, 0);
+    };
+
+    // Stage s+1 is written to LDS at the start of step s (from registers
+    // loaded during step s-1), and stage s+2 is then loaded into those
+    // registers, so the LDS writes overlap this step's matrix-core work.
     load_stage(s0 * TK);
     store_stage(0);
     if (nsteps > 1)
@@ -606,83 +635,53 @@ __global__ __launch_bounds__(512) void gram_i8_wide_kernel(
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1;
-        // this step's A fragments and first B fragments are read before the
-        // next stage is written, so these reads lead the writes in the LDS
-        // queue and the first products need not wait behind them
-        v4i afr[2][4], bfr0[4];
-#pragma unroll
-        for (int sl = 0; sl < 4; ++sl)
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-                afr[x][sl] = *reinterpret_cast<const v4i *>(As[cur] +
-                                                            gw_offset(sl, wi + 16 * x + l16, g));
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-            bfr0[y] = *reinterpret_cast<const v4i *>(Bs[cur] + gw_offset(0, wj + 16 * y + l16, g));
+        v4i a[4];
+        read_a(cur, 0, a);
+        v4i b0 = read_b(cur, 0, 0);
         // the other buffer was last read in step s-1, before the barrier that ended it
         if (s + 1 < nsteps)
             store_stage(cur ^ 1);
         if (s + 2 < nsteps)
             load_stage((s0 + s + 2) * TK);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v4i bfr[4];
+        for (int kc = 0; kc < 2; ++kc) {
+            if (kc == 1) {
+                read_a(cur, 1, a);
+                b0 = read_b(cur, 1, 0);
+            }
 #pragma unroll
-            for (int y = 0; y < 4; ++y)
-                bfr[y] = j == 0 ? bfr0[y]
-                                : *reinterpret_cast<const v4i *>(Bs[cur] +
-                                                                 gw_offset(j, wj + 16 * y + l16, g));
-#pragma unroll
-            for (int i = 0; i + j <= 3; ++i)
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        acc[x][y][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                            afr[x][i], bfr[y], acc[x][y][i + j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j)
+                products(j, a, j == 0 ? b0 : read_b(cur, kc, j));
         }
         __syncthreads();
     }
 
+    // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r mod 4 and
+    // column l mod 32 of the wave's block
     const int *EWk = EW + (long)k * R_f_pad;
     if (part > 0) {
         // a later K part of a split tail item: the partial tile to its slot
         double *sl = tail_slot(slab, xcd, tail, part, parts);
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = wi + 16 * x + 4 * g + r;
-                const int i = i0 + a;
-#pragma unroll
-                for (int y = 0; y < 4; ++y) {
-                    const int b = wj + 16 * y + l16;
-                    const int j = j0 + b;
-                    if (i < R_f && j < R_f && i <= j)
-                        sl[a * GT2 + b] = combine(acc[x][y], r, EU[i] + EWk[j]);
-                }
-            }
+        for (int r = 0; r < 16; ++r) {
+            const int a = wi + 8 * (r >> 2) + 4 * h + (r & 3), b = wj + l32;
+            const int i = i0 + a, j = j0 + b;
+            if (i < R_f && j < R_f && i <= j)
+                sl[a * GT2 + b] = combine16(acc, r, EU[i] + EWk[j]);
+        }
         return;
     }
     double *Gk = G + (long)k * R_f * R_f;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = i0 + wi + 16 * x + 4 * g + r;
-            if (i >= R_f)
-                continue;
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                const int j = j0 + wj + 16 * y + l16;
-                if (j < R_f && i <= j) {
-                    const double v = combine(acc[x][y], r, EU[i] + EWk[j]);
-                    Gk[(long)i * R_f + j] = v;
-                    if (mirror && parts == 1)
-                        Gk[(long)j * R_f + i] = v;
-                }
-            }
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + wi + 8 * (r >> 2) + 4 * h + (r & 3), j = j0 + wj + l32;
+        if (i < R_f && j < R_f && i <= j) {
+            const double v = combine16(acc, r, EU[i] + EWk[j]);
+            Gk[(long)i * R_f + j] = v;
+            if (mirror && parts == 1)
+                Gk[(long)j * R_f + i] = v;
         }
+    }
 }
 
 // The split tail items: part 0's tile in G plus the later parts' slots, in
@@ -797,7 +796,7 @@ hipError_t launch_gram_i8(const int8_t *US, const int *EU, const int8_t *WS, con
         const int per = cls ? (R_N * ntri + 7) / 8 : ((R_N + 7) / 8) * ntri;
         const int cux = cus_per_xcd();
         const int items = 8 * (per + (tail ? kTailSlots : 0));
-        hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(512), 0, stream, US, EU,
+        hipLaunchKernelGGL(gram_i8_wide_kernel, dim3(items), dim3(kWideThreads), 0, stream, US, EU,
                            L.uplane, WS, EW, L.wplane, L.n_pad, L.R_f_pad, G, R_f, R_N, ntri,
                            cls, (int)mirror, cux, tail);
         hipError_t e = hipGetLastError();
