@@ -491,6 +491,11 @@ hipError_t launch_poly_rows(int n, double *Q, hipStream_t stream)
 hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q, double *part,
                                double *X, hipStream_t stream)
 {
+    // on the binary64 matrix cores (X = U Q^T, contraction split into fixed
+    // slices summed in order) where its slices fit part: the vector form below
+    // is bound by LDS instruction issue (five 8-byte reads per four FMAs)
+    if (gemm_splits(R_f, RQ, n) <= PKS)
+        return launch_gemm_f64(false, U, Q, X, R_f, RQ, n, part, stream);
     hipLaunchKernelGGL(poly_project_kernel, dim3((R_f + PRT - 1) / PRT, PKS), dim3(256), 0,
                        stream, U, n, R_f, Q, part);
     hipError_t e = hipGetLastError();
