@@ -1553,14 +1553,7 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         need(r[l], n[l], k);
         need(r[l], R, n[l]);
         need(q, n[l], R);
-        for (int b0 = 0; b0 < k; b0 += kOrthBlock) {
-            const int bk = std::min(kOrthBlock, k - b0);
-            need(bk, bk, n[l]);
-            if (b0 > 0) {
-                need(bk, b0, n[l]);
-                need(bk, n[l], b0);
-            }
-        }
+        need(k, k, n[l]);
     }
     need(r[0], (long)r[1] * r[2], R);
     T.part = c.take<double>(part);
@@ -1571,9 +1564,9 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         T.Ut[l] = c.take<double>((size_t)r[l] * R);
     T.K = c.take<double>((size_t)rr * R);
     T.Mt = c.take<double>((size_t)rr * nmax);
-    T.D = c.take<double>((size_t)kOrthBlock * kTuckerMaxSub);
-    T.nrm = c.take<double>(kOrthBlock);
-    T.Linv = c.take<double>((size_t)kOrthBlock * kOrthBlock);
+    T.D = c.take<double>((size_t)kOrthRows * kOrthRows);
+    T.nrm = c.take<double>(kOrthRows);
+    T.Linv = c.take<double>((size_t)kOrthRows * kOrthRows);
     T.flag = c.take<int>(1);
     T.lamA = c.take<double>(3 * (size_t)kTuckerMaxSub);
     T.bytes = c.used;
@@ -1582,7 +1575,15 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
 
 // The r dominant left singular vectors of B^T (B [m][n] rows) as the rows of
 // Z [r][n]: orthogonal iteration, then Rayleigh-Ritz.  warm: the first r rows
-// of the start are Z itself.
+// of the start are Z itself.  Only the last step's rows enter the
+// Rayleigh-Ritz step, so the steps before it take one Cholesky-QR pass (rows
+// orthonormal to about (condition number)^2 u, enough to keep the next
+// product well conditioned) and the last takes two.  The first step, where
+// the start (random rows, or a basis of another matrix) is furthest from the
+// dominant subspace, orthonormalises between X B^T and its product with B:
+// each half then raises the condition number of the rows once, not twice (the
+// same subspace in exact arithmetic).  That needs m >= k; with fewer rows in
+// B the product has rank below k anyway and the fallback refills it.
 static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int n, int r,
                                int its, bool warm, double *Z, double *sv,
                                unsigned long long salt, hipStream_t st)
@@ -1591,13 +1592,17 @@ static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int 
     if (warm && hipMemcpyAsync(T.X, Z, sizeof(double) * (size_t)r * n, hipMemcpyDeviceToDevice,
                                st) != hipSuccess)
         return TC_ERR_HIP;
+    auto orth = [&](double *X, int len, int passes, unsigned long long s) {
+        return launch_orth_rows(X, k, len, passes, T.D, T.nrm, T.Linv, T.flag, T.part, s, st);
+    };
     TRYK("random_rows", launch_random_rows(T.X, warm ? r : 0, k, n, salt, st));
-    TRYK("orth_rows", launch_orth_rows(T.X, k, n, T.D, T.nrm, T.Linv, T.flag, T.part, salt + 1, st));
+    TRYK("orth_rows", orth(T.X, n, 1, salt + 1));
     for (int it = 0; it < its; ++it) {
         TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));  // X B^T
+        if (it == 0 && m >= k)
+            TRYK("orth_rows", orth(T.P, m, 1, salt + 1 + its + 1));
         TRYK("gemm_f64", launch_gemm_f64(true, T.P, B, T.X, k, n, m, T.part, st));   // (X B^T) B
-        TRYK("orth_rows", launch_orth_rows(T.X, k, n, T.D, T.nrm, T.Linv, T.flag, T.part,
-                                           salt + 2 + it, st));
+        TRYK("orth_rows", orth(T.X, n, it == its - 1 ? 2 : 1, salt + 2 + it));
     }
     TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));
     TRYK("gemm_f64", launch_gemm_f64(false, T.P, T.P, T.H, k, k, m, T.part, st));

@@ -263,13 +263,16 @@ int gemm_splits(int I, int N, int K);
 // sub: C -= the product instead of C = it.
 hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C, int I, int N,
                            int K, double *part, hipStream_t st, bool sub = false);
-// orthonormal rows of X [k][n] (k <= kTuckerMaxSub <= n), in place, in blocks
-// of kOrthBlock rows; scratch D [kOrthBlock][k], nrm [kOrthBlock],
-// Linv [kOrthBlock]^2, flag [1]; part as for launch_gemm_f64 (products
-// bk x b0 over n, bk x n over b0 and bk x bk over n)
-constexpr int kOrthBlock = 32;
-hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, double *Linv,
-                            int *flag, double *part, unsigned long long salt, hipStream_t st);
+// rows of X [k][n] (1 <= k <= kOrthRows, k <= n) brought to an orthonormal
+// basis of their span, in place, by `passes` (1 or 2) Cholesky-QR passes, with
+// the Gram-Schmidt fallback on the device where a pass flags; one pass leaves
+// rows orthonormal to about (condition number)^2 u, two to working precision.
+// Scratch D [k][k], nrm [k], Linv [k][k], flag [1]; part as for
+// launch_gemm_f64 (the product k x k over n).
+constexpr int kOrthRows = kTuckerMaxSub;
+hipError_t launch_orth_rows(double *X, int k, int n, int passes, double *D, double *nrm,
+                            double *Linv, int *flag, double *part, unsigned long long salt,
+                            hipStream_t st);
 // rows i0..k-1 of X [k][n] pseudo-random in [-1, 1)
 hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
                               hipStream_t st);

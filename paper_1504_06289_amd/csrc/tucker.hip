@@ -13,14 +13,13 @@
 //                 column), 64 x 64 tiles on binary64 matrix cores, the
 //                 contraction split over blockIdx.z into fixed slices whose
 //                 partial tiles are summed in order (bitwise reproducible);
-//   orth_rows     block Gram-Schmidt: each block of 16 rows is projected
-//                 against the earlier rows twice by matrix-core products, then
-//                 orthonormalised within the block by two Cholesky-QR passes
-//                 (block Gram, 16 x 16 Cholesky, column-parallel forward
-//                 substitution); where a row keeps less than 1e-4 of its norm the
-//                 block falls back, on the device, to classical Gram-Schmidt
-//                 applied twice in one workgroup, and a row that keeps less
-//                 than 1e-10 is replaced by pseudo-random values and
+//   orth_rows     Cholesky-QR of the k <= 64 rows: their Gram on matrix
+//                 cores, a 64 x 64 Cholesky in one workgroup (one barrier per
+//                 column) and a column-parallel forward substitution, once or
+//                 twice (CholeskyQR2); where a row keeps less than about 3e-6
+//                 of its norm the rows fall back, on the device, to classical
+//                 Gram-Schmidt applied twice in one workgroup, and a row that
+//                 keeps less than 1e-10 is replaced by pseudo-random values and
 //                 orthogonalised against every earlier row;
 //   jacobi_eig    cyclic Jacobi on a symmetric k x k matrix (k <= 64) held in
 //                 LDS, the k/2 disjoint rotations of a round-robin round at
@@ -224,9 +223,10 @@ __device__ double block_sum(double v, double *red)
 
 // Rows b0 .. b0+bk-1 of X, already projected against the rows before b0:
 // two-pass classical Gram-Schmidt within the block.  A row left with less
-// than 1e-10 of its norm before any projection (nrm_pre, squared) lies in the
-// span of the rows before it: it is refilled with pseudo-random values and
-// orthogonalised against every earlier row of X.
+// than 1e-10 of its reference norm (nrm_pre, squared: before any projection,
+// or after the first Cholesky pass where the second flagged the block) lies
+// in the span of the rows before it: it is refilled with pseudo-random values
+// and orthogonalised against every earlier row of X.
 __global__ __launch_bounds__(OT) void orth_block_kernel(double *__restrict__ X, int b0, int bk,
                                                         int n,
                                                         const double *__restrict__ nrm_pre,
@@ -307,104 +307,231 @@ __global__ __launch_bounds__(OT) void orth_block_kernel(double *__restrict__ X, 
     }
 }
 
-// Cholesky factor L of the block Gram W [bk][bk] (bk <= kOrthBlock),
-// right-looking, one column per barrier step (thread (i, k) updates the
-// trailing entry (i, k)).  First pass (ref = the squared row norms before any
-// projection): flag = 1 when a pivot keeps less than 1e-8 of its reference
-// (a row within 1e-4 of the span of the rows before it), and the Cholesky
-// passes are then skipped for the Gram-Schmidt fallback.  Second pass (ref
-// NULL): runs only where the first did not flag, and flags a non-positive
-// pivot the same way.  Lout [bk][bk]: L (lower triangle).
-__global__ __launch_bounds__(kOrthBlock * kOrthBlock) void chol_small_kernel(
-    const double *__restrict__ W, int bk, const double *__restrict__ ref, int *__restrict__ flag,
-    double *__restrict__ Lout)
+// 1 / d for a positive normal d: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r), each of which squares the
+// relative error (a shorter dependent chain than the IEEE division, whose
+// scaling and fix-up steps only matter near the range limits)
+__device__ inline double recip(double d)
 {
-    __shared__ double A[kOrthBlock][kOrthBlock + 1];
-    __shared__ int bad;
-    const int tid = threadIdx.x;
-    const int i = tid / kOrthBlock, k = tid % kOrthBlock;
-    if (!ref && *flag)
-        return;
-    if (i < bk && k < bk)
-        A[i][k] = 0.5 * (W[i * bk + k] + W[k * bk + i]);
-    if (tid == 0)
-        bad = 0;
-    __syncthreads();
-    for (int j = 0; j < bk; ++j) {
-        if (tid == 0) {
-            const double d = A[j][j];
-            const double lim = ref ? 1e-8 * ref[j] : 0.0;
-            if (!(d > lim) || !(d > 0.0))
-                bad = 1;
-            else
-                A[j][j] = sqrt(d);
-        }
-        __syncthreads();
-        if (bad)
-            break;
-        if (tid > j && tid < bk)
-            A[tid][j] /= A[j][j];
-        __syncthreads();
-        if (i > j && k > j && k <= i && i < bk)
-            A[i][k] -= A[i][j] * A[k][j];
-        __syncthreads();
-    }
-    if (tid == 0 && (ref || bad))
-        *flag = bad;  // a failed second pass also hands the block to the fallback
-    if (!bad && i < bk && k < bk)
-        Lout[i * bk + k] = k <= i ? A[i][k] : 0.0;
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
 }
 
-// X_B <- L^{-1} X_B by forward substitution, one thread per column (skipped
-// when flagged)
-__global__ __launch_bounds__(256) void apply_linv_kernel(double *__restrict__ XB, int bk, int n,
-                                                         const double *__restrict__ L,
-                                                         const int *__restrict__ flag)
+// value of v in lane l (l uniform across the wave)
+__device__ inline double lane_value(double v, int l)
 {
-    __shared__ double Ls[kOrthBlock * kOrthBlock];
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Cholesky factor of the Gram W [k][k] of the k <= kOrthRows rows being
+// orthonormalised (W = X X^T, symmetrised on load), right-looking and blocked
+// by 16 columns.  Four waves: lane i holds row i, wave w its columns
+// 16w .. 16w + 15, in registers.  For each panel the owning wave factors its
+// 16 columns alone, column by column, broadcasting each column to its lanes
+// through LDS (within one wave, no barrier); it publishes the
+// finished columns to LDS, unscaled and scaled by the pivot's reciprocal, with
+// the entries above the diagonal as zeros, and after one barrier every later
+// wave applies the panel's 16 column steps A[i][c] -= (A[i][j] / A[j][j]) A[c][j]
+// to its own columns, in column order.
+// The zeros leave finished entries unchanged; entries above the diagonal take
+// meaningless values but are never published or stored.
+// First pass: nrm takes the squared row norms (the diagonal of W), the
+// reference of the Gram-Schmidt fallback; flag = 1 when a pivot keeps less
+// than 1e-11 of its row's squared norm (a row within about 3e-6 of the span of
+// the rows before it).  Above that limit the row-scaled matrix has a
+// condition number below about 3e5, inside the range (about 1e6 for 64 rows
+// of 65536 entries) where CholeskyQR2 returns rows orthonormal to working
+// precision (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya 2015; the
+// factorisation and the substitution are invariant to row scaling).  Second
+// pass: runs only where the first did not flag; its rows are then orthonormal
+// to within a few percent, so a pivot below half its row's squared norm means
+// the first pass lost more than the bound allows: the rows are flagged, and
+// nrm takes their squared norms.
+// Lt [k][k]: L transposed (Lt[c][i] = L[i][c] for i > c), 1 / L[c][c] on the
+// diagonal, zeros below it.
+constexpr int CW = 16;                     // columns per wave (one panel)
+constexpr int CT = 64 * (kOrthRows / CW);  // threads
+static_assert(kOrthRows == 64, "one row per lane");
+__global__ __launch_bounds__(CT) void chol_gram_kernel(const double *__restrict__ W, int k,
+                                                       double *__restrict__ nrm, int second,
+                                                       int *__restrict__ flag,
+                                                       double *__restrict__ Lt)
+{
+    __shared__ double pf[2][CW][kOrthRows];  // A[i][j] / A[j][j] (zero for i < j)
+    __shared__ double pv[2][CW][kOrthRows];  // A[i][j] (zero for i < j)
+    __shared__ double d0[kOrthRows];
+    __shared__ double piv[kOrthRows];
+    __shared__ double pc[kOrthRows];  // the panel owner's current column
+    __shared__ int sbad;
+    const int tid = threadIdx.x;
+    const int i = tid & 63, wave = tid >> 6, c0 = wave * CW;
+    if (second && *flag)
+        return;
+    const bool row = i < k;
+    // every load in bounds (indices clamped to k - 1), all issued before the
+    // first use
+    const int ic = min(i, k - 1);
+    double wa[CW], wb[CW];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        const int cc = min(c0 + m, k - 1);
+        wa[m] = W[ic * k + cc];
+        wb[m] = W[cc * k + ic];
+    }
+    const double dr = W[ic * k + ic];  // row i's squared norm (lane i)
+    double a[CW], lf[CW];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        a[m] = row && c0 + m < k ? 0.5 * (wa[m] + wb[m]) : 0.0;
+        lf[m] = 0.0;
+    }
+    if (tid < k)
+        d0[tid] = dr;
+    if (tid == 0)
+        sbad = 0;
+    int bad = 0;
+    for (int pb = 0; pb * CW < k; ++pb) {
+        const int buf = pb & 1;
+        if (wave == pb) {
+            int wbad = 0;
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) {
+                const int j = pb * CW + jj;
+                if (j < k && !wbad) {
+                    // the column through LDS (one wave: its LDS accesses
+                    // complete in order, no barrier needed)
+                    pc[i] = a[jj];
+                    const double d = pc[j];
+                    double v[CW];
+#pragma unroll
+                    for (int m = 0; m < CW; ++m)
+                        v[m] = pc[c0 + m];
+                    const double dj = lane_value(dr, j);
+                    const double lim = second ? 0.5 * dj : 1e-11 * dj;
+                    if (!(d > lim) || !(d > 0.0)) {
+                        wbad = 1;
+                    } else {
+                        if (i == 0)
+                            piv[j] = d;
+                        const double rd = recip(d);
+                        lf[jj] = a[jj];
+                        const double f = i >= j ? a[jj] * rd : 0.0;
+                        pf[buf][jj][i] = f;
+                        pv[buf][jj][i] = i >= j ? a[jj] : 0.0;
+#pragma unroll
+                        for (int m = jj + 1; m < CW; ++m)
+                            a[m] = fma(-f, v[m], a[m]);
+                    }
+                }
+            }
+            if (i == 0 && wbad)
+                sbad = 1;
+        }
+        __syncthreads();
+        if (sbad) {
+            bad = 1;
+            break;
+        }
+        if (wave > pb) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) {
+                const int j = pb * CW + jj;
+                if (j < k) {
+                    const double f = pf[buf][jj][i];
+                    double v[CW];
+#pragma unroll
+                    for (int m = 0; m < CW; ++m)
+                        v[m] = pv[buf][jj][c0 + m];
+#pragma unroll
+                    for (int m = 0; m < CW; ++m)
+                        a[m] = fma(-f, v[m], a[m]);
+                }
+            }
+        }
+    }
+    if (tid == 0 && (!second || bad))
+        *flag = bad;  // a failed second pass also hands the rows to the fallback
+    if ((!second || bad) && tid < k)
+        nrm[tid] = d0[tid];
+    if (bad || !row)
+        return;
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+        const int c = c0 + m;
+        if (c < k)
+            Lt[c * k + i] = c < i ? lf[m] / sqrt(piv[c]) : c == i ? 1.0 / sqrt(piv[c]) : 0.0;
+    }
+}
+
+// X <- L^{-1} X by forward substitution, one thread per column (skipped when
+// flagged); Lt as chol_gram_kernel writes it, staged in LDS.  Right-looking:
+// once x_j is final every later row takes its term at once, so the dependent
+// chain is two operations per row.  KB: k rounded up to a multiple of 16 (the
+// rows beyond k read clamped, in-bounds entries and are never stored).  Each
+// step sits behind its own (uniform) test against k, so that the reads of L
+// are not all hoisted at once (which would hold the whole factor in
+// registers); instead each step reads the next column while it computes.
+constexpr int AT = 64;
+template <int KB>
+__global__ __launch_bounds__(AT) void apply_linv_kernel(double *__restrict__ X, int k, int n,
+                                                        const double *__restrict__ Lt,
+                                                        const int *__restrict__ flag)
+{
+    __shared__ double Ls[KB * KB];
     if (*flag)
         return;
-    for (int e = threadIdx.x; e < bk * bk; e += 256)
-        Ls[e] = L[e];
+    static_assert(KB * KB % AT == 0, "whole staging rounds");
+    constexpr int SQ = KB * KB / AT;
+    double sv[SQ];
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {  // every load issued before the first store
+        const int e = threadIdx.x + AT * q;
+        sv[q] = Lt[min(e / KB, k - 1) * k + min(e % KB, k - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+        const int e = threadIdx.x + AT * q;
+        Ls[e] = e / KB < k && e % KB < k ? sv[q] : 0.0;
+    }
     __syncthreads();
-    const int a = blockIdx.x * 256 + threadIdx.x;
+    const int a = blockIdx.x * AT + threadIdx.x;
     if (a >= n)
         return;
-    double x[kOrthBlock];
+    double x[KB];
 #pragma unroll
-    for (int i = 0; i < kOrthBlock; ++i)
-        x[i] = i < bk ? XB[(long)i * n + a] : 0.0;
+    for (int i = 0; i < KB; ++i)
+        x[i] = X[(long)min(i, k - 1) * n + a];
+    // column j of L in registers, the next one read while step j computes
+    double lc[KB];
 #pragma unroll
-    for (int i = 0; i < kOrthBlock; ++i) {
-        if (i < bk) {
-            double v = x[i];
+    for (int i = 0; i < KB; ++i)
+        lc[i] = Ls[i];
 #pragma unroll
-            for (int j = 0; j < kOrthBlock; ++j)
-                if (j < i)
-                    v -= Ls[i * bk + j] * x[j];
-            x[i] = v / Ls[i * bk + i];
-            XB[(long)i * n + a] = x[i];
+    for (int j = 0; j < KB; ++j) {
+        if (j < k) {
+            double ln[KB];
+#pragma unroll
+            for (int i = j + 1; i < KB; ++i)
+                ln[i] = j + 1 < KB ? Ls[(j + 1) * KB + i] : 0.0;
+            x[j] *= lc[j];
+#pragma unroll
+            for (int i = j + 1; i < KB; ++i)
+                x[i] = fma(-lc[i], x[j], x[i]);
+#pragma unroll
+            for (int i = j + 1; i < KB; ++i)
+                lc[i] = ln[i];
         }
     }
-}
-
-__global__ __launch_bounds__(256) void row_norms_kernel(const double *__restrict__ X, int n,
-                                                        double *__restrict__ nrm)
-{
-    __shared__ double red[256];
-    const double *x = X + (long)blockIdx.x * n;
-    double s = 0.0;
-    for (int a = threadIdx.x; a < n; a += 256)
-        s += x[a] * x[a];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        nrm[blockIdx.x] = red[0];
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+        if (i < k)
+            X[(long)i * n + a] = x[i];
 }
 
 __global__ __launch_bounds__(256) void zero_rows_kernel(double *__restrict__ X, int i0, int k,
@@ -618,39 +745,31 @@ hipError_t launch_gemm_f64(bool nn, const double *A, const double *B, double *C,
     return hipGetLastError();
 }
 
-hipError_t launch_orth_rows(double *X, int k, int n, double *D, double *nrm, double *Linv,
-                            int *flag, double *part, unsigned long long salt, hipStream_t st)
+hipError_t launch_orth_rows(double *X, int k, int n, int passes, double *D, double *nrm,
+                            double *Linv, int *flag, double *part, unsigned long long salt,
+                            hipStream_t st)
 {
-    for (int b0 = 0; b0 < k; b0 += kOrthBlock) {
-        const int bk = std::min(kOrthBlock, k - b0);
-        double *XB = X + (long)b0 * n;
-        hipLaunchKernelGGL(row_norms_kernel, dim3(bk), dim3(256), 0, st, XB, n, nrm);
-        for (int pass = 0; pass < 2 && b0 > 0; ++pass) {
-            // D = X_B X_prev^T, X_B -= D X_prev
-            hipError_t e = launch_gemm_f64(false, XB, X, D, bk, b0, n, part, st, false);
-            if (e != hipSuccess)
-                return e;
-            e = launch_gemm_f64(true, D, X, XB, bk, n, b0, part, st, true);
-            if (e != hipSuccess)
-                return e;
-        }
-        // two Cholesky passes within the block (W in D)
-        for (int pass = 0; pass < 2; ++pass) {
-            hipError_t e = launch_gemm_f64(false, XB, XB, D, bk, bk, n, part, st, false);
-            if (e != hipSuccess)
-                return e;
-            hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(kOrthBlock * kOrthBlock), 0, st,
-                               D, bk, pass == 0 ? nrm : nullptr, flag, Linv);
-            hipLaunchKernelGGL(apply_linv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, XB,
-                               bk, n, Linv, flag);
-        }
-        hipLaunchKernelGGL(orth_block_kernel, dim3(1), dim3(OT), 0, st, X, b0, bk, n, nrm, flag,
-                           salt + 104729ull * b0);
-        const hipError_t e = hipGetLastError();
+    if (k < 1 || k > kOrthRows || k > n || passes < 1 || passes > 2)
+        return hipErrorInvalidValue;
+    for (int pass = 0; pass < passes; ++pass) {
+        // W = X X^T on matrix cores, its Cholesky factor, X <- L^{-1} X
+        hipError_t e = launch_gemm_f64(false, X, X, D, k, k, n, part, st, false);
         if (e != hipSuccess)
             return e;
+        hipLaunchKernelGGL(chol_gram_kernel, dim3(1), dim3(CT), 0, st, D, k, nrm, pass, flag,
+                           Linv);
+        const dim3 grid((n + AT - 1) / AT);
+        if (k <= 16)
+            hipLaunchKernelGGL(apply_linv_kernel<16>, grid, dim3(AT), 0, st, X, k, n, Linv, flag);
+        else if (k <= 32)
+            hipLaunchKernelGGL(apply_linv_kernel<32>, grid, dim3(AT), 0, st, X, k, n, Linv, flag);
+        else if (k <= 48)
+            hipLaunchKernelGGL(apply_linv_kernel<48>, grid, dim3(AT), 0, st, X, k, n, Linv, flag);
+        else
+            hipLaunchKernelGGL(apply_linv_kernel<64>, grid, dim3(AT), 0, st, X, k, n, Linv, flag);
     }
-    return hipSuccess;
+    hipLaunchKernelGGL(orth_block_kernel, dim3(1), dim3(OT), 0, st, X, 0, k, n, nrm, flag, salt);
+    return hipGetLastError();
 }
 
 hipError_t launch_random_rows(double *X, int i0, int k, int n, unsigned long long salt,
