@@ -22,9 +22,9 @@
 //                 keeps less than 1e-10 is replaced by pseudo-random values and
 //                 orthogonalised against every earlier row;
 //   jacobi_eig    cyclic Jacobi on a symmetric k x k matrix (k <= 64) held in
-//                 LDS, the k/2 disjoint rotations of a round-robin round at
-//                 once; eigenvalues sorted in decreasing order, eigenvectors
-//                 as rows;
+//                 LDS, the k/2 disjoint rotations of a round-robin round
+//                 applied at once, block by block; eigenvalues sorted in
+//                 decreasing order, eigenvectors as rows;
 //   khatri_rao    K[(i, j)][t] = c_t Ua[i][t] Ub[j][t];
 //   sign_rows     each basis vector's entry of largest magnitude positive.
 #include "tc_internal.h"
@@ -553,7 +553,24 @@ __global__ __launch_bounds__(256) void random_rows_kernel(double *__restrict__ X
     X[(long)i * n + a] = hash_unit(salt, i, a);
 }
 
-constexpr int JT = 256;
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton-Raphson steps r <- r (3 - x r^2) / 2
+__device__ inline double rsqrt_nr(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    r = r * fma(-0.5 * x, r * r, 1.5);
+    return r * fma(-0.5 * x, r * r, 1.5);
+}
+
+// Cyclic Jacobi on the symmetric H [k][k] in LDS.  Each round-robin round
+// rotates k/2 disjoint pairs (p, q); since the pairs partition the indices,
+// the 2 x 2 blocks (rows of one pair, columns of another) partition H, and
+// each block becomes R1 B R2^T in one pass, one thread per block, with
+// R = [[c, -s], [s, c]] (the identity for a pair that is not rotated); the
+// columns of V take the same rotations in that pass.  A round in which no
+// pair rotates (all of the last, confirming sweep) skips that pass and its
+// barrier.
+constexpr int JT = 1024;
 
 __global__ __launch_bounds__(JT) void jacobi_eig_kernel(const double *__restrict__ Hin, int k,
                                                         double *__restrict__ lam,
@@ -563,19 +580,20 @@ __global__ __launch_bounds__(JT) void jacobi_eig_kernel(const double *__restrict
     __shared__ double V[kTuckerMaxSub][kTuckerMaxSub + 1];
     __shared__ double cs[kTuckerMaxSub / 2], sn[kTuckerMaxSub / 2];
     __shared__ int pp[kTuckerMaxSub / 2], qq[kTuckerMaxSub / 2];
-    __shared__ int rotated;
+    __shared__ int rotated, live[2];
     const int tid = threadIdx.x;
-    for (int e = tid; e < k * k; e += JT) {
-        const int i = e / k, j = e % k;
-        H[i][j] = 0.5 * (Hin[(long)i * k + j] + Hin[(long)j * k + i]);
+    const int kk = k + (k & 1);  // an odd k gets one padding index, never rotated
+    const int half = kk / 2;
+    for (int e = tid; e < kk * kk; e += JT) {
+        const int i = e / kk, j = e % kk;
+        H[i][j] = i < k && j < k ? 0.5 * (Hin[(long)i * k + j] + Hin[(long)j * k + i]) : 0.0;
         V[i][j] = i == j ? 1.0 : 0.0;
     }
-    const int kk = k + (k & 1);
-    const int half = kk / 2;
-    __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
-        if (tid == 0)
+        if (tid == 0) {
             rotated = 0;
+            live[0] = 0;  // round 0's flag (the previous sweep ended with a barrier)
+        }
         __syncthreads();
         for (int rnd = 0; rnd < kk - 1; ++rnd) {
             if (tid < half) {
@@ -588,54 +606,55 @@ __global__ __launch_bounds__(JT) void jacobi_eig_kernel(const double *__restrict
                     p = q;
                     q = t;
                 }
-                double c = 1.0, s = 0.0;
-                int live = 0;
+                double c = 1.0, sv = 0.0;
                 if (q < k) {
                     const double hpq = H[p][q], hpp = H[p][p], hqq = H[q][q];
-                    if (hpq != 0.0 && fabs(hpq) > 1e-17 * sqrt(fabs(hpp * hqq))) {
-                        const double th = (hqq - hpp) / (2.0 * hpq);
-                        const double t = th != 0.0
-                                             ? copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0))
-                                             : 1.0;
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                        live = 1;
+                    // |h_pq| > 1e-17 sqrt(|h_pp h_qq|), squared
+                    if (hpq != 0.0 && hpq * hpq > 1e-34 * fabs(hpp * hqq)) {
+                        const double th = (hqq - hpp) * recip(2.0 * hpq);
+                        const double u = fma(th, th, 1.0);
+                        const double t =
+                            th != 0.0 ? copysign(recip(fabs(th) + u * rsqrt_nr(u)), th) : 1.0;
+                        c = rsqrt_nr(fma(t, t, 1.0));
+                        sv = t * c;
                         rotated = 1;
+                        live[rnd & 1] = 1;
                     }
                 }
-                pp[tid] = live ? p : -1;
+                pp[tid] = p;
                 qq[tid] = q;
                 cs[tid] = c;
-                sn[tid] = s;
+                sn[tid] = sv;
             }
+            if (tid == JT - 1)
+                live[(rnd + 1) & 1] = 0;  // the next round's flag (read two barriers ago)
             __syncthreads();
-            for (int e = tid; e < half * k; e += JT) {
-                const int r = e / k, col = e % k;
-                const int p = pp[r];
-                if (p >= 0) {
-                    const int q = qq[r];
-                    const double c = cs[r], s = sn[r];
-                    const double hp = H[p][col], hq = H[q][col];
-                    H[p][col] = c * hp - s * hq;
-                    H[q][col] = s * hp + c * hq;
+            if (live[rnd & 1]) {
+                for (int e = tid; e < half * half; e += JT) {
+                    const int r1 = e / half, r2 = e % half;
+                    const int p1 = pp[r1], q1 = qq[r1], p2 = pp[r2], q2 = qq[r2];
+                    const double c1 = cs[r1], s1 = sn[r1], c2 = cs[r2], s2 = sn[r2];
+                    const double h00 = H[p1][p2], h01 = H[p1][q2], h10 = H[q1][p2],
+                                 h11 = H[q1][q2];
+                    // rows: R1 B
+                    const double a00 = c1 * h00 - s1 * h10, a01 = c1 * h01 - s1 * h11;
+                    const double a10 = s1 * h00 + c1 * h10, a11 = s1 * h01 + c1 * h11;
+                    // columns: (R1 B) R2^T
+                    H[p1][p2] = c2 * a00 - s2 * a01;
+                    H[p1][q2] = s2 * a00 + c2 * a01;
+                    H[q1][p2] = c2 * a10 - s2 * a11;
+                    H[q1][q2] = s2 * a10 + c2 * a11;
                 }
-            }
-            __syncthreads();
-            for (int e = tid; e < half * k; e += JT) {
-                const int r = e / k, row = e % k;
-                const int p = pp[r];
-                if (p >= 0) {
-                    const int q = qq[r];
-                    const double c = cs[r], s = sn[r];
-                    const double hp = H[row][p], hq = H[row][q];
-                    H[row][p] = c * hp - s * hq;
-                    H[row][q] = s * hp + c * hq;
+                for (int e = tid; e < half * kk; e += JT) {
+                    const int r = e / kk, row = e % kk;
+                    const int p = pp[r], q = qq[r];
+                    const double c = cs[r], sv = sn[r];
                     const double vp = V[row][p], vq = V[row][q];
-                    V[row][p] = c * vp - s * vq;
-                    V[row][q] = s * vp + c * vq;
+                    V[row][p] = c * vp - sv * vq;
+                    V[row][q] = sv * vp + c * vq;
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if (!rotated)
             break;
