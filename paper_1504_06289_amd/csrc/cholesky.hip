@@ -222,6 +222,89 @@ __global__ __launch_bounds__(kFitUThreads) void fit_u_kernel(const double *__res
         U[(long)s * n + a] = 0.0;
 }
 
+// The same solve with the solved entries of the thread's own column kept in
+// LDS (ush[r][lane]), for R <= kFitMaxR.  The rows of T^T that a block of
+// eight unknowns needs (Tsh[q][r] = T[r][s], s = top - q) are staged in LDS as
+// well, and the next block's rows of T and of L are loaded into registers
+// while the current block is solved, so that no step waits on global memory.
+// The inner products run over four interleaved partial sums.  (fit_u_kernel
+// above re-reads every solved entry from global memory in its inner loop.)
+constexpr int kFitMaxR = 256;  // ush 128 KB + Tsh 16 KB of LDS
+constexpr int kFitBlk = 8;
+constexpr int kFitTQ = kFitBlk * kFitMaxR / kFitUThreads;  // staged T entries per lane
+
+__global__ __launch_bounds__(kFitUThreads) void fit_u_lds_kernel(const double *__restrict__ L,
+                                                                 int n, int R, int R_max,
+                                                                 const double *__restrict__ Tg,
+                                                                 double *__restrict__ U)
+{
+    __shared__ double ush[kFitMaxR][kFitUThreads];
+    __shared__ double Tsh[kFitBlk][kFitMaxR];
+    const int lane = threadIdx.x;
+    const int a = blockIdx.x * kFitUThreads + lane;
+    const int ac = min(a, n - 1);  // loads stay in bounds; results of a >= n are not stored
+    // rows top, top - 1, ..., top - 7 of L and of T^T (zero below row 0)
+    auto load_l = [&](int top, double(&dst)[kFitBlk]) {
+#pragma unroll
+        for (int q = 0; q < kFitBlk; ++q) {
+            const int sr = top - q;
+            dst[q] = sr >= 0 ? L[(long)sr * n + ac] : 0.0;
+        }
+    };
+    auto load_t = [&](int top, double(&dst)[kFitTQ]) {
+#pragma unroll
+        for (int e = 0; e < kFitTQ; ++e) {
+            const int idx = lane + kFitUThreads * e;
+            const int q = idx / kFitMaxR, r = idx % kFitMaxR;
+            const int sr = top - q;
+            dst[e] = sr >= 0 && r < R ? Tg[(long)sr * R + r] : 0.0;
+        }
+    };
+    double lcur[kFitBlk], lnxt[kFitBlk], tnxt[kFitTQ];
+    load_l(R - 1, lnxt);
+    load_t(R - 1, tnxt);
+    for (int top = R - 1; top >= 0; top -= kFitBlk) {
+        __syncthreads();  // the previous block's reads of Tsh are done
+#pragma unroll
+        for (int e = 0; e < kFitTQ; ++e) {
+            const int idx = lane + kFitUThreads * e;
+            Tsh[idx / kFitMaxR][idx % kFitMaxR] = tnxt[e];
+        }
+#pragma unroll
+        for (int q = 0; q < kFitBlk; ++q)
+            lcur[q] = lnxt[q];
+        __syncthreads();
+        if (top - kFitBlk >= 0) {
+            load_l(top - kFitBlk, lnxt);
+            load_t(top - kFitBlk, tnxt);
+        }
+#pragma unroll
+        for (int q = 0; q < kFitBlk; ++q) {
+            const int sr = top - q;
+            if (sr >= 0) {
+                const double *ts = Tsh[q];  // T[r][sr] = ts[r]
+                double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+                int r = sr + 1;
+                for (; r + 3 < R; r += 4) {
+                    acc0 = fma(ts[r], ush[r][lane], acc0);
+                    acc1 = fma(ts[r + 1], ush[r + 1][lane], acc1);
+                    acc2 = fma(ts[r + 2], ush[r + 2][lane], acc2);
+                    acc3 = fma(ts[r + 3], ush[r + 3][lane], acc3);
+                }
+                for (; r < R; ++r)
+                    acc0 = fma(ts[r], ush[r][lane], acc0);
+                const double v = (lcur[q] - ((acc0 + acc1) + (acc2 + acc3))) / ts[sr];
+                ush[sr][lane] = v;
+                if (a < n)
+                    U[(long)sr * n + a] = v;
+            }
+        }
+    }
+    if (a < n)
+        for (int sr = R; sr < R_max; ++sr)
+            U[(long)sr * n + a] = 0.0;
+}
+
 // V[i][r] = F[i][P[r]] for r < R, zero for R <= r < R_max
 __global__ __launch_bounds__(CT) void fit_v_kernel(const double *__restrict__ F, int n,
                                                    int N_pair, int R, int R_max,
@@ -447,8 +530,12 @@ hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair
         hipLaunchKernelGGL(fit_t_kernel, dim3((unsigned)((e + CT - 1) / CT)), dim3(CT), 0, st, L,
                            n, R, piv, Tg);
     }
-    hipLaunchKernelGGL(fit_u_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
-                       dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
+    if (R <= kFitMaxR)
+        hipLaunchKernelGGL(fit_u_lds_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
+                           dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
+    else
+        hipLaunchKernelGGL(fit_u_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
+                           dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
     const long e = (long)N_pair * R_max;
     hipLaunchKernelGGL(fit_v_kernel, dim3((unsigned)((e + CT - 1) / CT)), dim3(CT), 0, st, F, n,
                        N_pair, R, R_max, piv, V);
