@@ -36,34 +36,50 @@ def agreed_prefix(m):
     return int(bad[0]) if len(bad) else len(m)
 
 
+def check_fit(tc, orc, F, tol, label):
+    n = F.shape[1]
+    Uo, Vo, po, reso = orc.density_fit(F, tol, n)
+    U, V, piv, R, res = tc.density_fit(dev(F), tol)
+    U, V = host(U), host(V)
+    k = agreed_prefix(margins(F.T @ F, po))
+    say(f"   {label}: R = {R} (oracle {len(po)}), pivots agree on {k} decisive steps")
+    np.testing.assert_array_equal(piv[:k], po[:k])
+    # the fit itself: |F - V U|^2 = residual trace <= tol^2 trace(F^T F)
+    trA = np.sum(F * F)
+    err2 = np.sum((F - V[:, :R] @ U[:R]) ** 2)
+    assert abs(err2 - res) <= 1e-9 * trA
+    assert err2 <= tol * tol * trA * (1 + 1e-6) + 1e-28 * trA
+    np.testing.assert_array_equal(V[:, R:], 0.0)
+    np.testing.assert_array_equal(U[R:], 0.0)
+    np.testing.assert_array_equal(V[:, :R], F[:, piv])
+    if k == len(po) == R:
+        # the same pivots: the same fitted matrix (U itself is the
+        # solution of a triangular system whose late pivots are small, so
+        # its entries carry rounding amplified by that conditioning)
+        fit_diff = np.linalg.norm(V[:, :R] @ U[:R] - Vo @ Uo)
+        say(f"      |VU - (VU)_oracle| / |F| = {fit_diff / np.sqrt(trA):.2e}")
+        assert fit_diff <= max(tol, 1e-9) * np.sqrt(trA)
+    return R
+
+
 @pytest.mark.parametrize("n,N_pair,tol", [(96, 60, 1e-3), (200, 150, 1e-6), (333, 90, 1e-7),
                                           (64, 10, 1e-6)])
 def test_density_fit(tc, orc, n, N_pair, tol):
     say(f"density fit n={n} N_pair={N_pair} tol={tol}")
     U0, _ = wl.gaussian_products(n, 8.0, N_pair, seed=n + N_pair)
     for l in range(3):
-        F = U0[l]
-        Uo, Vo, po, reso = orc.density_fit(F, tol, n)
-        U, V, piv, R, res = tc.density_fit(dev(F), tol)
-        U, V = host(U), host(V)
-        k = agreed_prefix(margins(F.T @ F, po))
-        say(f"   mode {l}: R = {R} (oracle {len(po)}), pivots agree on {k} decisive steps")
-        np.testing.assert_array_equal(piv[:k], po[:k])
-        # the fit itself: |F - V U|^2 = residual trace <= tol^2 trace(F^T F)
-        trA = np.sum(F * F)
-        err2 = np.sum((F - V[:, :R] @ U[:R]) ** 2)
-        assert abs(err2 - res) <= 1e-9 * trA
-        assert err2 <= tol * tol * trA * (1 + 1e-6) + 1e-28 * trA
-        np.testing.assert_array_equal(V[:, R:], 0.0)
-        np.testing.assert_array_equal(U[R:], 0.0)
-        np.testing.assert_array_equal(V[:, :R], F[:, piv])
-        if k == len(po) == R:
-            # the same pivots: the same fitted matrix (U itself is the
-            # solution of a triangular system whose late pivots are small, so
-            # its entries carry rounding amplified by that conditioning)
-            fit_diff = np.linalg.norm(V[:, :R] @ U[:R] - Vo @ Uo)
-            say(f"      |VU - (VU)_oracle| / |F| = {fit_diff / np.sqrt(trA):.2e}")
-            assert fit_diff <= max(tol, 1e-9) * np.sqrt(trA)
+        check_fit(tc, orc, U0[l], tol, f"mode {l}")
+
+
+def test_density_fit_rank_above_256(tc, orc):
+    """Random products (no decay of the spectrum) fitted to rank above 256:
+    the back substitution that keeps its solved entries in global memory
+    (ranks up to 256 keep them in LDS)."""
+    rng = np.random.default_rng(11)
+    F = rng.standard_normal((320, 400))
+    say("density fit of rank above 256")
+    R = check_fit(tc, orc, F, 1e-6, "random 320 x 400")
+    assert R > 256
 
 
 def test_tei_cholesky_pipeline(tc, orc):
