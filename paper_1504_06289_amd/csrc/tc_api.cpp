@@ -1519,10 +1519,22 @@ static int tucker_sub(int n, int r)
 // Workspace: [X: 64 x nmax][P: 64 x mmax][part: slices x 64 x max(nmax, mmax)]
 // [H: 64 x 64][lam: 64][Vt: 64 x 64][Ut: 3 x 48 x R][K: 48^2 x R][Mt: 48^2 x nmax]
 struct TuckerPlan {
-    double *X, *P, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt, *D, *nrm, *Linv, *lamA;
+    double *X, *P, *P2, *Gm, *part, *H, *lam, *Vt, *Ut[3], *K, *Mt, *D, *nrm, *Linv, *lamA;
     int *flag;
     size_t bytes;
 };
+
+// Orthogonal iteration in the space of B's rows (Y <- orth(Y B B^T), k x m)
+// instead of on X (k x n) when forming B B^T once costs less than the
+// products it saves (2 m^2 n against 2 its k m n).  The workspace holds B B^T
+// for m up to 4096 where that pays at the default of 20 steps; a call with
+// fewer steps checks its own count as well.
+constexpr int kTuckerGramIts = 20;
+constexpr int kTuckerGramMaxM = 4096;
+static bool tucker_gram_form(int m, int n, int k)
+{
+    return m >= k && m <= kTuckerGramMaxM && (long)m * m <= (long)kTuckerGramIts * k * n;
+}
 
 static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
 {
@@ -1534,8 +1546,19 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         for (int m = l + 1; m < 3; ++m)
             rr = std::max(rr, (long)r[l] * r[m]);
     const long mmax = std::max((long)R, rr);
+    // the Gram form's B B^T: the largest m that takes it
+    long gmax = 0;
+    for (int l = 0; l < 3; ++l) {
+        const int k = tucker_sub(n[l], r[l]);
+        const int m1 = l == 0 ? 1 : 0, m2 = l == 2 ? 1 : 2;
+        for (long m : {(long)R, (long)r[m1] * r[m2]})
+            if (tucker_gram_form((int)m, n[l], k))
+                gmax = std::max(gmax, m);
+    }
     T.X = c.take<double>((size_t)kTuckerMaxSub * nmax);
     T.P = c.take<double>((size_t)kTuckerMaxSub * mmax);
+    T.P2 = c.take<double>((size_t)kTuckerMaxSub * mmax);
+    T.Gm = c.take<double>((size_t)gmax * gmax);
     // split-slice scratch: the largest of the products the transform forms
     size_t part = 0;
     auto need = [&](long I, long N, long K) {
@@ -1554,6 +1577,11 @@ static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
         need(r[l], R, n[l]);
         need(q, n[l], R);
         need(k, k, n[l]);
+        for (long m : {(long)R, q})
+            if (tucker_gram_form((int)m, n[l], k)) {
+                need(m, m, n[l]);  // B B^T
+                need(k, m, m);     // Y (B B^T)
+            }
     }
     need(r[0], (long)r[1] * r[2], R);
     T.part = c.take<double>(part);
@@ -1597,6 +1625,23 @@ static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int 
     };
     TRYK("random_rows", launch_random_rows(T.X, warm ? r : 0, k, n, salt, st));
     TRYK("orth_rows", orth(T.X, n, 1, salt + 1));
+    if (tucker_gram_form(m, n, k) && (long)m * m <= (long)its * k * n) {
+        // Y_0 = orth(X B^T), Y_t = orth(Y_{t-1} B B^T), X = orth2(Y_{its-1} B): the
+        // subspaces of the loop below (its applications of B^T B) with one
+        // product of k x m by m x m per step
+        TRYK("gemm_f64", launch_gemm_f64(false, B, B, T.Gm, m, m, n, T.part, st));  // B B^T
+        TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));  // X B^T
+        TRYK("orth_rows", orth(T.P, m, 1, salt + 1 + its + 1));
+        double *Y = T.P, *Yn = T.P2;
+        for (int it = 1; it < its; ++it) {
+            TRYK("gemm_f64", launch_gemm_f64(false, Y, T.Gm, Yn, k, m, m, T.part, st));
+            std::swap(Y, Yn);
+            TRYK("orth_rows", orth(Y, m, 1, salt + 2 + it));
+        }
+        TRYK("gemm_f64", launch_gemm_f64(true, Y, B, T.X, k, n, m, T.part, st));  // Y B
+        TRYK("orth_rows", orth(T.X, n, 2, salt + 2));
+        its = 0;  // the steps are done
+    }
     for (int it = 0; it < its; ++it) {
         TRYK("gemm_f64", launch_gemm_f64(false, T.X, B, T.P, k, m, n, T.part, st));  // X B^T
         if (it == 0 && m >= k)
