@@ -1,7 +1,7 @@
 // Diagnostics behind two environment switches (read at every call):
 //   TC_CHECK_FINITE=1  the binary64 inputs of a call are scanned for NaN and
 //                      Inf before any work is enqueued; the call then
-//                      synchronises its stream once to read the verdict.
+//                      synchronises its stream once to read the result.
 //   TC_DEBUG_SYNC=1    every kernel launch is followed by a synchronisation
 //                      of its stream, and the first failing kernel is named
 //                      on stderr.
