@@ -416,9 +416,9 @@ tc_status tc_coulomb(const tc_density *prob, tc_precision prec, void *ws, size_t
  *   (residual trace; may be NULL) host outputs.
  *   ws: tc_density_fit_workspace_bytes(n, N_pair, R_max).
  * Synchronises `stream`: once before the first step (to read trace(A)), once
- * per group of 16 steps (the stopping test runs on the device, which turns
- * the remaining steps of a group into no-ops; the host reads its flag once
- * per group), and once at the end.
+ * per group of steps (16, then 32, then 64 steps a group; the stopping test
+ * runs on the device, which turns the remaining steps of a group into no-ops;
+ * the host reads its flag once per group), and once at the end.
  */
 size_t tc_density_fit_workspace_bytes(int n, int N_pair, int R_max);
 tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int R_max,
@@ -442,7 +442,7 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
  *   pivots_host [R_max] (may be NULL), R_out, residual_out (may be NULL).
  *   ws: tc_tei_cholesky_workspace_bytes(N_pair, R, R_N, R_max).
  * Synchronises `stream` as tc_density_fit does: before the first step and
- * once per group of 16 steps.
+ * once per group of steps (16, 32, then 64).
  */
 size_t tc_tei_cholesky_workspace_bytes(int N_pair, int R, int R_N, int R_max);
 tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,

@@ -1097,9 +1097,13 @@ CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
 // Runs the loop: `column` enqueues the column of A at the pivot into s.col.
 // thr_rel: the steps run while the residual trace exceeds thr_rel * trace(A).
 // After one synchronisation for trace(A), the steps are enqueued in groups of
-// kCholGroup; the device stops itself (done flag) and the host checks the
-// flag once per group.
+// 16, 32, then 64 steps; the device stops itself (done flag: the rest of a
+// group are no-ops) and the host checks the flag once per group.  Each check
+// leaves the device idle for a round trip to the host, and the growing groups
+// take fewer of them on long factorisations at the cost of at most 63 no-op
+// steps after the last.
 constexpr int kCholGroup = 16;
+constexpr int kCholGroupMax = 64;
 
 template <class Column>
 // A: the formed matrix [N][N] (its pivot rows are the columns), or null and
@@ -1129,8 +1133,9 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
         state[2] = 0;
     }
     int r = 0;
+    int group = kCholGroup;
     while (!state[1]) {
-        for (int g = 0; g < kCholGroup && r < R_max; ++g, ++r) {
+        for (int g = 0; g < group && r < R_max; ++g, ++r) {
             if (!A) {
                 const tc_status cs = column(st);
                 if (cs != TC_OK)
@@ -1142,6 +1147,7 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
         }
         if (!fetch())
             return TC_ERR_HIP;
+        group = std::min(2 * group, kCholGroupMax);
     }
     const int R = state[2];
     *R_out = R;
