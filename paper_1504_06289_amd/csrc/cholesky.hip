@@ -113,6 +113,93 @@ __global__ __launch_bounds__(kStepA * kStepG) void chol_step_kernel(
     }
 }
 
+// One step on a formed matrix, with the selection of its pivot in the same
+// launch.  Every workgroup scans the residual diagonal d_in (the previous
+// step's output, earlier pivots already zero) with chol_select's loop and
+// reduction order, so each finds the same pivot, trace and stopping decision
+// without communicating; workgroup 0 records them (state, stats, piv, ispiv).
+// Unless the factorisation is done, each workgroup then forms its kStepA
+// entries of L_r as chol_step does and writes the next residual diagonal to
+// d_out (the pivot's entry zero), so no workgroup reads an entry that another
+// is updating.  The steps alternate the two diagonal buffers.
+__global__ __launch_bounds__(kStepA * kStepG) void chol_select_step_kernel(
+    const double *__restrict__ A, double *__restrict__ L, int N, int r, int *__restrict__ ispiv,
+    int *__restrict__ state, const double *__restrict__ d_in, double *__restrict__ d_out,
+    double thr, int R_max, double *__restrict__ stats, int *__restrict__ piv)
+{
+    constexpr int TT = kStepA * kStepG;
+    static_assert(TT == 1024, "chol_select's reduction order");
+    __shared__ double smax[TT], ssum[TT];
+    __shared__ int sidx[TT];
+    __shared__ double red[kStepG][kStepA + 1];
+    if (state[1])
+        return;
+    const int tid = threadIdx.x;
+    {
+        double m = -1.0, sm = 0.0;
+        int idx = 0x7fffffff;
+        for (int a = tid; a < N; a += TT) {
+            const double v = d_in[a];
+            sm += v;
+            if (v > m) {
+                m = v;
+                idx = a;
+            }
+        }
+        smax[tid] = m;
+        ssum[tid] = sm;
+        sidx[tid] = idx;
+    }
+    __syncthreads();
+    for (int w = TT / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            const double m2 = smax[tid + w];
+            const int i2 = sidx[tid + w];
+            if (m2 > smax[tid] || (m2 == smax[tid] && i2 < sidx[tid])) {
+                smax[tid] = m2;
+                sidx[tid] = i2;
+            }
+            ssum[tid] += ssum[tid + w];
+        }
+        __syncthreads();
+    }
+    const double mx = smax[0], tr = ssum[0];
+    const int p = sidx[0];
+    const bool done = r >= R_max || !(tr > thr) || !(mx > 0.0);
+    if (blockIdx.x == 0 && tid == 0) {
+        stats[0] = mx;
+        stats[1] = tr;
+        if (done) {
+            state[1] = 1;
+            state[2] = r;
+        } else {
+            state[0] = p;
+            piv[r] = p;
+            ispiv[p] = 1;  // read below only at a != p
+        }
+    }
+    if (done)
+        return;
+    const int al = tid & (kStepA - 1), g = tid / kStepA;
+    const int a = blockIdx.x * kStepA + al;
+    double sum = 0.0;
+    if (a < N)
+        for (int q = g; q < r; q += kStepG)
+            sum = fma(L[(long)q * N + a], L[(long)q * N + p], sum);
+    red[g][al] = sum;
+    __syncthreads();
+    if (g == 0 && a < N) {
+        double v = A[(long)p * N + a];
+        for (int h = 0; h < kStepG; ++h)
+            v -= red[h][al];
+        double l = v / sqrt(d_in[p]);
+        if (a != p && ispiv[a])
+            l = 0.0;
+        L[(long)r * N + a] = l;
+        d_out[a] = a == p ? 0.0 : d_in[a] - l * l;
+    }
+}
+
 // The largest residual diagonal entry (first index among equals) and the
 // residual trace; one workgroup.  state = {pivot, done, steps}, stats = {max,
 // trace}.  Nothing happens once done is set.  `clear`: the last pivot's entry
@@ -442,6 +529,16 @@ hipError_t launch_chol_step(const double *col, const double *A, double *L, int N
 {
     hipLaunchKernelGGL(chol_step_kernel, dim3((N + kStepA - 1) / kStepA), dim3(kStepA * kStepG),
                        0, st, col, A, L, N, r, ispiv, state, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_select_step(const double *A, double *L, int N, int r, int *ispiv,
+                                   int *state, const double *d_in, double *d_out, double thr,
+                                   int R_max, double *stats, int *piv, hipStream_t st)
+{
+    hipLaunchKernelGGL(chol_select_step_kernel, dim3((N + kStepA - 1) / kStepA),
+                       dim3(kStepA * kStepG), 0, st, A, L, N, r, ispiv, state, d_in, d_out, thr,
+                       R_max, stats, piv);
     return hipGetLastError();
 }
 

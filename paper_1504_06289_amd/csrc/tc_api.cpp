@@ -1074,7 +1074,7 @@ tc_status backward_instance(const tc_instance &I, const double *Jbar, double *co
 // Scratch of one pivoted Cholesky: residual diagonal, pivot column, device
 // pivots, pivot state and statistics, and (fit only) the factor L.
 struct CholScratch {
-    double *d, *col, *L, *y, *Yd, *stats;
+    double *d, *d2, *col, *L, *y, *Yd, *stats;
     int *piv, *state, *ispiv;
 };
 
@@ -1083,6 +1083,7 @@ CholScratch carve_chol(Carver &c, int N, int R_max, bool own_L, size_t y_len,
 {
     CholScratch s{};
     s.d = c.take<double>(N);
+    s.d2 = c.take<double>(N);  // the other residual diagonal of the formed-matrix steps
     s.col = c.take<double>(N);
     s.L = own_L ? c.take<double>((size_t)R_max * N) : nullptr;
     s.y = y_len ? c.take<double>(y_len) : nullptr;
@@ -1136,14 +1137,27 @@ tc_status pivoted_cholesky(int N, int R_max, double thr_rel, const CholScratch &
     int group = kCholGroup;
     while (!state[1]) {
         for (int g = 0; g < group && r < R_max; ++g, ++r) {
-            if (!A) {
-                const tc_status cs = column(st);
-                if (cs != TC_OK)
-                    return cs;
+            if (A) {
+                // formed matrix: the selection of step r's pivot and the step
+                // in one launch (the diagonal alternates between d and d2;
+                // step r reads the one step r - 1 wrote)
+                double *din = (r & 1) ? s.d2 : s.d, *dout = (r & 1) ? s.d : s.d2;
+                TRYK("chol_step", launch_chol_select_step(A, L, N, r, s.ispiv, s.state, din,
+                                                          dout, thr, R_max, s.stats, s.piv, st));
+                continue;
             }
+            const tc_status cs = column(st);
+            if (cs != TC_OK)
+                return cs;
             TRYK("chol_step", launch_chol_step(s.col, A, L, N, r, s.ispiv, s.state, s.d, st));
             TRYK("chol_select", launch_chol_select(s.d, N, 1, r + 1, thr, R_max, s.state,
                                                    s.stats, s.piv, s.ispiv, st));
+        }
+        if (A && r >= R_max && !state[1]) {
+            // every step enqueued: one more selection records the end (r = R_max)
+            double *din = (r & 1) ? s.d2 : s.d, *dout = (r & 1) ? s.d : s.d2;
+            TRYK("chol_step", launch_chol_select_step(A, L, N, r, s.ispiv, s.state, din, dout,
+                                                      thr, R_max, s.stats, s.piv, st));
         }
         if (!fetch())
             return TC_ERR_HIP;

@@ -226,6 +226,13 @@ hipError_t launch_chol_step(const double *col, const double *A, double *L, int N
                             const int *ispiv, const int *state, double *d, hipStream_t st);
 // state = {pivot, done, steps}; the next pivot is recorded in piv[steps] and
 // ispiv; see cholesky.hip
+// step r on the formed matrix A with the selection of its pivot (from d_in,
+// the previous step's residual diagonal) in one launch: records state, stats,
+// piv[r] and ispiv as launch_chol_select does, then (unless done) forms L_r
+// and writes the next residual diagonal to d_out (d_in and d_out distinct).
+hipError_t launch_chol_select_step(const double *A, double *L, int N, int r, int *ispiv,
+                                   int *state, const double *d_in, double *d_out, double thr,
+                                   int R_max, double *stats, int *piv, hipStream_t st);
 hipError_t launch_chol_select(double *d, int N, int clear, int steps, double thr, int R_max,
                               int *state, double *stats, int *piv, int *ispiv, hipStream_t st);
 // entries of the factorised TEI matrix from V and Y = V M (Y as left by
