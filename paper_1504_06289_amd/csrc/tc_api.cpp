@@ -1546,14 +1546,19 @@ struct TuckerPlan {
 
 // Orthogonal iteration in the space of B's rows (Y <- orth(Y B B^T), k x m)
 // instead of on X (k x n) when forming B B^T once costs less than the
-// products it saves (2 m^2 n against 2 its k m n).  The workspace holds B B^T
-// for m up to 4096 where that pays at the default of 20 steps; a call with
-// fewer steps checks its own count as well.
+// products it saves: 2 m^2 n flops in one square product against
+// 2 its k m n in skinny ones, which run at about half the rate
+// (m^2 <= 2 its k n).  The workspace holds B B^T for m up to 4096 where that
+// holds at the default of 20 steps; a call checks its own step count too.
 constexpr int kTuckerGramIts = 20;
 constexpr int kTuckerGramMaxM = 4096;
+static bool tucker_gram_pays(long m, long n, long k, long its)
+{
+    return m >= k && m * m <= 2 * its * k * n;
+}
 static bool tucker_gram_form(int m, int n, int k)
 {
-    return m >= k && m <= kTuckerGramMaxM && (long)m * m <= (long)kTuckerGramIts * k * n;
+    return m <= kTuckerGramMaxM && tucker_gram_pays(m, n, k, kTuckerGramIts);
 }
 
 static TuckerPlan plan_tucker(void *ws, const int *n, int R, const int *r)
@@ -1645,7 +1650,7 @@ static tc_status dominant_rows(const TuckerPlan &T, const double *B, int m, int 
     };
     TRYK("random_rows", launch_random_rows(T.X, warm ? r : 0, k, n, salt, st));
     TRYK("orth_rows", orth(T.X, n, 1, salt + 1));
-    if (tucker_gram_form(m, n, k) && (long)m * m <= (long)its * k * n) {
+    if (tucker_gram_form(m, n, k) && tucker_gram_pays(m, n, k, its)) {
         // Y_0 = orth(X B^T), Y_t = orth(Y_{t-1} B B^T), X = orth2(Y_{its-1} B): the
         // subspaces of the loop below (its applications of B^T B) with one
         // product of k x m by m x m per step
