@@ -309,28 +309,34 @@ __global__ __launch_bounds__(kFitUThreads) void fit_u_kernel(const double *__res
         U[(long)s * n + a] = 0.0;
 }
 
-// The same solve with the solved entries of the thread's own column kept in
-// LDS (ush[r][lane]), for R <= kFitMaxR.  The rows of T^T that a block of
-// eight unknowns needs (Tsh[q][r] = T[r][s], s = top - q) are staged in LDS as
-// well, and the next block's rows of T and of L are loaded into registers
-// while the current block is solved, so that no step waits on global memory.
-// The inner products run over four interleaved partial sums.  (fit_u_kernel
-// above re-reads every solved entry from global memory in its inner loop.)
-constexpr int kFitMaxR = 256;  // ush 128 KB + Tsh 16 KB of LDS
+// The same solve, blocked by eight unknowns, for R <= kFitMaxR: the solved
+// entries of the workgroup's 64 columns stay in LDS (ush[r][lane]), and so do
+// the rows of T that a block needs (Tsh[r][q] = T[r][top - q], eight
+// contiguous values per r).  For a block s = top - 7 .. top, each of four
+// waves sums T[r][s] u_r over its share of the rows solved before the block
+// (r > top), every u_r read once for eight products; after one barrier wave
+// 0 adds the four partial sums in fixed order and solves the 8 x 8 triangle
+// in registers.  The next block's rows of T and of L are loaded into
+// registers while the current block is solved.  (fit_u_kernel above
+// re-reads every solved entry from global memory in its inner loop.)
+constexpr int kFitMaxR = 240;
 constexpr int kFitBlk = 8;
-constexpr int kFitTQ = kFitBlk * kFitMaxR / kFitUThreads;  // staged T entries per lane
+constexpr int kFitW = 4;                 // waves
+constexpr int kFitT = 64 * kFitW;        // threads
+constexpr int kFitTQ = (kFitMaxR * kFitBlk + kFitT - 1) / kFitT;  // staged T entries per thread
 
-__global__ __launch_bounds__(kFitUThreads) void fit_u_lds_kernel(const double *__restrict__ L,
-                                                                 int n, int R, int R_max,
-                                                                 const double *__restrict__ Tg,
-                                                                 double *__restrict__ U)
+__global__ __launch_bounds__(kFitT) void fit_u_blk_kernel(const double *__restrict__ L, int n,
+                                                          int R, int R_max,
+                                                          const double *__restrict__ Tg,
+                                                          double *__restrict__ U)
 {
-    __shared__ double ush[kFitMaxR][kFitUThreads];
-    __shared__ double Tsh[kFitBlk][kFitMaxR];
-    const int lane = threadIdx.x;
-    const int a = blockIdx.x * kFitUThreads + lane;
+    __shared__ double ush[kFitMaxR][64];
+    __shared__ __align__(16) double Tsh[kFitMaxR][kFitBlk];
+    __shared__ double red[kFitW][kFitBlk][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int a = blockIdx.x * 64 + lane;
     const int ac = min(a, n - 1);  // loads stay in bounds; results of a >= n are not stored
-    // rows top, top - 1, ..., top - 7 of L and of T^T (zero below row 0)
+    // rows top, top - 1, ..., top - 7 of L (zero below row 0)
     auto load_l = [&](int top, double(&dst)[kFitBlk]) {
 #pragma unroll
         for (int q = 0; q < kFitBlk; ++q) {
@@ -338,24 +344,26 @@ __global__ __launch_bounds__(kFitUThreads) void fit_u_lds_kernel(const double *_
             dst[q] = sr >= 0 ? L[(long)sr * n + ac] : 0.0;
         }
     };
+    // T[r][top - q] for r < R (Tg[s][r] = T[r][s]), entry e = r * 8 + q
     auto load_t = [&](int top, double(&dst)[kFitTQ]) {
 #pragma unroll
         for (int e = 0; e < kFitTQ; ++e) {
-            const int idx = lane + kFitUThreads * e;
-            const int q = idx / kFitMaxR, r = idx % kFitMaxR;
+            const int idx = tid + kFitT * e;
+            const int r = idx / kFitBlk, q = idx % kFitBlk;
             const int sr = top - q;
-            dst[e] = sr >= 0 && r < R ? Tg[(long)sr * R + r] : 0.0;
+            dst[e] = idx < kFitMaxR * kFitBlk && r < R && sr >= 0 ? Tg[(long)sr * R + r] : 0.0;
         }
     };
     double lcur[kFitBlk], lnxt[kFitBlk], tnxt[kFitTQ];
     load_l(R - 1, lnxt);
     load_t(R - 1, tnxt);
     for (int top = R - 1; top >= 0; top -= kFitBlk) {
-        __syncthreads();  // the previous block's reads of Tsh are done
+        __syncthreads();  // the previous block's solved entries are stored, its T no longer read
 #pragma unroll
         for (int e = 0; e < kFitTQ; ++e) {
-            const int idx = lane + kFitUThreads * e;
-            Tsh[idx / kFitMaxR][idx % kFitMaxR] = tnxt[e];
+            const int idx = tid + kFitT * e;
+            if (idx < kFitMaxR * kFitBlk)
+                Tsh[idx / kFitBlk][idx % kFitBlk] = tnxt[e];
         }
 #pragma unroll
         for (int q = 0; q < kFitBlk; ++q)
@@ -365,29 +373,46 @@ __global__ __launch_bounds__(kFitUThreads) void fit_u_lds_kernel(const double *_
             load_l(top - kFitBlk, lnxt);
             load_t(top - kFitBlk, tnxt);
         }
+        // this wave's share of the rows solved before the block
+        double acc[kFitBlk];
 #pragma unroll
-        for (int q = 0; q < kFitBlk; ++q) {
-            const int sr = top - q;
-            if (sr >= 0) {
-                const double *ts = Tsh[q];  // T[r][sr] = ts[r]
-                double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-                int r = sr + 1;
-                for (; r + 3 < R; r += 4) {
-                    acc0 = fma(ts[r], ush[r][lane], acc0);
-                    acc1 = fma(ts[r + 1], ush[r + 1][lane], acc1);
-                    acc2 = fma(ts[r + 2], ush[r + 2][lane], acc2);
-                    acc3 = fma(ts[r + 3], ush[r + 3][lane], acc3);
+        for (int q = 0; q < kFitBlk; ++q)
+            acc[q] = 0.0;
+        for (int r = top + 1 + w; r < R; r += kFitW) {
+            const double ur = ush[r][lane];
+            const double2 *tp = reinterpret_cast<const double2 *>(Tsh[r]);
+#pragma unroll
+            for (int h = 0; h < kFitBlk / 2; ++h) {
+                const double2 t = tp[h];
+                acc[2 * h] = fma(t.x, ur, acc[2 * h]);
+                acc[2 * h + 1] = fma(t.y, ur, acc[2 * h + 1]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kFitBlk; ++q)
+            red[w][q][lane] = acc[q];
+        __syncthreads();
+        if (w == 0) {
+            double us[kFitBlk];
+#pragma unroll
+            for (int q = 0; q < kFitBlk; ++q) {
+                const int sr = top - q;
+                us[q] = 0.0;
+                if (sr >= 0) {
+                    double v = lcur[q] - (((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) +
+                                          red[3][q][lane]);
+#pragma unroll
+                    for (int q2 = 0; q2 < q; ++q2)
+                        v = fma(-Tsh[top - q2][q], us[q2], v);  // T[top - q2][sr] u
+                    us[q] = v / Tsh[sr][q];                    // T[sr][sr]
+                    ush[sr][lane] = us[q];
+                    if (a < n)
+                        U[(long)sr * n + a] = us[q];
                 }
-                for (; r < R; ++r)
-                    acc0 = fma(ts[r], ush[r][lane], acc0);
-                const double v = (lcur[q] - ((acc0 + acc1) + (acc2 + acc3))) / ts[sr];
-                ush[sr][lane] = v;
-                if (a < n)
-                    U[(long)sr * n + a] = v;
             }
         }
     }
-    if (a < n)
+    if (w == 0 && a < n)
         for (int sr = R; sr < R_max; ++sr)
             U[(long)sr * n + a] = 0.0;
 }
@@ -628,8 +653,8 @@ hipError_t launch_fit_finish(const double *F, const double *L, int n, int N_pair
                            n, R, piv, Tg);
     }
     if (R <= kFitMaxR)
-        hipLaunchKernelGGL(fit_u_lds_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
-                           dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
+        hipLaunchKernelGGL(fit_u_blk_kernel, dim3((n + 63) / 64), dim3(kFitT), 0, st, L, n, R,
+                           R_max, Tg, U);
     else
         hipLaunchKernelGGL(fit_u_kernel, dim3((n + kFitUThreads - 1) / kFitUThreads),
                            dim3(kFitUThreads), 0, st, L, n, R, R_max, Tg, U);
