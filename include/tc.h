@@ -66,6 +66,13 @@
  *                          synchronisation of its stream; the first failing
  *                          kernel is named on stderr and the call returns
  *                          TC_ERR_HIP.
+ *     and one that selects a code path:
+ *       TC_CHOL_COLUMNS=1  tc_density_fit and tc_tei_cholesky form each
+ *                          pivot's column from the factors at every step, the
+ *                          path they take by themselves only beyond the sizes
+ *                          where they form the matrix (n > 8192 cells,
+ *                          N_pair > 4096 products); same workspace, same
+ *                          results up to rounding.
  */
 #ifndef TC_H
 #define TC_H

@@ -1,4 +1,4 @@
-// Diagnostics behind two environment switches (read at every call):
+// Diagnostics behind environment switches (read at every call):
 //   TC_CHECK_FINITE=1  the binary64 inputs of a call are scanned for NaN and
 //                      Inf before any work is enqueued; the call then
 //                      synchronises its stream once to read the result.
@@ -6,6 +6,10 @@
 //                      of its stream, and the first failing kernel is named
 //                      on stderr.
 // Both synchronise, so neither may be on while a call is captured in a graph.
+//   TC_CHOL_COLUMNS=1  the pivoted Cholesky drivers form each pivot's column
+//                      from the factors, the path they take on their own only
+//                      beyond the sizes where the matrix is formed (a check
+//                      of that path at small sizes).
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -61,6 +65,7 @@ bool env_on(const char *name)
 
 bool check_finite_on() { return env_on("TC_CHECK_FINITE"); }
 bool debug_sync_on() { return env_on("TC_DEBUG_SYNC"); }
+bool chol_columns_on() { return env_on("TC_CHOL_COLUMNS"); }
 
 bool debug_sync_check(const char *kernel, hipStream_t st)
 {

@@ -1449,7 +1449,7 @@ tc_status tc_density_fit(int n, int N_pair, const double *F_dev, double tol, int
     const CholScratch s =
         carve_chol(c, n, R_max, true, (size_t)fit_column_parts() * n, (size_t)R_max * R_max);
     double *A = nullptr;
-    if (n <= kFitFormedMaxN) {
+    if (n <= kFitFormedMaxN && !chol_columns_on()) {
         double *Ft = c.take<double>((size_t)n * N_pair);
         A = c.take<double>((size_t)n * n);
         TRYK("fit_gram", launch_fit_gram(F_dev, n, N_pair, Ft, A, st));
@@ -1500,7 +1500,7 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
     const CholScratch s = carve_chol(c, N_pair, R_max, false, 0, (size_t)3 * R_N * N_pair * R);
     TRYK("tei_diag", launch_tei_diag(c_dev, V_dev, M_dev, R, R_N, N_pair, s.Yd, s.d, st));
     double *B = nullptr;
-    if (N_pair <= kTeiFormedMaxN) {
+    if (N_pair <= kTeiFormedMaxN && !chol_columns_on()) {
         // B formed once (GEMMs of V with Y on matrix cores); its diagonal
         // replaces d, so that the steps and the pivot choices read one matrix
         B = c.take<double>((size_t)N_pair * N_pair);

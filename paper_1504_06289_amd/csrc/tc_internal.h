@@ -351,6 +351,7 @@ tc_status tei_gram_call(const tc_instance *inst, int count, tc_precision prec, v
 namespace tc {
 bool check_finite_on();   // TC_CHECK_FINITE set (and not "0")
 bool debug_sync_on();     // TC_DEBUG_SYNC set (and not "0")
+bool chol_columns_on();   // TC_CHOL_COLUMNS set (and not "0")
 // synchronise st after launching `kernel`; false (and a line on stderr) on error
 bool debug_sync_check(const char *kernel, hipStream_t st);
 struct FiniteSpan {

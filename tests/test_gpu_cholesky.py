@@ -64,8 +64,13 @@ def check_fit(tc, orc, F, tol, label):
 
 @pytest.mark.parametrize("n,N_pair,tol", [(96, 60, 1e-3), (200, 150, 1e-6), (333, 90, 1e-7),
                                           (64, 10, 1e-6)])
-def test_density_fit(tc, orc, n, N_pair, tol):
-    say(f"density fit n={n} N_pair={N_pair} tol={tol}")
+@pytest.mark.parametrize("columns", [False, True])
+def test_density_fit(tc, orc, n, N_pair, tol, columns, monkeypatch):
+    """columns: TC_CHOL_COLUMNS=1, each pivot's column formed from F at every
+    step (the path beyond 8192 cells) instead of from the formed F^T F."""
+    if columns:
+        monkeypatch.setenv("TC_CHOL_COLUMNS", "1")
+    say(f"density fit n={n} N_pair={N_pair} tol={tol} columns={columns}")
     U0, _ = wl.gaussian_products(n, 8.0, N_pair, seed=n + N_pair)
     for l in range(3):
         check_fit(tc, orc, U0[l], tol, f"mode {l}")
@@ -82,12 +87,17 @@ def test_density_fit_rank_above_256(tc, orc):
     assert R > 256
 
 
-def test_tei_cholesky_pipeline(tc, orc):
+@pytest.mark.parametrize("columns", [False, True])
+def test_tei_cholesky_pipeline(tc, orc, columns, monkeypatch):
     """Fit each mode, M_k = U T_k U^T from the TEI assembly's saved Grams of
     the fitted rows, then the pivoted Cholesky of B: against the oracle's
     own pipeline from the same inputs, and B ~ L L^T against the J of the
-    TEI assembly of the products."""
-    say("TEI Cholesky pipeline")
+    TEI assembly of the products.  columns: TC_CHOL_COLUMNS=1, the columns
+    of A and B formed from the factors at every step (the path beyond 8192
+    cells and 4096 products) instead of from the formed matrices."""
+    if columns:
+        monkeypatch.setenv("TC_CHOL_COLUMNS", "1")
+    say(f"TEI Cholesky pipeline columns={columns}")
     w = wl.small_products((48, 40, 56), 60, R_N=8, b=7.0, seed=9)
     c, ps = oracle_setup(orc, w)
     # oracle pipeline

@@ -56,7 +56,8 @@ def compare(tc, orc, c, A3, ranks, m_max, its=20, eps=0.0):
                                               ((300, 200, 100), 150, (12, 10, 9), 1),
                                               ((200, 150, 120), 90, (10, 10, 10), 0),
                                               ((20, 12, 30), 40, (6, 5, 7), 2),
-                                              ((512, 512, 512), 400, (24, 20, 22), 1)])
+                                              ((512, 512, 512), 400, (24, 20, 22), 1),
+                                              ((48, 40, 36), 400, (8, 8, 8), 1)])
 def test_c2t_density(tc, orc, n, R, ranks, m_max):
     """A density in canonical format (Gaussian-product factors, weights in
     [0.1, 1]): the rank reduction the transform is there for."""
