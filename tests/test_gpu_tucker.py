@@ -79,6 +79,20 @@ def test_c2t_exact_low_multilinear_rank(tc, orc):
     assert np.max(np.abs(orc.tucker_full(Zg, bg) - T)) <= 1e-11 * np.max(np.abs(T))
 
 
+def test_c2t_subspace_of_64_rows(tc, orc):
+    """Ranks of 32 make the iterated subspace k = 64 rows in every mode: the
+    largest orthonormalisation block (four Cholesky panels, the 64-row
+    substitution) on full-rank side matrices with a decaying spectrum; phase
+    (A) takes the Gram form (m = 200), the sweeps iterate on X (m = 1024)."""
+    rng = np.random.default_rng(8)
+    n3, R, r3 = (80, 76, 72), 200, (32, 32, 32)
+    A3 = [rng.standard_normal((R, n3[l])) * np.exp(-0.05 * np.arange(n3[l]))[None, :]
+          for l in range(3)]
+    c = rng.uniform(0.5, 2.0, R)
+    say("c2t k = 64")
+    compare(tc, orc, c, A3, r3, 1)
+
+
 def test_c2t_few_terms_and_determinism(tc, orc):
     """Fewer terms than the iterated subspace (R < k: the subspace is filled
     with pseudo-random rows) and bitwise repeatable results."""
