@@ -498,15 +498,6 @@ tc_status mode_grams(tc_precision prec, tc_algorithm algo, int n, int R_f, int R
     return TC_OK;
 }
 
-int max_n(const tc_instance &I)
-{
-    int m = I.n[0];
-    for (int l = 1; l < 3; ++l)
-        if (I.n[l] > m)
-            m = I.n[l];
-    return m;
-}
-
 // Workspace plan of one instance.  Layout: [G?][D?] and then either one
 // [W][per-mode scratch] region sized for the largest mode and reused by the
 // three modes in turn, or (split) one such region per mode, so that the modes
