@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx *__restrict__ Uspec, const cplx *__restrict__ Cspec, int n, int R_f, int R_N,
     const cplx *__restrict__ twN, double *__restrict__ W, int8_t *__restrict__ WS,
     int *__restrict__ EW, int R_f_pad, int n_pad, long wplane, const double *__restrict__ U,
-    const double *__restrict__ p, const int *__restrict__ band)
+    const double *__restrict__ p, const int *__restrict__ band, int narrow_here)
 {
     constexpr int TT = kConvThreads;
     constexpr int PAIRS = (M / 2 + 1 + TT - 1) / TT;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         k = kn;
     }
 
-    if (band && !W) {
+    if (band && !W && narrow_here) {
         // narrow terms: u_j in LDS with kBandPad zeros on both sides (buf is
         // free: the last transform's reads ended before the barrier in its
         // emit; 2M >= 9/8 (n + 2 kBandPad) is checked at launch).  Entry x of
@@ -521,6 +521,103 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
                 zs[i] = t0 + i < n ? acc[i] : 0.0;
             emit(kt, zs);
         }
+    }
+}
+
+// The narrow terms of fft_conv_kernel in a launch of their own: for row j
+// (blockIdx.x < R_f) and every narrow term k (band[k] >= 0) in [0, R_N),
+// W_k[j][t] = sum_{|m| <= B} p_k[m] u_j[t - m] in binary64 and its int8
+// slices, exactly as fft_conv_kernel's direct loop and split output compute
+// them.  With only the padded row of u_j in LDS (37 KB at n = 4096) and no
+// transform registers, several workgroups share a CU, which hides the
+// latency of the direct loops and of the split output that the transform
+// kernel's one workgroup per CU cannot.  Rows j >= R_f are zeroed by the
+// transform kernel.
+__global__ __launch_bounds__(kConvThreads) void narrow_conv_kernel(
+    const double *__restrict__ U, const double *__restrict__ p, const int *__restrict__ band,
+    int n, int R_N, int8_t *__restrict__ WS, int *__restrict__ EW, int R_f_pad, int n_pad,
+    long wplane)
+{
+    constexpr int TT = kConvThreads;
+    constexpr int NU = (4096 + 2 * kBandPad) * 9 / 8 + 1;  // padded row, entry x at x + x/8
+    __shared__ double ush[NU];
+    __shared__ double red[2][TT / 64];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double *urow = U + (long)j * n;
+    for (int t = tid; t < n + 2 * kBandPad; t += TT) {
+        const int x = t - kBandPad;
+        ush[t + (t >> 3)] = (x >= 0 && x < n) ? urow[x] : 0.0;
+    }
+    __syncthreads();
+    int nemit = 0;
+    auto emit = [&](int k, const double (&zs)[8]) {
+        const bool own = 8 * tid < n_pad;
+        double amax = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            amax = fmax(amax, fabs(zs[q]));
+        for (int o = 32; o > 0; o >>= 1)
+            amax = fmax(amax, __shfl_xor(amax, o));
+        double *rd = red[nemit & 1];
+        ++nemit;
+        if ((tid & 63) == 0)
+            rd[tid >> 6] = amax;
+        __syncthreads();
+        amax = rd[0];
+#pragma unroll
+        for (int wv = 1; wv < TT / 64; ++wv)
+            amax = fmax(amax, rd[wv]);
+        const int E = row_exp(amax);
+        if (tid == 0)
+            EW[(long)k * R_f_pad + j] = E;
+        if (own) {
+            unsigned long long packed[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int8_t d[4];
+                split4_i8(zs[q], E, d);
+#pragma unroll
+                for (int sl = 0; sl < 4; ++sl)
+                    packed[sl] |= (unsigned long long)(unsigned char)d[sl] << (8 * q);
+            }
+            int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad + 8 * tid;
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl)
+                *reinterpret_cast<unsigned long long *>(row + sl * wplane) = packed[sl];
+        }
+    };
+    const int t0 = 8 * tid;
+    const double *uw = ush + 9 * tid;  // entry 8 tid + c of the padded row at uw[c + c/8]
+    for (int kt = 0; kt < R_N; ++kt) {
+        const int b = band[kt];
+        if (b < 0)
+            continue;
+        const double *pk = p + (long)kt * (2L * n - 1) + (n - 1);  // pk[lag]
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (t0 < n) {
+            for (int m0 = -b; m0 <= b; m0 += 8) {
+                double pm[8], win[15];
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    pm[r] = m0 + r <= b ? pk[m0 + r] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 15; ++q) {
+                    const int c = kBandPad - 7 + q - m0;
+                    win[q] = uw[c + (c >> 3)];
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        acc[i] = fma(pm[r], win[i - r + 7], acc[i]);
+            }
+        }
+        double zs[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            zs[i] = t0 + i < n ? acc[i] : 0.0;
+        emit(kt, zs);
     }
 }
 
@@ -673,12 +770,14 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
         band = nullptr;  // the direct path is for int8 output with room for the padded row
     if (!W && (n_pad > 8 * kConvThreads || n_pad % 8 != 0))
         return hipErrorInvalidValue;  // one 8-byte slice chunk per thread
+    // the narrow terms in a launch of their own (its padded row holds n <= 4096)
+    const int narrow_apart = band && n <= 4096 && R_f >= 256;
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
         hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks, ysplit), dim3(kConvThreads), 0,    \
                            stream,                                                              \
                            Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane,  \
-                           U, p, band);                                                         \
+                           U, p, band, !narrow_apart);                                          \
         break;
     switch (M) {
         TC_FFT_CONV_CASE(1)
@@ -698,6 +797,9 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
         return hipErrorInvalidValue;
     }
 #undef TC_FFT_CONV_CASE
+    if (narrow_apart)
+        hipLaunchKernelGGL(narrow_conv_kernel, dim3(R_f), dim3(kConvThreads), 0, stream, U, p,
+                           band, n, R_N, WS, EW, R_f_pad, n_pad, wplane);
     return hipGetLastError();
 }
 
