@@ -471,7 +471,10 @@ tc_status tc_tei_cholesky(int N_pair, int R, int R_N, const double *c_dev,
  *         the call returns; the tables travel as kernel arguments).
  *   The 1D matrices U^l diag(p^l_q shifted) U^l^T of every (nucleus, term)
  *   pair on binary64 matrix cores, then the product over the modes and the
- *   sum over the pairs in a fixed order (bitwise reproducible).
+ *   sum over the pairs in a fixed order (bitwise reproducible). Groups of
+ *   four pairs whose kernel vectors are all narrow (the lags beyond a band
+ *   B <= 16 carry below 2^-60 of the vector's l1 norm) sum only over the
+ *   cells within B of their nuclei.
  *   ws    tc_nuclear_workspace_bytes(prob) bytes of device memory
  *         (3 M R_N R_f^2 doubles for the 1D matrices, plus tables); returns
  *         (size_t)-1 for an invalid descriptor.

@@ -138,6 +138,7 @@ constexpr int kDiagTerms = 4;
 __global__ __launch_bounds__(256) void diag_gram_f64_kernel(const double *__restrict__ U,
                                                             const double *__restrict__ p,
                                                             const int *__restrict__ shift,
+                                                            const int *__restrict__ cls,
                                                             double *__restrict__ G, int n,
                                                             int R_f, int ntiles, int T, int R_N,
                                                             int mirror)
@@ -211,14 +212,36 @@ __global__ __launch_bounds__(256) void diag_gram_f64_kernel(const double *__rest
             for (int y = 0; y < 2; ++y)
                 acc[u][x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    const int nsteps = (n + BK - 1) / BK;
-    load_stage(0);
+    // K steps: every cell, or, when every term of the group is narrow (class
+    // B >= 0: the lags beyond B carry less than 2^-60 of the kernel vector's
+    // l1 norm), only the cells within B of the group's nuclei
+    int sbeg = 0, send = (n + BK - 1) / BK;
+    if (cls) {
+        int lo = n, hi = -1;
+        bool narrow = true;
+        for (int u = 0; u < nt && narrow; ++u) {
+            const int tt = t0 + u;
+            const int alpha = tt / R_N, q = tt - alpha * R_N;
+            const int b = cls[q];
+            narrow = b >= 0;
+            lo = min(lo, shift[alpha] - b);
+            hi = max(hi, shift[alpha] + b);
+        }
+        if (narrow) {
+            lo = max(lo, 0);
+            hi = min(hi, n - 1);
+            sbeg = lo / BK;
+            send = hi >= lo ? hi / BK + 1 : sbeg;
+        }
+    }
+    const int nsteps = send - sbeg;
+    load_stage(sbeg * BK);
     store_stage(0);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int buf = s & 1;
         if (s + 1 < nsteps)
-            load_stage((s + 1) * BK);
+            load_stage((sbeg + s + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double afr[2], bfr[2];
@@ -279,14 +302,15 @@ hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n, i
     return hipGetLastError();
 }
 
-hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift, double *G,
-                                int n, int R_f, int R_N, int M, bool mirror, hipStream_t stream)
+hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift,
+                                const int *cls, double *G, int n, int R_f, int R_N, int M,
+                                bool mirror, hipStream_t stream)
 {
     const int nt = (R_f + BT - 1) / BT;
     const int T = M * R_N;
     dim3 grid(nt * (nt + 1) / 2, (T + kDiagTerms - 1) / kDiagTerms);
-    hipLaunchKernelGGL(diag_gram_f64_kernel, grid, dim3(256), 0, stream, U, p, shift, G, n, R_f,
-                       nt, T, R_N, (int)mirror);
+    hipLaunchKernelGGL(diag_gram_f64_kernel, grid, dim3(256), 0, stream, U, p, shift, cls, G, n,
+                       R_f, nt, T, R_N, (int)mirror);
     return hipGetLastError();
 }
 

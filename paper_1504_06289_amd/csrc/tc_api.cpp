@@ -1785,9 +1785,9 @@ static bool nuclear_ok(const tc_nuclear_problem &P)
     return true;
 }
 
-// Workspace: [shift: 3 x M ints][cw: M R_N][G: 3 x M R_N x R_f x R_f]
+// Workspace: [shift: 3 x M ints][cls: 3 x R_N ints][cw: M R_N][G: 3 x M R_N x R_f x R_f]
 struct NuclearPlan {
-    int *shift;
+    int *shift, *cls;
     double *cw, *G;
     size_t bytes;
 };
@@ -1798,6 +1798,7 @@ static NuclearPlan plan_nuclear(void *ws, const tc_nuclear_problem &P)
     Carver c(ws);
     const size_t T = (size_t)P.M * P.R_N;
     N.shift = c.take<int>(3 * (size_t)P.M);
+    N.cls = c.take<int>(3 * (size_t)P.R_N);  // term classes of each mode's kernel vectors
     N.cw = c.take<double>(T);
     N.G = c.take<double>(3 * T * P.R_f * P.R_f);
     N.bytes = c.used;
@@ -1840,10 +1841,13 @@ tc_status tc_nuclear(const tc_nuclear_problem *prob, void *ws, size_t ws_bytes, 
              launch_nuclear_table(ch, P.c, P.R_N, P.M, inv_vol, N.shift, N.cw, st));
     }
     const size_t plane = (size_t)P.M * P.R_N * P.R_f * P.R_f;
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < 3; ++l) {
+        // narrow terms' Grams sum only over the cells near their nuclei
+        TRYK("term_class", launch_term_class(P.p[l], P.n[l], P.R_N, N.cls + l * P.R_N, st));
         TRYK("diag_gram_f64", launch_diag_gram_f64(P.U[l], P.p[l], N.shift + l * P.M,
-                                                   N.G + l * plane, P.n[l], P.R_f, P.R_N, P.M,
-                                                   false, st));
+                                                   N.cls + l * P.R_N, N.G + l * plane, P.n[l],
+                                                   P.R_f, P.R_N, P.M, false, st));
+    }
     TRYK("hadamard_sum", launch_hadamard_sum(N.cw, N.G, N.G + plane, N.G + 2 * plane, P.V, P.R_f,
                                              P.M * P.R_N, st));
     return TC_OK;

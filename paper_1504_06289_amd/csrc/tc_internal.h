@@ -30,8 +30,11 @@ hipError_t launch_gram_f64(const double *U, const double *W, double *G, int n,
 // Diagonal form: term k = alpha R_N + q (k < M R_N) with p_q shifted to the
 // cell shift[alpha] (0 <= shift < n) in place of W_k:
 // G[k][i][j] = sum_a U[i][a] U[j][a] p[q][a - shift[alpha] + n - 1].
-hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift, double *G,
-                                int n, int R_f, int R_N, int M, bool mirror, hipStream_t stream);
+// cls [R_N] (the term classes of launch_term_class for p, or null): groups of
+// narrow terms sum only over the cells within their band of their nuclei.
+hipError_t launch_diag_gram_f64(const double *U, const double *p, const int *shift,
+                                const int *cls, double *G, int n, int R_f, int R_N, int M,
+                                bool mirror, hipStream_t stream);
 
 // ---- nuclear potential tables (nuclear.hip) -------------------------------
 constexpr int kNuclearChunk = 64;
