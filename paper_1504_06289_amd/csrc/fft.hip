@@ -174,6 +174,37 @@ __device__ inline void load_twiddles_pass(FftTwiddles<M, RMAX> &Tw, const cplx *
     }
 }
 
+// the butterfly of thread j (< M/R) in one Stockham pass: entries j + r M/R of
+// buf, twiddled and transformed into v (outputs base + r Ns of the pass)
+template <int M, int R, int Ns, int SIGN>
+__device__ inline void butterfly_fixed(const cplx *buf, const cplx *wb, cplx (&v)[R])
+{
+    constexpr int nb = M / R;
+    const int j = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        v[r] = buf[pad(j + r * nb)];
+    if constexpr (Ns > 1) {
+        // w^r from the bases w^1, w^2, w^4, w^8 (binary digits of r),
+        // applied as soon as it is formed to keep few values live
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            cplx w = (r & 1) ? wb[0] : make_double2(1.0, 0.0);
+            if constexpr (R >= 4)
+                if (r & 2)
+                    w = (r & 1) ? cmul(w, wb[1]) : wb[1];
+            if constexpr (R >= 8)
+                if (r & 4)
+                    w = (r & 3) ? cmul(w, wb[2]) : wb[2];
+            if constexpr (R >= 16)
+                if (r & 8)
+                    w = (r & 7) ? cmul(w, wb[3]) : wb[3];
+            v[r] = cmul(v[r], w);
+        }
+    }
+    dft_small<R, SIGN>(v);
+}
+
 // one in-place Stockham pass with T threads (M/R <= T butterflies); outputs
 // at indices >= keep are not stored (the caller reads only [0, keep))
 template <int M, int R, int Ns, int T, int SIGN>
@@ -184,30 +215,8 @@ __device__ inline void pass_fixed(cplx *buf, const cplx *wb, int keep)
     const int j = threadIdx.x;
     const bool active = nb >= T || j < nb;
     cplx v[R];
-    if (active) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            v[r] = buf[pad(j + r * nb)];
-        if constexpr (Ns > 1) {
-            // w^r from the bases w^1, w^2, w^4, w^8 (binary digits of r),
-            // applied as soon as it is formed to keep few values live
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cplx w = (r & 1) ? wb[0] : make_double2(1.0, 0.0);
-                if constexpr (R >= 4)
-                    if (r & 2)
-                        w = (r & 1) ? cmul(w, wb[1]) : wb[1];
-                if constexpr (R >= 8)
-                    if (r & 4)
-                        w = (r & 3) ? cmul(w, wb[2]) : wb[2];
-                if constexpr (R >= 16)
-                    if (r & 8)
-                        w = (r & 7) ? cmul(w, wb[3]) : wb[3];
-                v[r] = cmul(v[r], w);
-            }
-        }
-        dft_small<R, SIGN>(v);
-    }
+    if (active)
+        butterfly_fixed<M, R, Ns, SIGN>(buf, wb, v);
     __syncthreads();
     if (active) {
         const int base = (j / Ns) * Ns * R + (j % Ns);
@@ -227,6 +236,29 @@ __device__ inline void fft_fixed(cplx *buf, const FftTwiddles<M, RMAX> &Tw, int 
     if constexpr (P < F::NP) {
         pass_fixed<M, F::radix(P), F::ns(P), T, SIGN>(buf, Tw.w[P], P + 1 == F::NP ? keep : M);
         fft_fixed<M, RMAX, T, SIGN, P + 1>(buf, Tw, keep);
+    }
+}
+
+// The whole transform with the last pass kept in registers: thread j ends
+// with the outputs j + r Ns (r < R, R and Ns the last pass's radix and
+// sub-transform size) in v and buf holds the last pass's inputs.  Needs one
+// last-pass butterfly per thread (M / R == T), so that Ns == T.
+template <int M, int RMAX> struct FftLast {
+    using F = FftShape<M, RMAX>;
+    static constexpr int R = F::radix(F::NP - 1);
+    static constexpr int Ns = F::ns(F::NP - 1);
+};
+template <int M, int RMAX, int T, int SIGN, int P>
+__device__ inline void fft_fixed_regs(cplx *buf, const FftTwiddles<M, RMAX> &Tw,
+                                      cplx (&v)[FftLast<M, RMAX>::R])
+{
+    using F = FftShape<M, RMAX>;
+    static_assert(M / FftLast<M, RMAX>::R == T, "one last-pass butterfly per thread");
+    if constexpr (P + 1 < F::NP) {
+        pass_fixed<M, F::radix(P), F::ns(P), T, SIGN>(buf, Tw.w[P], M);
+        fft_fixed_regs<M, RMAX, T, SIGN, P + 1>(buf, Tw, v);
+    } else {
+        butterfly_fixed<M, F::radix(P), F::ns(P), SIGN>(buf, Tw.w[P], v);
     }
 }
 
@@ -291,7 +323,7 @@ constexpr int kConvThreads = 512;  // 8 waves: two per SIMD with one workgroup p
 constexpr int kConvRadix = 8;      // M/8 <= 512 butterflies per pass
 constexpr int kBandPad = 32;       // zeros around u_j in LDS: >= kBandMax + 15
 
-template <int M>
+template <int M, bool F64>
 __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
     const cplx *__restrict__ Uspec, const cplx *__restrict__ Cspec, int n, int R_f, int R_N,
     const cplx *__restrict__ twN, double *__restrict__ W, int8_t *__restrict__ WS,
@@ -398,6 +430,57 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         }
     };
 
+    // With one last-pass butterfly per thread, thread tid ends the transform
+    // holding the complex outputs m = tid + r TT (r < LR), i.e. the samples
+    // t = 2m, 2m + 1, and splits them from registers: two bytes per slice and
+    // output, consecutive across the lanes of a wave.  Same values, maximum
+    // and digits as emit.  Only r < LR/2 (m < M/2) can hold samples t < n or
+    // slice bytes t < n_pad, since n <= M and n_pad <= M, so the other half of
+    // the last butterfly is never formed.
+    using Last = FftLast<M, kConvRadix>;
+    constexpr int LR = Last::R;
+    constexpr int RU = LR / 2;
+    constexpr bool kLastInRegs = M / LR == TT;
+    auto emit_regs = [&](int k, const cplx (&v)[LR]) {
+        double za[RU], zb[RU];
+        double amax = 0.0;
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+            const int t = 2 * (tid + r * TT);
+            za[r] = t < n ? v[r].x * invM : 0.0;
+            zb[r] = t + 1 < n ? v[r].y * invM : 0.0;
+            amax = fmax(amax, fmax(fabs(za[r]), fabs(zb[r])));
+        }
+        for (int o = 32; o > 0; o >>= 1)
+            amax = fmax(amax, __shfl_xor(amax, o));
+        double *rd = red[nemit & 1];
+        ++nemit;
+        if ((tid & 63) == 0)
+            rd[tid >> 6] = amax;
+        __syncthreads();
+        amax = rd[0];
+#pragma unroll
+        for (int wv = 1; wv < TT / 64; ++wv)
+            amax = fmax(amax, rd[wv]);
+        const int E = row_exp(amax);
+        if (tid == 0)
+            EW[(long)k * R_f_pad + j] = E;
+        int8_t *row = WS + ((long)k * R_f_pad + j) * n_pad;
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+            const int t = 2 * (tid + r * TT);
+            if (t < n_pad) {  // n_pad is even: t + 1 < n_pad too
+                int8_t da[4], db[4];
+                split4_i8(za[r], E, da);
+                split4_i8(zb[r], E, db);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    *reinterpret_cast<unsigned short *>(row + s * wplane + t) =
+                        (unsigned short)((unsigned char)da[s] | ((unsigned)(unsigned char)db[s] << 8));
+            }
+        }
+    };
+
     int k = next_fft(kb);
     if (k < ke)
         load_c(k);
@@ -438,10 +521,19 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         if (kn < ke)
             load_c(kn);  // in flight during the transform
         __syncthreads();
+        if constexpr (kLastInRegs && !F64) {
+            // the last pass's outputs go to the split from registers; buf's
+            // last reads end before the barrier inside emit_regs
+            cplx v[LR];
+            fft_fixed_regs<M, kConvRadix, TT, +1, 0>(buf, Tw, v);
+            emit_regs(k, v);
+            k = kn;
+            continue;
+        }
         // outputs m hold the samples 2m, 2m + 1: only m < ceil(n/2) are used
         fft_fixed<M, kConvRadix, TT, +1, 0>(buf, Tw, (n + 1) / 2);
 
-        if (W) {
+        if constexpr (F64) {
             double *Wrow = W + ((long)k * R_f + j) * n;
             for (int m = tid; m < M; m += TT) {
                 const cplx z = buf[pad(m)];
@@ -473,7 +565,7 @@ __global__ __launch_bounds__(kConvThreads) void fft_conv_kernel(
         k = kn;
     }
 
-    if (band && !W && narrow_here) {
+    if (!F64 && band && narrow_here) {
         // narrow terms: u_j in LDS with kBandPad zeros on both sides (buf is
         // free: the last transform's reads ended before the barrier in its
         // emit; 2M >= 9/8 (n + 2 kBandPad) is checked at launch).  Entry x of
@@ -772,12 +864,19 @@ hipError_t launch_fft_conv(const cplx *Uspec, const cplx *Cspec, int n, int N, i
         return hipErrorInvalidValue;  // one 8-byte slice chunk per thread
     // the narrow terms in a launch of their own (its padded row holds n <= 4096)
     const int narrow_apart = band && n <= 4096 && R_f >= 256;
+    // the int8 output of the last pass's registers covers the bytes t < M
+    if (!W && M >= 128 && n_pad > M)
+        return hipErrorInvalidValue;
 #define TC_FFT_CONV_CASE(MM)                                                                    \
     case MM:                                                                                    \
-        hipLaunchKernelGGL(fft_conv_kernel<MM>, dim3(blocks, ysplit), dim3(kConvThreads), 0,    \
-                           stream,                                                              \
-                           Uspec, Cspec, n, R_f, R_N, twN, W, WS, EW, R_f_pad, n_pad, wplane,  \
-                           U, p, band, !narrow_apart);                                          \
+        if (W)                                                                                  \
+            hipLaunchKernelGGL((fft_conv_kernel<MM, true>), dim3(blocks, ysplit),                 \
+                               dim3(kConvThreads), 0, stream, Uspec, Cspec, n, R_f, R_N, twN,   \
+                               W, WS, EW, R_f_pad, n_pad, wplane, U, p, band, 0);               \
+        else                                                                                    \
+            hipLaunchKernelGGL((fft_conv_kernel<MM, false>), dim3(blocks, ysplit),                \
+                               dim3(kConvThreads), 0, stream, Uspec, Cspec, n, R_f, R_N, twN,   \
+                               W, WS, EW, R_f_pad, n_pad, wplane, U, p, band, !narrow_apart);   \
         break;
     switch (M) {
         TC_FFT_CONV_CASE(1)
