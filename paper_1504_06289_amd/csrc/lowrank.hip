@@ -360,39 +360,24 @@ __global__ __launch_bounds__(256) void spectral_reduce_kernel(const double *__re
     }
 }
 
-// Y[k] = X S_k ([R_f][kPolyRank]) for the smooth terms: one thread per entry
-__global__ __launch_bounds__(256) void lowrank_y_kernel(const double *__restrict__ X,
-                                                        const double *__restrict__ S,
-                                                        const int *__restrict__ cls, int R_f,
-                                                        double *__restrict__ Y)
-{
-    const int k = blockIdx.y;
-    if (cls[k] != -2)
-        return;
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (long)R_f * RQ)
-        return;
-    const long i = e / RQ;
-    const int s = (int)(e % RQ);
-    const double *x = X + i * RQ;
-    const double *Sk = S + (long)k * RQ * RQ;
-    double v = 0.0;
-#pragma unroll
-    for (int r = 0; r < RQ; ++r)
-        v = fma(x[r], Sk[r * RQ + s], v);
-    Y[(long)k * R_f * RQ + e] = v;
-}
-
-// G_k = Y_k X^T for the smooth terms: upper-triangle 64 x 64 tiles, mirrored
+// G_k = X S_k X^T for the smooth terms: upper-triangle 64 x 64 tiles,
+// mirrored.  A workgroup stages the row blocks X_i and X_j (64 x RQ) and S_k
+// in LDS, forms Y_i = X_i S_k (each wave 16 rows) into X_i's place, then
+// contracts Y_i X_j^T with four waves of 32 x 32 (2 x 2 blocks of 16 x 16).
+// Both products run on v_mfma_f64_16x16x4_f64 (lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; result lane l holds D[l/16 + 4r][l%16]).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int LT = 64;
+static_assert(LT == 4 * 16 && RQ % 16 == 0, "four waves of 16 rows form Y_i");
 __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restrict__ X,
-                                                           const double *__restrict__ Y,
+                                                           const double *__restrict__ S,
                                                            const int *__restrict__ cls,
                                                            double *__restrict__ G, int R_f,
                                                            int ntiles, int mirror)
 {
-    __shared__ double Ys[LT][RQ + 1];
-    __shared__ double Xs[LT][RQ + 1];
+    __shared__ double Ys[LT][RQ + 1];  // X_i, then Y_i
+    __shared__ double Xs[LT][RQ + 1];  // X_j
+    __shared__ double Ss[RQ][RQ + 1];
     const int k = blockIdx.y;
     if (cls[k] != -2)
         return;
@@ -405,50 +390,79 @@ __global__ __launch_bounds__(256) void lowrank_gram_kernel(const double *__restr
     const int tj = ti + t;
     const int i0 = ti * LT, j0 = tj * LT;
     const int tid = threadIdx.x;
-    const double *Yk = Y + (long)k * R_f * RQ;
+    const double *Sk = S + (long)k * RQ * RQ;
     for (int e = tid; e < LT * RQ; e += 256) {
         const int row = e / RQ, r = e % RQ;
-        Ys[row][r] = i0 + row < R_f ? Yk[(long)(i0 + row) * RQ + r] : 0.0;
+        Ys[row][r] = i0 + row < R_f ? X[(long)(i0 + row) * RQ + r] : 0.0;
         Xs[row][r] = j0 + row < R_f ? X[(long)(j0 + row) * RQ + r] : 0.0;
     }
+    for (int e = tid; e < RQ * RQ; e += 256)
+        Ss[e / RQ][e % RQ] = Sk[e];
     __syncthreads();
-    // thread -> rows 4 (tid/16) + a, columns (tid%16) + 16 b
-    const int ra = (tid >> 4) * 4, cb = tid & 15;
-    double acc[4][4];
+    const int lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lk = lane >> 4;
+
+    // Y_i rows 16 wave .. 16 wave + 15: Y[i][s] = sum_r X[i][r] S_k[r][s]
+    {
+        f64x4 ay[RQ / 16];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int y = 0; y < RQ / 16; ++y)
+            ay[y] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            acc[a][b] = 0.0;
-#pragma unroll 4
-    for (int r = 0; r < RQ; ++r) {
-        double ya[4], xb[4];
+        for (int kk = 0; kk < RQ; kk += 4) {
+            const double afr = Ys[16 * wave + l16][kk + lk];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-            ya[a] = Ys[ra + a][r];
+            for (int y = 0; y < RQ / 16; ++y)
+                ay[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr, Ss[kk + lk][16 * y + l16],
+                                                             ay[y], 0, 0, 0);
+        }
+        __syncthreads();  // every wave has read its rows of X_i
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            xb[b] = Xs[cb + 16 * b][r];
+        for (int y = 0; y < RQ / 16; ++y)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int r = 0; r < 4; ++r)
+                Ys[16 * wave + lk + 4 * r][16 * y + l16] = ay[y][r];
+        __syncthreads();
+    }
+
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    f64x4 acc[2][2];
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = fma(ya[a], xb[b], acc[a][b]);
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < RQ; kk += 4) {
+        double afr[2], bfr[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+            afr[x] = Ys[wi + 16 * x + l16][kk + lk];
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            bfr[y] = Xs[wj + 16 * y + l16][kk + lk];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[x], bfr[y], acc[x][y], 0, 0, 0);
     }
     double *Gk = G + (long)k * R_f * R_f;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int i = i0 + ra + a;
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = j0 + cb + 16 * b;
-            if (i < R_f && j < R_f && i <= j) {
-                Gk[(long)i * R_f + j] = acc[a][b];
-                if (mirror)
-                    Gk[(long)j * R_f + i] = acc[a][b];
+        for (int y = 0; y < 2; ++y) {
+            const int j = j0 + wj + 16 * y + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + 16 * x + lk + 4 * r;
+                if (i < R_f && j < R_f && i <= j) {
+                    Gk[(long)i * R_f + j] = acc[x][y][r];
+                    if (mirror)
+                        Gk[(long)j * R_f + i] = acc[x][y][r];
+                }
             }
         }
-    }
 }
 
 }  // namespace
@@ -520,17 +534,12 @@ hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int 
     return hipGetLastError();
 }
 
-hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
-                               double *G, int R_f, int R_N, bool mirror, hipStream_t stream)
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
+                               int R_f, int R_N, bool mirror, hipStream_t stream)
 {
-    hipLaunchKernelGGL(lowrank_y_kernel, dim3((unsigned)(((long)R_f * RQ + 255) / 256), R_N),
-                       dim3(256), 0, stream, X, S, cls, R_f, Y);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
     const int nt = (R_f + LT - 1) / LT;
     dim3 grid(nt * (nt + 1) / 2, R_N);
-    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, Y, cls, G, R_f, nt,
+    hipLaunchKernelGGL(lowrank_gram_kernel, grid, dim3(256), 0, stream, X, S, cls, G, R_f, nt,
                        (int)mirror);
     return hipGetLastError();
 }

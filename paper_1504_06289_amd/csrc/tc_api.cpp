@@ -173,7 +173,6 @@ struct ModeScratch {
     double2 *Qspec = nullptr;  // half spectra of Q's rows
     double *Sp = nullptr;      // partial sums of S over frequency ranges
     double *S = nullptr;       // [R_N][kPolyRank][kPolyRank] = Q T_k Q^T
-    double *Y = nullptr;       // [R_N][R_f][kPolyRank] = X S_k
     // FFT route beyond 4096 cells (four-step transforms)
     double2 *Zl = nullptr;     // spectra of the pairs of U rows
     double2 *Cl = nullptr;     // spectra of the kernel embeddings
@@ -228,7 +227,6 @@ ModeScratch carve_mode(Carver &c, tc_precision prec, int n, int R_f, int R_N, bo
                 s.Qspec = c.take<double2>((size_t)kPolyRank * (N / 2 + 1));
                 s.Sp = c.take<double>((size_t)R_N * kSpectralSplit * kPolyRank * kPolyRank);
                 s.S = c.take<double>((size_t)R_N * kPolyRank * kPolyRank);
-                s.Y = c.take<double>((size_t)R_N * R_f * kPolyRank);
             }
         }
     }
@@ -436,7 +434,7 @@ tc_status int8fft_u_main(int n, int R_f, int R_N, const double *p, const double 
         // smooth terms: G_k = X S_k X^T with X = U Q^T
         TRYK("poly_project", launch_poly_project(U, n, R_f, kp.Q, s.Xp, s.X, st));
         TRYK("lowrank_gram",
-             launch_lowrank_gram(s.X, kp.S, kp.cls, s.Y, G, R_f, R_N, mirror, st));
+             launch_lowrank_gram(s.X, kp.S, kp.cls, G, R_f, R_N, mirror, st));
     }
     return TC_OK;
 }

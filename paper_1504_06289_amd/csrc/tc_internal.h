@@ -332,10 +332,9 @@ hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q,
 constexpr int kSpectralSplit = 16;
 hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int N, int R_N,
                                 const int *cls, double *partial, double *S, hipStream_t stream);
-// G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank];
-// Y: scratch [R_N][R_f][kPolyRank])
-hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *Y,
-                               double *G, int R_f, int R_N, bool mirror, hipStream_t stream);
+// G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank])
+hipError_t launch_lowrank_gram(const double *X, const double *S, const int *cls, double *G,
+                               int R_f, int R_N, bool mirror, hipStream_t stream);
 
 }  // namespace tc
 
