@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void poly_project_reduce(const double *__restr
 // m_0 = m_M = 1, else 2.  Workgroup (k, split) sums one range of frequencies in
 // chunks staged in LDS; its four waves take every fourth frequency and each
 // thread a 4 x 4 block of (r, s), and the waves' sums are added in LDS.
-// spectral_reduce adds the splits in a fixed order.
+// spectral_reduce adds the splits in a fixed order (one thread per entry).
 constexpr int SW = 64;  // frequencies per LDS chunk
 __global__ __launch_bounds__(256) void spectral_gram_kernel(const double2 *__restrict__ Qspec,
                                                             const double2 *__restrict__ Cspec,
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void spectral_reduce_kernel(const double *__re
     const int k = blockIdx.x;
     if (cls[k] != -2)
         return;
-    for (int e = threadIdx.x; e < RQ * RQ; e += 256) {
+    for (int e = blockIdx.y * 256 + threadIdx.x; e < RQ * RQ; e += 256 * gridDim.y) {
         double v = 0.0;
         for (int sp = 0; sp < nsplit; ++sp)
             v += partial[((long)k * nsplit + sp) * RQ * RQ + e];
@@ -529,8 +529,8 @@ hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(spectral_reduce_kernel, dim3(R_N), dim3(256), 0, stream, partial, cls,
-                       kSpectralSplit, 1.0 / (double)N, S);
+    hipLaunchKernelGGL(spectral_reduce_kernel, dim3(R_N, RQ * RQ / 256), dim3(256), 0, stream,
+                       partial, cls, kSpectralSplit, 1.0 / (double)N, S);
     return hipGetLastError();
 }
 

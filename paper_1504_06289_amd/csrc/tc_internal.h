@@ -329,7 +329,7 @@ hipError_t launch_poly_project(const double *U, int n, int R_f, const double *Q,
 // S[k] = Q T_k Q^T (kPolyRank x kPolyRank) for the terms of class -2, from the
 // half spectra of Q's rows [kPolyRank][N/2+1] and of the kernel embeddings
 // [R_N][N/2+1]; partial: scratch [R_N][kSpectralSplit][kPolyRank][kPolyRank]
-constexpr int kSpectralSplit = 16;
+constexpr int kSpectralSplit = 32;
 hipError_t launch_spectral_gram(const double2 *Qspec, const double2 *Cspec, int N, int R_N,
                                 const int *cls, double *partial, double *S, hipStream_t stream);
 // G_k = X S_k X^T for the terms of class -2 (S [R_N][kPolyRank][kPolyRank])
